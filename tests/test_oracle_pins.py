@@ -1,0 +1,410 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+None of these tests touches the GPU library.  Each test pins the oracle to
+something other than itself: values printed in the paper (tests/golden/),
+closed forms, invariants, high-precision arithmetic (mpmath, 50 digits),
+special cases with known answers, and LAPACK through numpy.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_28952_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+EPS = np.finfo(np.float64).eps
+
+
+def _read_rows(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# --------------------------------------------------------------------------
+# Orderings: Alg. 3 against the printed list L (eq. parallel_list, §3)
+# --------------------------------------------------------------------------
+
+def printed_L():
+    groups = []
+    for row in _read_rows("parallel_list_P8.txt"):
+        groups.append({tuple(int(x) - 1 for x in tok.split("-")) for tok in row})
+    return groups
+
+
+def test_alg3_matches_printed_list():
+    L = [set(g) for g in O.antidiag_list(8)]
+    P = printed_L()
+    # The paper prints Alg. 3's groups in the order K = 1, 0, 7, 6, ..., 2:
+    # printed group g (1-based) is Alg. 3's group K = (2 - g) mod 8.
+    for g in range(1, 9):
+        assert P[g - 1] == L[(2 - g) % 8], g
+    assert sorted(map(sorted, P)) == sorted(map(sorted, L))
+
+
+def test_alg3_group_sizes_alternate():
+    sizes = [len(g) for g in O.antidiag_list(8)]
+    assert sorted(sizes) == [3, 3, 3, 3, 4, 4, 4, 4]
+    assert all(sizes[k] != sizes[(k + 1) % 8] for k in range(8))
+
+
+def test_printed_labels_match_list():
+    rows = _read_rows("disjoint_labels_P8.txt")
+    P = printed_L()
+    for I, row in enumerate(rows):
+        for off, lab in enumerate(row):
+            J = I + 1 + off
+            assert (I, J) in P[int(lab) - 1]
+
+
+def _transformation_labels(group, P=8):
+    """Label of block (I, J): the transformation acting on block row I (left)
+    and the one acting on block column J (right)."""
+    who = {}
+    for t, (a, b) in enumerate(group, start=1):
+        who[a] = t
+        who[b] = t
+    out = []
+    for I in range(P):
+        row = []
+        for J in range(I, P):
+            l, r = who.get(I), who.get(J)
+            if l is not None and l == r:
+                row.append(str(l))
+            else:
+                row.append(("_" if l is None else str(l)) + ("_" if r is None else str(r)))
+        out.append(row)
+    return out
+
+
+@pytest.mark.parametrize("fname,g", [("group_one_transformations_P8.txt", 1),
+                                     ("group_two_transformations_P8.txt", 2)])
+def test_update_pattern_matches_paper(fname, g):
+    rows = _read_rows(fname)
+    # label order = printed order within the group
+    printed = [[tuple(int(x) - 1 for x in tok.split("-")) for tok in row]
+               for row in _read_rows("parallel_list_P8.txt")]
+    assert _transformation_labels(printed[g - 1]) == rows
+
+
+@pytest.mark.parametrize("N", [2, 4, 6, 8, 16, 64, 5, 7])
+def test_round_robin_covers_each_pair_once(N):
+    R = O.rr_list(N)
+    seen = set()
+    for rnd in R:
+        used = set()
+        for (I, J) in rnd:
+            assert 0 <= I < J < N
+            assert I not in used and J not in used
+            used |= {I, J}
+            assert (I, J) not in seen
+            seen.add((I, J))
+        if N % 2 == 0:
+            assert len(rnd) == N // 2
+    assert len(seen) == N * (N - 1) // 2
+    assert len(R) == (N - 1 if N % 2 == 0 else N)
+
+
+def test_round_robin_n64_shape():
+    R = O.rr_list(64)
+    assert len(R) == 63 and all(len(r) == 32 for r in R)
+
+
+# --------------------------------------------------------------------------
+# Scalar Jacobi eigensolver (Alg. 1 with b = 1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("a,b,d", [(2.0, 1.0, -1.0), (1.0, 0.5, 1.0), (0.0, 3.0, 0.0),
+                                   (1e-3, 1e-9, 2e-3), (-5.0, 2.0, 7.0)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_eig_2x2_closed_form(a, b, d, order):
+    A = np.array([[a, b], [b, d]])
+    r = O.eig(A, order=order)
+    m, h = 0.5 * (a + d), math.hypot(0.5 * (a - d), b)
+    assert r.status == 0
+    np.testing.assert_allclose(r.W, [m - h, m + h], rtol=0, atol=4 * EPS * max(abs(a), abs(b), abs(d)))
+    # one rotation diagonalises a 2x2 exactly; eigenvector check
+    for k in range(2):
+        v = r.Q[:, k]
+        np.testing.assert_allclose(A @ v, r.W[k] * v, atol=8 * EPS * (abs(a) + abs(b) + abs(d)))
+    assert r.rotations <= 1
+
+
+def _smith_3x3(A):
+    """O. K. Smith, 'Eigenvalues of a symmetric 3x3 matrix', CACM 4(4), 1961."""
+    q = np.trace(A) / 3.0
+    p1 = A[0, 1] ** 2 + A[0, 2] ** 2 + A[1, 2] ** 2
+    p2 = (A[0, 0] - q) ** 2 + (A[1, 1] - q) ** 2 + (A[2, 2] - q) ** 2 + 2 * p1
+    p = math.sqrt(p2 / 6.0)
+    B = (A - q * np.eye(3)) / p
+    r = np.linalg.det(B) / 2.0
+    r = min(1.0, max(-1.0, r))
+    phi = math.acos(r) / 3.0
+    l1 = q + 2 * p * math.cos(phi)
+    l3 = q + 2 * p * math.cos(phi + 2 * math.pi / 3)
+    l2 = 3 * q - l1 - l3
+    return np.sort([l1, l2, l3])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_eig_3x3_closed_form(seed):
+    rng = np.random.default_rng(100 + seed)
+    Q = inputs.haar(3, rng)
+    lam = np.array([-1.0, 0.3, 2.0]) * (1 + seed)
+    A = inputs.sym_with_spectrum(lam, Q)
+    r = O.eig(A)
+    np.testing.assert_allclose(r.W, _smith_3x3(A), rtol=0, atol=1e-13 * (1 + seed))
+    np.testing.assert_allclose(r.W, lam, rtol=0, atol=1e-14 * (1 + seed) * 4)
+
+
+def test_eig_mpmath_50_digits():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(7)
+    for n in (4, 7, 12):
+        X = rng.standard_normal((n, n))
+        A = X + X.T
+        ev = mpmath.eigsy(mpmath.matrix(A.tolist()), eigvals_only=True)
+        ref = np.sort(np.array([float(x) for x in ev]))
+        r = O.eig(A, order=1)
+        nrm = np.linalg.norm(A, 2)
+        assert np.max(np.abs(r.W - ref)) <= 8 * n * EPS * nrm
+
+
+@pytest.mark.parametrize("n,kind", [(64, "uniform"), (64, "graded"), (128, "uniform")])
+def test_eig_known_spectrum_and_invariants(n, kind):
+    A, lam = (inputs.eig_uniform(n, 11) if kind == "uniform" else inputs.eig_graded(n, 12))
+    r = O.eig(A, order=1)
+    assert r.status == 0
+    nrm = np.max(np.abs(lam))
+    # Weyl: each eigenvalue moves by at most the backward error ~ n u ||A||_2
+    assert np.max(np.abs(r.W - np.sort(lam))) <= n * EPS * nrm
+    res, orth, dtr, dfro = O.check_eig(A, r.W, r.Q)
+    # the A = Q D Q^T invariants at the 1e-12 bar, measured in long double
+    assert res <= 1e-13 and orth <= 1e-12
+    assert abs(dtr) <= n * EPS * np.sum(np.abs(lam))
+    assert abs(dfro) <= n * EPS
+    # numpy / LAPACK as a second, independent reference
+    assert np.max(np.abs(r.W - np.linalg.eigvalsh(A))) <= 1e-12 * nrm
+
+
+def test_eig_orders_agree():
+    A, _ = inputs.eig_uniform(40, 3)
+    r0 = O.eig(A, order=0)
+    r1 = O.eig(A, order=1)
+    r2 = O.eig(A, order=1, nthreads=4)
+    nrm = np.max(np.abs(r0.W))
+    assert np.max(np.abs(r0.W - r1.W)) <= 1e-13 * nrm
+    assert np.max(np.abs(r1.W - r2.W)) <= 1e-13 * nrm
+    for r in (r0, r1, r2):
+        res, orth, _, _ = O.check_eig(A, r.W, r.Q)
+        assert res <= 1e-13 and orth <= 1e-13
+
+
+def test_per_rotation_identity():
+    """§1: each 2x2 rotation lowers off^2 by exactly 2 a_pq^2 (to rounding)."""
+    A, _ = inputs.eig_uniform(24, 5)
+    for order in (0, 1):
+        r = O.eig(A, order=order, check_rotations=True)
+        assert r.rotations > 0
+        assert r.rot_identity <= 1e-12
+
+
+def test_diagonal_input_is_fixed_point():
+    d = np.array([3.0, -1.0, 2.0, 0.5, -7.0])
+    A = np.diag(d)
+    r = O.eig(A)
+    assert r.rotations == 0 and r.sweeps == 0
+    np.testing.assert_array_equal(r.W, np.sort(d))
+    perm = np.argsort(d, kind="stable")
+    np.testing.assert_array_equal(r.Q, np.eye(5)[:, perm])
+
+
+def test_identity_plus_rank_one():
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal(30)
+    A = np.eye(30) + np.outer(u, u)
+    r = O.eig(A)
+    expect = np.ones(30)
+    expect[-1] = 1 + u @ u
+    np.testing.assert_allclose(r.W, expect, rtol=0, atol=30 * EPS * (1 + u @ u))
+
+
+def test_block_diagonal_decouples():
+    A1, l1 = inputs.eig_uniform(7, 1)
+    A2, l2 = inputs.eig_uniform(5, 2)
+    A = np.zeros((12, 12))
+    A[:7, :7] = A1
+    A[7:, 7:] = A2
+    r = O.eig(A)
+    np.testing.assert_allclose(r.W, np.sort(np.concatenate([O.eig(A1).W, O.eig(A2).W])), atol=1e-14)
+    # no rotation ever mixes the blocks (their coupling entries are exact zeros)
+    for k in range(12):
+        v = r.Q[:, k]
+        assert np.all(v[:7] == 0) or np.all(v[7:] == 0)
+
+
+def test_metamorphic_shift_negate_permute():
+    A, _ = inputs.eig_uniform(32, 4)
+    w = O.eig(A).W
+    nrm = np.max(np.abs(w))
+    np.testing.assert_allclose(O.eig(A + 2.5 * np.eye(32)).W, w + 2.5, atol=1e-13 * (nrm + 2.5))
+    np.testing.assert_allclose(O.eig(-A).W, -w[::-1], atol=1e-13 * nrm)
+    p = np.random.default_rng(1).permutation(32)
+    np.testing.assert_allclose(O.eig(A[np.ix_(p, p)]).W, w, atol=1e-13 * nrm)
+
+
+def test_resume_from_intermediate_q():
+    A, _ = inputs.eig_uniform(48, 8)
+    full = O.eig(A)
+    part = O.eig(A, max_sweeps=2)
+    assert part.status == 1
+    # part.Q holds the (sorted) iterate after 2 sweeps; restart from it
+    res = O.eig(A, Q0=part.Q)
+    assert res.status == 0
+    assert np.max(np.abs(res.W - full.W)) <= 1e-13
+    assert res.sweeps < full.sweeps
+
+
+def test_status_codes():
+    A, _ = inputs.eig_uniform(16, 1)
+    assert O.eig(A, max_sweeps=1).status == 1
+    B = A.copy()
+    B[3, 4] = np.nan
+    assert O.eig(B).status == 2
+    assert O.eig(np.zeros((0, 0))).status == 0
+
+
+# --------------------------------------------------------------------------
+# One-sided Jacobi SVD (Alg. 6 with b = 1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m,n", [(20, 12), (64, 64), (100, 30)])
+def test_svd_constructed_sigma(m, n):
+    G, sigma = inputs.svd_case(m, n, 21)
+    r = O.svd(G)
+    assert r.status == 0
+    s_ref = np.sort(sigma)[::-1]
+    assert np.max(np.abs(r.S - s_ref)) <= 10 * n * EPS
+    np.testing.assert_allclose(r.S, np.linalg.svd(G, compute_uv=False), rtol=0, atol=10 * n * EPS)
+    res, ov, ou = O.check_svd(G, r.S, r.U, r.V)
+    assert res <= 1e-13 and ov <= 1e-12
+    # U's orthogonality degrades like u / sigma_min for the tiny sigmas
+    assert ou <= 1e-13 / s_ref[-1] * 10
+
+
+def test_svd_mpmath():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((9, 6))
+    ref = np.array([float(x) for x in mpmath.svd_r(mpmath.matrix(G.tolist()), compute_uv=False)])
+    r = O.svd(G)
+    np.testing.assert_allclose(r.S, np.sort(ref)[::-1], rtol=0, atol=50 * EPS * ref.max())
+
+
+def test_svd_orthonormal_columns_and_rank_deficient():
+    rng = np.random.default_rng(4)
+    G = inputs.haar(8, rng, 20)
+    r = O.svd(G)
+    np.testing.assert_allclose(r.S, np.ones(8), atol=1e-14)
+    H = rng.standard_normal((15, 6))
+    H[:, 2] = 0.0
+    r = O.svd(H)
+    assert r.S[-1] == 0.0
+    assert np.all(r.U[:, -1] == 0.0)
+
+
+def test_svd_squares_are_gram_eigenvalues():
+    G, _ = inputs.svd_case(40, 10, 5)
+    G = G + np.asfortranarray(np.eye(40, 10))  # well conditioned
+    s = O.svd(G).S
+    w = O.eig(G.T @ G).W
+    np.testing.assert_allclose(np.sort(s ** 2), w, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Block step (Alg. 2 formulas) against the composite product V^T A V
+# --------------------------------------------------------------------------
+
+def _composite(n, b, pairs, Vhat):
+    V = np.eye(n)
+    for (I, J), Vh in zip(pairs, Vhat):
+        idx = np.r_[I * b:(I + 1) * b, J * b:(J + 1) * b]
+        V[np.ix_(idx, idx)] = Vh
+    return V
+
+
+@pytest.mark.parametrize("N,b,rnd", [(4, 3, 0), (6, 2, 2), (5, 2, 1)])
+def test_block_step_equals_composite_rotation(N, b, rnd):
+    n = N * b
+    rng = np.random.default_rng(N * 10 + b)
+    A, _ = inputs.eig_uniform(n, 30 + N)
+    Q = inputs.haar(n, rng)
+    pairs = O.rr_list(N)[rnd]
+    Vhat = [inputs.haar(2 * b, rng) for _ in pairs]
+    Dhat = [np.diag(rng.standard_normal(2 * b)) for _ in pairs]
+    An, Qn = O.block_step(A, Q, b, pairs, Vhat, Dhat)
+    V = _composite(n, b, pairs, Vhat)
+    ref = V.T @ A @ V
+    for (I, J), D in zip(pairs, Dhat):
+        idx = np.r_[I * b:(I + 1) * b, J * b:(J + 1) * b]
+        ref[np.ix_(idx, idx)] = D
+    np.testing.assert_allclose(An, ref, rtol=0, atol=1e-14 * n)
+    np.testing.assert_allclose(Qn, Q @ V, rtol=0, atol=1e-14 * n)
+
+
+def test_block_step_identity_rotations_keep_a():
+    n, b = 12, 3
+    A, _ = inputs.eig_uniform(n, 2)
+    pairs = O.rr_list(4)[1]
+    An, Qn = O.block_step(A, np.eye(n), b, pairs, [np.eye(2 * b)] * len(pairs))
+    np.testing.assert_array_equal(An, A)
+    np.testing.assert_array_equal(Qn, np.eye(n))
+
+
+# --------------------------------------------------------------------------
+# Cayley map
+# --------------------------------------------------------------------------
+
+def test_cayley_identities():
+    rng = np.random.default_rng(0)
+    n = 10
+    X = rng.standard_normal((n, n)) * 0.3
+    S = X - X.T
+    W = O.cayley(S)
+    np.testing.assert_allclose(W.T @ W, np.eye(n), atol=1e-14 * n)
+    np.testing.assert_allclose(O.cayley(-S), W.T, atol=1e-14 * n)
+    np.testing.assert_array_equal(O.cayley(np.zeros((n, n))), np.eye(n))
+    np.testing.assert_allclose(O.cayley_inverse(W), S, atol=1e-13 * n)
+    s = 0.7
+    W2 = O.cayley(np.array([[0.0, s], [-s, 0.0]]))
+    ref = np.array([[1 - s * s, 2 * s], [-2 * s, 1 - s * s]]) / (1 + s * s)
+    np.testing.assert_allclose(W2, ref, atol=4 * EPS)
+
+
+# --------------------------------------------------------------------------
+# Checkers
+# --------------------------------------------------------------------------
+
+def test_checker_detects_errors():
+    A, lam = inputs.eig_uniform(20, 6)
+    r = O.eig(A)
+    good = O.check_eig(A, r.W, r.Q)
+    assert good[0] < 1e-14 and good[1] < 1e-13
+    Qb = r.Q.copy()
+    Qb[:, 3] *= -1.0
+    Qb[:, [4, 5]] = Qb[:, [5, 4]]  # swapped vectors: residual must see it
+    bad = O.check_eig(A, r.W, Qb)
+    assert bad[0] > 1e-3 and bad[1] < 1e-13
+    samp = O.check_eig_sampled(A, r.W, r.Q, [0, 3, 19])
+    assert samp[0] < 1e-14 and samp[1] < 1e-13
+    assert O.check_offnorm(np.diag([1.0, 2.0])) == 0.0
+    assert abs(O.check_offnorm(np.array([[0.0, 3.0], [4.0, 0.0]])) - 5.0) < 1e-15
