@@ -1,0 +1,221 @@
+/*
+ * jacobi.h -- C ABI of libjacobi.so, an MI355X (gfx950) blocked Jacobi
+ * eigensolver and one-sided Jacobi SVD.
+ *
+ * Method: Demmel, Luo, Schneider, Wang, "Minimizing the Arithmetic and
+ * Communication Complexity of Jacobi's Method for Eigenvalues and Singular
+ * Values: Part Two -- Parallel Algorithms" (arXiv 2608.28952).
+ *   - jacobi_eig: block Jacobi (Alg. 1, §2.1) run in the parallel form of
+ *     Alg. 2 (§3): each step diagonalises N/2 disjoint 2b x 2b subproblems
+ *     A([I,J],[I,J]) (one GPU workgroup each, the workgroups playing the
+ *     processors of Alg. 2), then applies the block rotations to block rows,
+ *     block columns and Q.  Convergence is measured by the off-norm Xi(A) of
+ *     eq. (Omega_A), §2.1.
+ *   - jacobi_svd: one-sided block Jacobi (Alg. 6, §6); each subproblem is the
+ *     Gram block G(:,[I,J])^T G(:,[I,J]) of eq. (SVD_subproblem), formed on
+ *     the fly; Sigma = column norms and U = G Sigma^+ at the end.
+ *   - jacobi_eig_batched: many independent small problems in one launch.
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major: element (i, j) at ptr[i + j * ld].
+ *   - Pointers named d* are device pointers (HIP device memory) owned by the
+ *     caller; pointers named h* are host pointers, read or written only during
+ *     the call.  Inputs are never modified.  Outputs must not alias inputs.
+ *   - All device work is enqueued on `stream` (NULL = the default stream).  The
+ *     calls return after the results are complete (they synchronise `stream`),
+ *     because the sweep count and status are reported on the host.
+ *   - Scratch memory: `dWork`/`workBytes` may supply device workspace of at
+ *     least the size returned by the matching *_workspace query; if dWork is
+ *     NULL the library allocates (and frees) the workspace itself.
+ *   - Return value (also stored in info->status when info is non-NULL):
+ *         0    success
+ *        -i    argument i (1-based) is invalid
+ *      -100    dWork too small
+ *         1    not converged within opts->max_sweeps (outputs hold the last
+ *              iterate, sorted)
+ *         2    non-finite value in the input or an iterate
+ *         3    HIP runtime error (text from jacobi_last_error())
+ */
+#ifndef JACOBI_H
+#define JACOBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *jacobi_stream_t; /* the same type as hipStream_t */
+
+enum jacobi_order {
+    JACOBI_ORDER_ROUND_ROBIN = 0, /* N-1 rounds of N/2 disjoint block pairs */
+    JACOBI_ORDER_ANTIDIAG = 1     /* Alg. 3: groups I + J = K (mod N)       */
+};
+
+enum jacobi_prec {
+    JACOBI_PREC_FP64 = 0,       /* every sweep in FP64                            */
+    JACOBI_PREC_MIXED_FP32 = 1, /* FP32 MFMA sweeps, then FP64 recovery sweeps    */
+    JACOBI_PREC_MIXED_BF16 = 2  /* BF16 MFMA, then FP32, then FP64 sweeps         */
+};
+
+enum jacobi_dtype { JACOBI_F32 = 0, JACOBI_F64 = 1 };
+
+typedef struct {
+    double tol;           /* eig: stop when Xi(A) <= tol * ||A||_F (default 1e-14);
+                             svd: stop when every column pair has
+                             |g_i^T g_j| <= tol * |g_i| |g_j| (default sqrt(m) * eps) */
+    int max_sweeps;       /* default 60 */
+    int block;            /* b; 0 = default (64 for n > 512, smaller below) */
+    int ordering;         /* enum jacobi_order */
+    int precision;        /* enum jacobi_prec */
+    int inner_max_sweeps; /* cap on inner scalar sweeps per subproblem; 0 = until
+                             the subproblem's off-norm <= eps ||A_hat||_F (cap 30).
+                             Default 1: the paper allows approximate
+                             diagonalisation of the subproblem (§3). */
+    int refine;           /* 1 = orthogonality refinement of Q/V (Newton-Schulz,
+                             then a recomputed FP64 A = Q^T A0 Q or G = G0 V and
+                             FP64 sweeps to tol); -1 = automatic (default: on
+                             for n >= 512 or mixed precision) */
+    int sort;             /* 1 = eigenvalues ascending / sigma descending (default) */
+    int want_vectors;     /* 0 = eigenvalues (singular values) only; default 1 */
+} jacobi_opts;
+
+typedef struct {
+    int status;             /* same as the return value */
+    int sweeps;             /* total sweeps performed */
+    int sweeps_by_prec[3];  /* sweeps in BF16, FP32, FP64 */
+    int fallback_used;      /* batched warm start rejected -> cold start */
+    double off_rel;         /* final Xi(A)/||A||_F (eig) or max relative cosine (svd) */
+    double seconds;         /* wall time of the call */
+} jacobi_info;
+
+/* Fill *o with the defaults listed above.  Returns 0, or -1 if o is NULL. */
+int jacobi_opts_default(jacobi_opts *o);
+
+/* Device workspace in bytes needed by jacobi_eig / jacobi_svd /
+ * jacobi_eig_batched for these sizes and options (o may be NULL = defaults). */
+size_t jacobi_eig_workspace(int n, const jacobi_opts *o);
+size_t jacobi_svd_workspace(int m, int n, const jacobi_opts *o);
+size_t jacobi_eig_batched_workspace(int batch, const int *h_n, int dtype, const jacobi_opts *o);
+
+/*
+ * Symmetric eigendecomposition A = Q diag(W) Q^T (Alg. 1 Ensure clause).
+ *   n          order (>= 0)
+ *   dA, lda    symmetric input; only the `uplo` triangle ('U' or 'L') is read
+ *   dW         out: n eigenvalues (ascending when opts->sort)
+ *   dQ, ldq    out: n x n eigenvectors as columns (may be NULL when
+ *              opts->want_vectors == 0)
+ *   dQ0, ldq0  optional orthogonal start (warm start or resume from an
+ *              earlier iterate): the sweeps start from Q0^T A Q0 and Q = Q0.
+ *              NULL = identity.
+ *   dWork, workBytes, opts (NULL = defaults), info (may be NULL), stream
+ */
+int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq,
+               const double *dQ0, int ldq0, void *dWork, size_t workBytes,
+               const jacobi_opts *opts, jacobi_info *info, jacobi_stream_t stream);
+
+/*
+ * Thin SVD G = U diag(S) V^T by one-sided block Jacobi (Alg. 6, §6).
+ *   m >= n >= 0 (m < n returns -1); dG, ldg: m x n input
+ *   dS: n singular values (descending when opts->sort)
+ *   dU, ldu: m x n left vectors, U = G_final Sigma^+ (a zero sigma gives a
+ *   zero column); dV, ldv: n x n right vectors.  dU/dV may be NULL when
+ *   opts->want_vectors == 0.
+ */
+int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int ldu,
+               double *dV, int ldv, void *dWork, size_t workBytes, const jacobi_opts *opts,
+               jacobi_info *info, jacobi_stream_t stream);
+
+/*
+ * Batched symmetric eigendecomposition of `batch` independent matrices of
+ * orders h_n[k] (1 <= h_n[k] <= 256), one persistent launch.
+ *   h_offA[k]  element offset of matrix k in dA and dQ (host array, int64);
+ *              matrix k is column-major with leading dimension h_n[k]
+ *   dtype      JACOBI_F32 or JACOBI_F64: element type of dA
+ *   dW         out: eigenvalues, matrix k at offset sum_{i<k} h_n[i]
+ *   dQ         out: FP64 eigenvectors at the offsets h_offA
+ *   dQ0        optional FP64 warm starts at the offsets h_offA (NULL = cold);
+ *              a warm start that does not lower the off-norm is replaced by
+ *              the cold start (info[k].fallback_used)
+ *   info       NULL or an array of `batch` records
+ */
+int jacobi_eig_batched(int batch, const int *h_n, const int64_t *h_offA, int dtype, const void *dA,
+                       double *dW, double *dQ, const double *dQ0, void *dWork, size_t workBytes,
+                       const jacobi_opts *opts, jacobi_info *info, jacobi_stream_t stream);
+
+/* Text of the last error of the calling thread ("" if none). */
+const char *jacobi_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Building blocks exported for kernel-level tests                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The pair schedule used by the sweeps (Alg. 3 of §3, or the round-robin
+ * ordering derived from it).  N even >= 2 block indices.  Writes
+ * rounds * (N/2) pairs (I, J), I < J, 0-based, into hPairs (2 ints each,
+ * capacity N * (N - 1) ints) and returns the number of rounds, or a negative
+ * argument error.  For JACOBI_ORDER_ANTIDIAG the groups have unequal sizes;
+ * hSizes (capacity N) receives the size of each group (may be NULL for
+ * round-robin).
+ */
+int jacobi_schedule(int N, int ordering, int *hPairs, int *hSizes);
+
+/*
+ * Subproblem solver (the diagonalisation step of Alg. 2 on one processor):
+ * for `count` independent symmetric matrices of order m2 (32, 64 or 128),
+ * column-major and contiguous in dAhat (m2*m2 doubles each), run
+ * `inner_sweeps` round-robin sweeps of scalar Jacobi (0 = until the
+ * off-norm <= eps ||A_hat||_F, at most 30) and write the accumulated
+ * orthogonal V_hat (dV, m2*m2 doubles each, column-major) and the rotated
+ * matrix D_hat = V_hat^T A_hat V_hat (dD, same layout).  Returns 0 or an
+ * error code.
+ */
+int jacobi_subproblem_solve(int count, int m2, const double *dAhat, double *dV, double *dD,
+                            int inner_sweeps, jacobi_stream_t stream);
+
+/*
+ * One parallel step of Alg. 2 (§3) on explicit data: A (n x n, symmetric,
+ * full column-major, lda = n) and Q (n x n, may be NULL) are updated in place
+ * for the `npairs` disjoint block pairs hPairs (0-based, I < J, block size b;
+ * n must be a multiple of 2b and npairs == n / (2b), i.e. every block index
+ * belongs to one pair) with the rotations dV (npairs matrices of order 2b,
+ * column-major) and diagonal blocks dD (same layout):
+ *   A([I,J],[I,J]) <- D for each pair, every other block pair (p, q)
+ *   A[p, q] <- V_p^T A[p, q] V_q, and Q(:, [I,J]) <- Q(:, [I,J]) V.
+ */
+int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
+                      const double *dV, const double *dD, jacobi_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel profiling (benchmarks)                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Kernel kinds reported by jacobi_profile_query. */
+enum jacobi_prof_kind {
+    JACOBI_PROF_SUBPROBLEM = 0, /* 2b x 2b subproblem solver                     */
+    JACOBI_PROF_UPDATE_A = 1,   /* fused pair-tile update V_p^T A[p,q] V_q       */
+    JACOBI_PROF_UPDATE_Q = 2,   /* Q(:, [I,J]) V_hat                              */
+    JACOBI_PROF_GEMM = 3,       /* refinement GEMMs                              */
+    JACOBI_PROF_GRAM = 4        /* Gram blocks of the one-sided SVD              */
+};
+
+/*
+ * on != 0: from now on every launch of the kernels above records a HIP event
+ * pair on its launch stream plus its algorithmic work (flops and HBM bytes
+ * the method needs for that launch; rotation tiles whose both sides were
+ * skipped count zero).  Clears earlier records.  Synchronises the device.
+ * Not thread-safe against concurrent solver calls.  Returns 0 or 3.
+ */
+int jacobi_profile_enable(int on);
+
+/* Totals over the recorded launches of one kind: launch count, summed event
+ * time in milliseconds, summed algorithmic flops and bytes.  Any output
+ * pointer may be NULL.  Synchronises the device.  Returns 0 or 3. */
+int jacobi_profile_query(int kind, int *launches, double *total_ms, double *flops, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JACOBI_H */

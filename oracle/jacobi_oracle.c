@@ -223,6 +223,8 @@ static void sort_index(int n, const double *key, int *perm, int dir)
  *               (ora_rr_list on the n scalar indices)
  *   nthreads    > 1 with order 1: the disjoint rotations of a round are
  *               applied in parallel (§3: disjoint transformations commute)
+ *   max_rot     > 0: stop (status 1) once this many rotations were applied
+ *               (bounds the work for timing samples); 0 = no cap
  *   check_rot   if non-NULL, every rotation checks the identity
  *               off^2(after) = off^2(before) - 2 apq^2 (§1) and the largest
  *               relative deviation is stored here (O(n^2) per rotation).
@@ -230,7 +232,8 @@ static void sort_index(int n, const double *key, int *perm, int dir)
  */
 int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
             const double *Q0, int ldq0, double tol, int max_sweeps, int order,
-            int nthreads, double *check_rot, int *sweeps_out, long long *rot_out)
+            int nthreads, long long max_rot, double *check_rot, int *sweeps_out,
+            long long *rot_out)
 {
     if (n < 0) return -1;
     if (lda < (n > 1 ? n : 1)) return -3;
@@ -292,11 +295,13 @@ int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
         if (!isfinite(off)) { status = 2; break; }
         if (off <= tol * fro0) { status = 0; break; }
         if (sweeps >= max_sweeps) { status = 1; break; }
+        if (max_rot > 0 && nrot >= max_rot) { status = 1; break; }
         if (order == 0) {
             for (int p = 0; p < n - 1; ++p)
                 for (int q = p + 1; q < n; ++q) {
                     double apq = A[IDX(p, q, n)];
                     if (apq == 0.0) continue;
+                    if (max_rot > 0 && nrot >= max_rot) break;
                     double c, s, t, before = 0.0;
                     if (check_rot) before = ora_offnorm(n, A, n);
                     schur2(A[IDX(p, p, n)], A[IDX(q, q, n)], apq, &c, &s, &t);
@@ -312,6 +317,7 @@ int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
         } else {
             int base = 0;
             for (int K = 0; K < rounds; ++K) {
+                if (max_rot > 0 && nrot >= max_rot) break;
                 int np = rr_sizes[K];
                 const int *pr = rr_pairs + 2 * base;
                 base += np;

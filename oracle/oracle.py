@@ -25,7 +25,8 @@ def lib():
         L.ora_eig.restype = ctypes.c_int
         L.ora_eig.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
                               ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                              ctypes.c_int, _dp, _ip, ctypes.POINTER(ctypes.c_longlong)]
+                              ctypes.c_int, ctypes.c_longlong, _dp, _ip,
+                              ctypes.POINTER(ctypes.c_longlong)]
         L.ora_svd.restype = ctypes.c_int
         L.ora_svd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int,
                               _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip,
@@ -69,7 +70,7 @@ class OracleResult(dict):
 
 
 def eig(A, tol=1e-14, max_sweeps=50, order=1, Q0=None, want_vectors=True, nthreads=1,
-        check_rotations=False):
+        check_rotations=False, max_rotations=0):
     """Scalar cyclic Jacobi (Alg. 1 with b = 1).  Returns W ascending, Q, sweeps,
     rotations, status and (optionally) the largest relative deviation from the
     per-rotation identity off^2 -= 2 a_pq^2 (§1)."""
@@ -82,7 +83,7 @@ def eig(A, tol=1e-14, max_sweeps=50, order=1, Q0=None, want_vectors=True, nthrea
     nr = ctypes.c_longlong(0)
     chk = ctypes.c_double(0.0)
     rc = lib().ora_eig(n, _p(A), max(n, 1), _p(W), _p(Q), max(n, 1), _p(Q0a), max(n, 1),
-                       tol, max_sweeps, order, nthreads,
+                       tol, max_sweeps, order, nthreads, max_rotations,
                        ctypes.byref(chk) if check_rotations else None, ctypes.byref(sw),
                        ctypes.byref(nr))
     return OracleResult(W=W, Q=Q, sweeps=sw.value, rotations=nr.value, status=rc,

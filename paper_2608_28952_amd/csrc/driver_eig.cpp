@@ -1,0 +1,426 @@
+// driver_eig.cpp -- host orchestration of the blocked two-sided Jacobi
+// eigensolver (Alg. 1 run as Alg. 2, §3, on one GPU).
+//
+// Per sweep, per round r of the pair schedule (N/2 disjoint block pairs):
+//   K1  subproblem kernel: A_hat = A([I,J],[I,J]) -> V_hat, D_hat written back
+//   K2  fused tile update: A[p,q] <- V_p^T A[p,q] V_q for every p < q
+//   K2' Q(:, [I,J]) <- Q(:, [I,J]) V_hat
+// then Xi(A) (eq. Omega_A) is summed on the GPU and read back once per sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "jx_common.hpp"
+#include "jx_host.hpp"
+#include "jx_prof.hpp"
+
+namespace jx {
+
+// ---------------------------------------------------------------------------
+// Pair schedules
+// ---------------------------------------------------------------------------
+
+// Round-robin for even N: round K (0 .. N-2) pairs every I, J in 1 .. N-1 with
+// I + J = K (mod N-1) (Alg. 3's group K over the odd count N-1), and the index
+// left without a partner (2 I = K mod N-1) with N.  Pairs returned 0-based.
+static void schedule_rr(int N, std::vector<int> &pairs, std::vector<int> &sizes) {
+    const int M = N - 1;
+    pairs.clear();
+    sizes.assign(M, N / 2);
+    for (int K = 0; K < M; ++K) {
+        for (int I = 1; I <= M; ++I) {
+            int J = ((K - I) % M + M) % M;  // I + J = K (mod M), J in 0 .. M-1
+            if (J == 0) J = M;
+            if (J == I) {
+                pairs.push_back(I - 1);
+                pairs.push_back(N - 1);
+            } else if (I < J) {
+                pairs.push_back(I - 1);
+                pairs.push_back(J - 1);
+            }
+        }
+    }
+}
+
+// Alg. 3 (§3): group K holds the (I, J), I < J, with I + J = K (mod N).
+static void schedule_antidiag(int N, std::vector<int> &pairs, std::vector<int> &sizes) {
+    pairs.clear();
+    sizes.assign(N, 0);
+    for (int K = 0; K < N; ++K) {
+        for (int I = 1; I <= N; ++I) {
+            int J = ((K - I) % N + N) % N;
+            if (J == 0) J = N;
+            if (I < J) {
+                pairs.push_back(I - 1);
+                pairs.push_back(J - 1);
+                ++sizes[K];
+            }
+        }
+    }
+}
+
+int make_schedule(int N, int ordering, std::vector<int> &pairs, std::vector<int> &sizes) {
+    if (N < 2 || (N & 1)) return -1;
+    if (ordering == JACOBI_ORDER_ANTIDIAG) {
+        schedule_antidiag(N, pairs, sizes);
+        return N;
+    }
+    schedule_rr(N, pairs, sizes);
+    return N - 1;
+}
+
+// Rounds padded to N/2 pairs: a group of Alg. 3 with N/2 - 1 pairs leaves two
+// indices idle; they form a placeholder pair that is never rotated.
+static void padded_rounds(int N, int ordering, std::vector<int> &pairs, std::vector<int> &force) {
+    std::vector<int> raw, sizes;
+    const int R = make_schedule(N, ordering, raw, sizes);
+    const int H = N / 2;
+    pairs.assign((size_t)R * H * 2, 0);
+    force.assign((size_t)R * H, 0);
+    size_t base = 0;
+    for (int r = 0; r < R; ++r) {
+        std::vector<char> used(N, 0);
+        for (int k = 0; k < sizes[r]; ++k) {
+            const int I = raw[2 * (base + k)], J = raw[2 * (base + k) + 1];
+            pairs[2 * ((size_t)r * H + k)] = I;
+            pairs[2 * ((size_t)r * H + k) + 1] = J;
+            used[I] = used[J] = 1;
+        }
+        int k = sizes[r];
+        std::vector<int> idle;
+        for (int i = 0; i < N; ++i)
+            if (!used[i]) idle.push_back(i);
+        for (size_t t = 0; t + 1 < idle.size(); t += 2, ++k) {
+            pairs[2 * ((size_t)r * H + k)] = idle[t];
+            pairs[2 * ((size_t)r * H + k) + 1] = idle[t + 1];
+            force[(size_t)r * H + k] = 1;
+        }
+        base += sizes[r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plan and workspace
+// ---------------------------------------------------------------------------
+
+static int default_block(int n) { return n > 512 ? 64 : 32; }
+
+EigPlan plan_eig(int n, const jacobi_opts &o) {
+    EigPlan p{};
+    p.n = n;
+    p.b = o.block > 0 ? o.block : default_block(n);
+    const int unit = std::max(2 * p.b, 128);
+    p.npad = std::max(unit, (n + unit - 1) / unit * unit);
+    p.N = p.npad / p.b;
+    p.H = p.N / 2;
+    p.R = (o.ordering == JACOBI_ORDER_ANTIDIAG) ? p.N : p.N - 1;
+    p.vectors = o.want_vectors != 0;
+    const bool mixed = o.precision != JACOBI_PREC_FP64;
+    p.refine = p.vectors && (o.refine == 1 || (o.refine < 0 && (n >= 256 || mixed)));
+    const size_t npad = p.npad, nb = (size_t)p.N * (p.N + 1) / 2;
+    const size_t m2sq = (size_t)(2 * p.b) * (2 * p.b);
+    WorkspaceBuilder wb;
+    p.off_ablk = wb.add(sizeof(double) * nb * p.b * p.b);
+    p.off_q = p.vectors ? wb.add(sizeof(double) * npad * npad) : 0;
+    p.off_v = wb.add(sizeof(double) * 2 * p.H * m2sq);
+    p.off_flags = wb.add(sizeof(int) * 2 * p.H);
+    p.off_pairs = wb.add(sizeof(int) * 2 * (size_t)p.R * p.H);
+    p.off_force = wb.add(sizeof(int) * (size_t)p.R * p.H);
+    p.off_tiles = wb.add(sizeof(int) * (size_t)p.H * (p.H - 1));
+    p.off_partial = wb.add(sizeof(double) * 2 * nb);
+    p.off_scal = wb.add(sizeof(double) * 8);
+    p.off_w = wb.add(sizeof(double) * npad);
+    p.off_rank = wb.add(sizeof(int) * npad);
+    if (p.refine) {
+        p.off_a0 = wb.add(sizeof(double) * npad * npad);
+        p.off_t1 = wb.add(sizeof(double) * npad * npad);
+        p.off_t2 = wb.add(sizeof(double) * npad * npad);
+    }
+    p.total = wb.total();
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps
+// ---------------------------------------------------------------------------
+
+struct EigState {
+    const EigPlan &p;
+    char *ws;
+    hipStream_t s;
+    double *ablk, *Q, *V, *partial, *scal;
+    int *flags, *pairs, *force, *tiles;
+    double *h_scal;  // pinned
+    int inner;
+    double tol;
+    int any_force;
+    // profiling: skip flags of every round copied to pinned host memory
+    int *h_flaglog = nullptr;
+    int flog_cap = 0, flog_count = 0, flog_base = 0;
+
+    double *Vbuf(int r) const { return V + (size_t)(r & 1) * p.H * (2 * p.b) * (2 * p.b); }
+    int *Fbuf(int r) const { return flags + (size_t)(r & 1) * p.H; }
+
+    // {Xi(A)^2, sum of squared diagonal}
+    void norms(double &off2, double &dia2) {
+        launch_block_norms(p.npad, p.b, ablk, partial, scal, s);
+        JX_HIP(hipMemcpyAsync(h_scal, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        JX_HIP(hipStreamSynchronize(s));
+        off2 = h_scal[0];
+        dia2 = h_scal[1];
+    }
+
+    void sweep(double skip_thr) {
+        const int m2 = 2 * p.b;
+        const int ntiles = p.H * (p.H - 1) / 2;
+        // subproblem work per pair and inner sweep: 2x2 pair-block updates
+        // (24 flops off the diagonal) and the V_hat rotations (6 flops per entry pair)
+        const double hi = m2 / 2;  // inner pairs per inner round
+        const double k1_flops = (double)p.H * std::max(1, inner) * (m2 - 1) *
+                                (24.0 * hi * (hi - 1) / 2 + 6.0 * m2 * hi);
+        const double k1_bytes = (double)p.H * 6.0 * p.b * p.b * sizeof(double);
+        for (int r = 0; r < p.R; ++r) {
+            const int *pr = pairs + (size_t)2 * r * p.H;
+            SubArgs a{};
+            a.mode = SUB_EIG;
+            a.m2 = m2;
+            a.count = p.H;
+            a.pairs = pr;
+            a.ablk = ablk;
+            a.vout = Vbuf(r);
+            a.flags = Fbuf(r);
+            a.skip_thr = skip_thr;
+            a.inner_sweeps = inner;
+            a.force_skip = any_force ? force + (size_t)r * p.H : nullptr;
+            {
+                ProfScope ps(PROF_SUBPROBLEM, s, k1_flops, k1_bytes);
+                launch_subproblem(a, s);
+            }
+            int slot = -1;
+            if (h_flaglog && flog_count < flog_cap) {
+                JX_HIP(hipMemcpyAsync(h_flaglog + (size_t)flog_count * p.H, Fbuf(r), sizeof(int) * p.H,
+                                      hipMemcpyDeviceToHost, s));
+                slot = flog_base + flog_count * p.H;
+                ++flog_count;
+            }
+            {
+                ProfScope ps(PROF_UPDATE_A, s, 0.0, 0.0, slot, p.H, m2);
+                launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tiles, ntiles, s);
+            }
+            if (p.vectors) {
+                ProfScope ps(PROF_UPDATE_Q, s, (double)p.npad, 0.0, slot, p.H, m2);
+                launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), s);
+            }
+        }
+    }
+};
+
+// FP64 GEMM with profiling record.
+static void gemm_p(char ta, char tb, int M, int N, int K, double alpha, const double *A, int lda,
+                   const double *B, int ldb, double beta, double *C, int ldc, hipStream_t s) {
+    ProfScope ps(PROF_GEMM, s, 2.0 * M * (double)N * K,
+                 sizeof(double) * ((double)M * K + (double)K * N + (beta != 0.0 ? 2.0 : 1.0) * M * N));
+    launch_gemm_f64(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+
+static bool finite(double x) { return std::isfinite(x); }
+
+int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq,
+            const double *dQ0, int ldq0, void *dWork, size_t workBytes, const jacobi_opts &o,
+            jacobi_info *info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    jacobi_info inf{};
+    EigPlan p = plan_eig(n, o);
+    DeviceBuffer own;
+    char *ws = static_cast<char *>(dWork);
+    if (!ws) {
+        own.alloc(p.total);
+        ws = own.ptr;
+    } else if (workBytes < p.total) {
+        return -100;
+    }
+    PinnedScalars pin(8);
+
+    EigState st{p, ws, s};
+    st.ablk = reinterpret_cast<double *>(ws + p.off_ablk);
+    st.Q = p.vectors ? reinterpret_cast<double *>(ws + p.off_q) : nullptr;
+    st.V = reinterpret_cast<double *>(ws + p.off_v);
+    st.flags = reinterpret_cast<int *>(ws + p.off_flags);
+    st.pairs = reinterpret_cast<int *>(ws + p.off_pairs);
+    st.force = reinterpret_cast<int *>(ws + p.off_force);
+    st.tiles = reinterpret_cast<int *>(ws + p.off_tiles);
+    st.partial = reinterpret_cast<double *>(ws + p.off_partial);
+    st.scal = reinterpret_cast<double *>(ws + p.off_scal);
+    st.h_scal = pin.ptr;
+    st.inner = o.inner_max_sweeps;
+    st.tol = o.tol;
+    struct PinnedInts {
+        int *ptr = nullptr;
+        ~PinnedInts() { if (ptr) (void)hipHostFree(ptr); }
+    } flaglog;
+    if (prof_on()) {
+        st.flog_cap = (o.max_sweeps + 8) * p.R;
+        JX_HIP(hipHostMalloc(reinterpret_cast<void **>(&flaglog.ptr), sizeof(int) * (size_t)st.flog_cap * p.H,
+                             hipHostMallocDefault));
+        st.h_flaglog = flaglog.ptr;
+        st.flog_base = prof_flag_base();
+    }
+
+    // schedule and tile list (host -> device once per call)
+    std::vector<int> hp, hf;
+    padded_rounds(p.N, o.ordering, hp, hf);
+    st.any_force = std::any_of(hf.begin(), hf.end(), [](int v) { return v != 0; }) ? 1 : 0;
+    std::vector<int> ht;
+    for (int a = 0; a < p.H; ++a)
+        for (int b = a + 1; b < p.H; ++b) { ht.push_back(a); ht.push_back(b); }
+    JX_HIP(hipMemcpyAsync(st.pairs, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, s));
+    JX_HIP(hipMemcpyAsync(st.force, hf.data(), sizeof(int) * hf.size(), hipMemcpyHostToDevice, s));
+    if (!ht.empty())
+        JX_HIP(hipMemcpyAsync(st.tiles, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
+
+    // A -> upper block storage; Q = I or Q0 (then A <- Q0^T A Q0)
+    double *A0 = p.refine ? reinterpret_cast<double *>(ws + p.off_a0) : nullptr;
+    double *T1 = p.refine ? reinterpret_cast<double *>(ws + p.off_t1) : nullptr;
+    double *T2 = p.refine ? reinterpret_cast<double *>(ws + p.off_t2) : nullptr;
+    if (p.refine) launch_full_from_triangle(n, p.npad, dA, lda, uplo, A0, s);
+    if (dQ0 && p.vectors) {
+        launch_copy_pad(n, p.npad, dQ0, ldq0, st.Q, p.npad, s);
+        double *F = A0, *T = T1, *A1 = T2;
+        DeviceBuffer tmp;
+        if (!p.refine) {
+            tmp.alloc(sizeof(double) * 3 * (size_t)p.npad * p.npad);
+            F = reinterpret_cast<double *>(tmp.ptr);
+            T = F + (size_t)p.npad * p.npad;
+            A1 = T + (size_t)p.npad * p.npad;
+            launch_full_from_triangle(n, p.npad, dA, lda, uplo, F, s);
+        }
+        gemm_p('N', 'N', p.npad, p.npad, p.npad, 1.0, F, p.npad, st.Q, p.npad, 0.0, T, p.npad, s);
+        gemm_p('T', 'N', p.npad, p.npad, p.npad, 1.0, st.Q, p.npad, T, p.npad, 0.0, A1, p.npad, s);
+        launch_pack_sym(p.npad, p.npad, p.b, A1, p.npad, 'U', st.ablk, s);
+        JX_HIP(hipStreamSynchronize(s));
+    } else {
+        launch_pack_sym(n, p.npad, p.b, dA, lda, uplo, st.ablk, s);
+        if (p.vectors) launch_set_identity(p.npad, p.npad, st.Q, p.npad, s);
+    }
+
+    double off2, dia2;
+    st.norms(off2, dia2);
+    const double fro0 = std::sqrt(off2 + dia2);
+    int status = 1;
+    if (!finite(off2) || !finite(dia2)) status = 2;
+    const double skip_thr = o.tol * fro0 * std::sqrt(2.0 / ((double)p.N * (p.N - 1)));
+    int sweeps = 0;
+    auto converge = [&](int cap) -> int {
+        for (;;) {
+            if (!finite(off2) || !finite(dia2)) return 2;
+            if (std::sqrt(off2) <= o.tol * fro0) return 0;
+            if (sweeps >= cap) return 1;
+            st.sweep(skip_thr);
+            ++sweeps;
+            st.norms(off2, dia2);
+        }
+    };
+    if (status != 2) status = converge(o.max_sweeps);
+
+    // orthogonality refinement: Q <- Q (3 I - Q^T Q) / 2, A1 = Q^T A0 Q in FP64,
+    // then sweeps to tol from A1 (whose rotations are tiny)
+    if (status == 0 && p.refine) {
+        const int np = p.npad;
+        gemm_p('T', 'N', np, np, np, 1.0, st.Q, np, st.Q, np, 0.0, T1, np, s);    // M = Q^T Q
+        JX_HIP(hipMemcpyAsync(T2, st.Q, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
+        gemm_p('N', 'N', np, np, np, -0.5, st.Q, np, T1, np, 1.5, T2, np, s);     // 1.5 Q - 0.5 Q M
+        JX_HIP(hipMemcpyAsync(st.Q, T2, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
+        gemm_p('N', 'N', np, np, np, 1.0, A0, np, st.Q, np, 0.0, T1, np, s);      // A0 Q
+        gemm_p('T', 'N', np, np, np, 1.0, st.Q, np, T1, np, 0.0, T2, np, s);      // Q^T A0 Q
+        launch_pack_sym(np, np, p.b, T2, np, 'U', st.ablk, s);
+        st.norms(off2, dia2);
+        status = converge(o.max_sweeps + 4);
+    }
+
+    // eigenvalues (first n diagonal entries), sorted; Q columns permuted alike
+    double *w = reinterpret_cast<double *>(ws + p.off_w);
+    int *rank = reinterpret_cast<int *>(ws + p.off_rank);
+    if (status != 2) {
+        launch_extract_diag(p.npad, p.b, st.ablk, w, s);
+        if (o.sort) {
+            launch_rank(n, w, +1, rank, s);
+        } else {
+            std::vector<int> id(n);
+            for (int i = 0; i < n; ++i) id[i] = i;
+            JX_HIP(hipMemcpyAsync(rank, id.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        }
+        launch_scatter_values(n, w, rank, dW, s);
+        if (p.vectors && dQ) launch_scatter_columns(n, n, st.Q, p.npad, rank, dQ, ldq, s);
+        JX_HIP(hipStreamSynchronize(s));
+    }
+    if (st.h_flaglog) {
+        JX_HIP(hipStreamSynchronize(s));
+        prof_add_flags(std::vector<int>(st.h_flaglog, st.h_flaglog + (size_t)st.flog_count * p.H));
+    }
+    inf.status = status;
+    inf.sweeps = sweeps;
+    inf.sweeps_by_prec[2] = sweeps;
+    inf.off_rel = fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-level entry points for tests
+// ---------------------------------------------------------------------------
+
+int run_subproblem(int count, int m2, const double *dAhat, double *dV, double *dD, int inner,
+                   hipStream_t s) {
+    SubArgs a{};
+    a.mode = SUB_PLAIN;
+    a.m2 = m2;
+    a.count = count;
+    a.ahat = dAhat;
+    a.vout = dV;
+    a.dout = dD;
+    a.inner_sweeps = inner;
+    launch_subproblem(a, s);
+    JX_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
+                   const double *dV, const double *dD, hipStream_t s) {
+    const int N = n / b, H = N / 2, m2 = 2 * b;
+    const size_t nb = (size_t)N * (N + 1) / 2;
+    DeviceBuffer buf;
+    WorkspaceBuilder wb;
+    const size_t o_ab = wb.add(sizeof(double) * nb * b * b);
+    const size_t o_v = wb.add(sizeof(double) * (size_t)H * m2 * m2);
+    const size_t o_f = wb.add(sizeof(int) * H);
+    const size_t o_p = wb.add(sizeof(int) * 2 * H);
+    const size_t o_t = wb.add(sizeof(int) * (size_t)H * (H - 1) + sizeof(int));
+    buf.alloc(wb.total());
+    double *ablk = reinterpret_cast<double *>(buf.ptr + o_ab);
+    double *V = reinterpret_cast<double *>(buf.ptr + o_v);
+    int *flags = reinterpret_cast<int *>(buf.ptr + o_f);
+    int *pairs = reinterpret_cast<int *>(buf.ptr + o_p);
+    int *tiles = reinterpret_cast<int *>(buf.ptr + o_t);
+    std::vector<int> ht;
+    for (int a = 0; a < H; ++a)
+        for (int c = a + 1; c < H; ++c) { ht.push_back(a); ht.push_back(c); }
+    (void)npairs;
+    JX_HIP(hipMemcpyAsync(pairs, hPairs, sizeof(int) * 2 * H, hipMemcpyHostToDevice, s));
+    if (!ht.empty()) JX_HIP(hipMemcpyAsync(tiles, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
+    JX_HIP(hipMemsetAsync(flags, 0, sizeof(int) * H, s));
+    launch_pack_sym(n, n, b, dA, n, 'U', ablk, s);
+    launch_vperm_from_colmajor(H, m2, dV, V, s);
+    launch_write_pair_blocks(H, b, pairs, dD, ablk, s);
+    launch_update_a(b, H, pairs, ablk, V, flags, tiles, (int)ht.size() / 2, s);
+    if (dQ) launch_update_q(b, H, pairs, dQ, n, n, V, flags, s);
+    launch_unpack_sym(n, b, ablk, dA, n, s);
+    JX_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+}  // namespace jx

@@ -1,0 +1,146 @@
+// jx_common.hpp -- shared definitions of the gfx950 kernels and their host
+// drivers (libjacobi.so).  Nothing here is exported; the public surface is
+// include/jacobi.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/jacobi.h"
+
+namespace jx {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+const char *last_error();
+
+struct HipFail {
+    hipError_t err;
+};
+
+#define JX_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::jx::set_error(std::string(#call) + ": " + hipGetErrorString(e_) + " at " +  \
+                            __FILE__ + ":" + std::to_string(__LINE__));                   \
+            throw ::jx::HipFail{e_};                                                      \
+        }                                                                                 \
+    } while (0)
+
+#define JX_LAUNCHED() JX_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// MFMA operand vectors
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4_f64 (lane layout measured on gfx950): lane l = 16 g + x
+// (g = l / 16, x = l % 16) supplies A(x, g) and B(g, x); component v of the
+// lane's d4 result holds D(g + 4 v, x) -- rows interleaved by 4.
+// v_mfma_f32_16x16x4_f32: same operands; component v holds D(4 g + v, x).
+// The contraction index g may be mapped to any column of A / row of B as long
+// as both operands use the same map.  With the f64 layout, component s of the
+// result tile of rows 16 a .. 16 a + 15 is exactly the B operand of the k-step
+// k = 16 a + 4 s + g, so a product can feed the next one from registers.
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Rotation storage ("V_hat") in the MFMA-operand order.
+//
+// V_hat of order m2 (multiple of 16) is consumed as an MFMA operand with the
+// contraction index k = k0 + g (k0 a multiple of 4, g the lane group) and the
+// free index i.  vperm(k, i) places the 64 values of one MFMA step (4 lane
+// groups x 16 consecutive i) in 64 consecutive doubles.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int vperm(int k, int i, int m2) {
+    return (((k >> 2) * (m2 >> 4) + (i >> 4)) << 6) + ((k & 3) << 4) + (i & 15);
+}
+
+// Upper block-triangle storage of the symmetric iterate: block (I, J), I <= J,
+// of order b, column-major, at block slot J (J + 1) / 2 + I.
+__host__ __device__ __forceinline__ size_t ublk(int I, int J) {
+    return (size_t)J * (J + 1) / 2 + I;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+
+// Where the subproblem solver reads A_hat and writes its results.
+enum SubMode {
+    SUB_EIG = 0,     // A_hat from the upper block storage, D_hat written back there
+    SUB_PLAIN = 1,   // A_hat contiguous (count x m2 x m2), V and D col-major out
+    SUB_GRAM = 2     // A_hat contiguous (Gram blocks), only V_hat (vperm) out
+};
+
+struct SubArgs {
+    int mode;
+    int m2;                 // 2b
+    int count;              // subproblems (pairs) in this launch
+    const int *pairs;       // device, 2 ints per pair (SUB_EIG)
+    double *ablk;           // SUB_EIG: upper block storage of A (b = m2 / 2)
+    const double *ahat;     // SUB_PLAIN / SUB_GRAM input
+    double *vout;           // V_hat per pair: vperm (SUB_EIG/GRAM) or col-major (PLAIN)
+    double *dout;           // SUB_PLAIN: D_hat col-major
+    int *flags;             // per pair: 1 = skipped (V_hat = I), may be NULL
+    double skip_thr;        // skip a pair whose off(A_hat) <= skip_thr (SUB_EIG/GRAM)
+    int inner_sweeps;       // 0 = to inner convergence (cap 30)
+    double *inner_off;      // optional per-pair |off(A_hat)| before the solve
+    const int *force_skip;  // optional per pair: 1 = placeholder pair, never rotated
+};
+void launch_subproblem(const SubArgs &a, hipStream_t s);
+
+// Fused two-sided update of the off-diagonal pair tiles of one round:
+// A[p,q] <- V_p^T A[p,q] V_q for p < q (pair indices of the round).
+void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
+                     const int *flags, const int *tiles, int ntiles, hipStream_t s);
+// One-sided update Q(:, [I,J]) <- Q(:, [I,J]) V_p for every pair p and every
+// 128-row chunk of Q (n_rows multiple of 128).
+void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
+                     const double *vhat, const int *flags, hipStream_t s);
+
+// Layout conversion and reductions.
+void launch_pack_sym(int n, int npad, int b, const double *A, int lda, char uplo, double *ablk,
+                     hipStream_t s);
+void launch_unpack_sym(int npad, int b, const double *ablk, double *A, int lda, hipStream_t s);
+void launch_full_from_triangle(int n, int npad, const double *A, int lda, char uplo, double *F,
+                               hipStream_t s);
+// partial[blk] = {off-diagonal sum of squares counted for both triangles,
+// sum of squares of the diagonal}; then reduce to out[0..1] in a fixed order.
+void launch_block_norms(int npad, int b, const double *ablk, double *partial, double *out,
+                        hipStream_t s);
+void launch_set_identity(int n, int npad, double *Q, int ldq, hipStream_t s);
+void launch_copy_pad(int n, int npad, const double *src, int lds_, double *dst, int ldd,
+                     hipStream_t s);
+void launch_extract_diag(int npad, int b, const double *ablk, double *w, hipStream_t s);
+// Stable rank sort of w[0..n) (ascending if dir > 0, descending otherwise):
+// rank[i] = number of j with w_j before w_i.
+void launch_rank(int n, const double *w, int dir, int *rank, hipStream_t s);
+void launch_scatter_values(int n, const double *w, const int *rank, double *out, hipStream_t s);
+// out(:, rank[i]) = src(:, i) for the first `rows` rows of n columns.
+void launch_scatter_columns(int rows, int n, const double *src, int lds_, const int *rank,
+                            double *out, int ldo, hipStream_t s);
+
+// Test helpers: column-major V_hat -> vperm order; D_hat -> pair blocks.
+void launch_vperm_from_colmajor(int count, int m2, const double *src, double *dst, hipStream_t s);
+void launch_write_pair_blocks(int count, int b, const int *pairs, const double *D, double *ablk,
+                              hipStream_t s);
+
+// General FP64 GEMM on column-major operands: C = alpha op(A) op(B) + beta C,
+// M x N result, K contraction, every dimension a multiple of 128 (16 for K).
+void launch_gemm_f64(char ta, char tb, int M, int N, int K, double alpha, const double *A, int lda,
+                     const double *B, int ldb, double beta, double *C, int ldc, hipStream_t s);
+
+}  // namespace jx

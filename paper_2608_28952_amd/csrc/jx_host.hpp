@@ -1,0 +1,68 @@
+// jx_host.hpp -- host-side helpers shared by the drivers of libjacobi.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "jx_common.hpp"
+
+namespace jx {
+
+// Sub-allocations of one device workspace, each aligned to 256 bytes.
+struct WorkspaceBuilder {
+    size_t off = 0;
+    size_t add(size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    }
+    size_t total() const { return off > 0 ? off : 256; }
+};
+
+// Library-owned device memory for calls that pass no workspace.
+struct DeviceBuffer {
+    char *ptr = nullptr;
+    void alloc(size_t bytes) {
+        void *p = nullptr;
+        JX_HIP(hipMalloc(&p, bytes));
+        ptr = static_cast<char *>(p);
+    }
+    ~DeviceBuffer() {
+        if (ptr) (void)hipFree(ptr);
+    }
+};
+
+// Small pinned host buffer for per-sweep scalars read back from the GPU.
+struct PinnedScalars {
+    double *ptr = nullptr;
+    explicit PinnedScalars(size_t count) {
+        void *p = nullptr;
+        JX_HIP(hipHostMalloc(&p, sizeof(double) * count, hipHostMallocDefault));
+        ptr = static_cast<double *>(p);
+    }
+    ~PinnedScalars() {
+        if (ptr) (void)hipHostFree(ptr);
+    }
+};
+
+struct EigPlan {
+    int n, npad, b, N, H, R;
+    bool vectors, refine;
+    size_t off_ablk, off_q, off_v, off_flags, off_pairs, off_force, off_tiles, off_partial,
+        off_scal, off_w, off_rank, off_a0, off_t1, off_t2;
+    size_t total;
+};
+
+EigPlan plan_eig(int n, const jacobi_opts &o);
+int make_schedule(int N, int ordering, std::vector<int> &pairs, std::vector<int> &sizes);
+int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq,
+            const double *dQ0, int ldq0, void *dWork, size_t workBytes, const jacobi_opts &o,
+            jacobi_info *info, hipStream_t s);
+int run_subproblem(int count, int m2, const double *dAhat, double *dV, double *dD, int inner,
+                   hipStream_t s);
+int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
+                   const double *dV, const double *dD, hipStream_t s);
+
+}  // namespace jx

@@ -1,0 +1,250 @@
+"""Thin ctypes binding of libjacobi.so (include/jacobi.h).
+
+Argument marshalling only: every step of the solvers runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.  If
+the built library is missing, every call raises; there is no fallback.
+
+Layout: the library is column-major.  A torch tensor is row-major, so a
+row-major n x n buffer read as column-major is the transpose; the wrappers
+below handle that (symmetric inputs flip `uplo`; outputs are returned as
+transposed views so that ``Q[:, j]`` is eigenvector j).
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libjacobi.so")
+
+_lib = None
+
+ORDER_ROUND_ROBIN = 0
+ORDER_ANTIDIAG = 1
+PREC_FP64 = 0
+PREC_MIXED_FP32 = 1
+PREC_MIXED_BF16 = 2
+F32 = 0
+F64 = 1
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("block", ctypes.c_int),
+                ("ordering", ctypes.c_int), ("precision", ctypes.c_int),
+                ("inner_max_sweeps", ctypes.c_int), ("refine", ctypes.c_int), ("sort", ctypes.c_int),
+                ("want_vectors", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("sweeps", ctypes.c_int), ("sweeps_by_prec", ctypes.c_int * 3),
+                ("fallback_used", ctypes.c_int), ("off_rel", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"status": self.status, "sweeps": self.sweeps, "sweeps_by_prec": list(self.sweeps_by_prec),
+                "fallback_used": self.fallback_used, "off_rel": self.off_rel, "seconds": self.seconds}
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    """Load libjacobi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libjacobi.so not built ({LIB_PATH}); run python -m paper_2608_28952_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.jacobi_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.jacobi_last_error.restype = ctypes.c_char_p
+        L.jacobi_eig_workspace.restype = ctypes.c_size_t
+        L.jacobi_eig_workspace.argtypes = [ctypes.c_int, ctypes.POINTER(Opts)]
+        L.jacobi_svd_workspace.restype = ctypes.c_size_t
+        L.jacobi_svd_workspace.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts)]
+        L.jacobi_eig_batched_workspace.restype = ctypes.c_size_t
+        L.jacobi_eig_batched_workspace.argtypes = [ctypes.c_int, _ip, ctypes.c_int, ctypes.POINTER(Opts)]
+        L.jacobi_eig.argtypes = [ctypes.c_int, _vp, ctypes.c_int, ctypes.c_char, _vp, _vp, ctypes.c_int, _vp,
+                                 ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(Opts), ctypes.POINTER(Info), _vp]
+        L.jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp,
+                                 ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(Opts), ctypes.POINTER(Info), _vp]
+        L.jacobi_eig_batched.argtypes = [ctypes.c_int, _ip, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _vp, _vp,
+                                         _vp, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Opts),
+                                         ctypes.POINTER(Info), _vp]
+        L.jacobi_schedule.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip]
+        L.jacobi_subproblem_solve.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
+        L.jacobi_block_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().jacobi_last_error().decode()
+
+
+def opts_default(**kw):
+    o = Opts()
+    lib().jacobi_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class JacobiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"jacobi error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, allow=(0,)):
+    if rc not in allow:
+        raise JacobiError(rc, last_error())
+    return rc
+
+
+def _colmajor_view(t):
+    """(ptr tensor, ld) for reading t (m x n) as column-major, copying if needed."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    if t.stride(0) == 1 and t.stride(1) >= max(t.shape[0], 1):
+        return t, t.stride(1)
+    c = t.t().contiguous().t()
+    return c, max(c.shape[0], 1)
+
+
+def jacobi_eig(A, uplo="U", Q0=None, opts=None, work=None, check=True):
+    """Symmetric eigendecomposition of the float64 CUDA tensor A (n x n).
+
+    Returns (W, Q, info) with W ascending and Q[:, j] the eigenvector of W[j]
+    (Q is None when opts.want_vectors == 0).  `uplo` names the valid triangle
+    of A in the usual (row, column) indexing.  With check=True a non-zero
+    status raises; otherwise it is returned in info["status"]."""
+    import torch
+    o = opts if opts is not None else opts_default()
+    n = A.shape[0]
+    if A.shape != (n, n) or A.dtype != torch.float64 or not A.is_cuda:
+        raise ValueError("A must be a square float64 CUDA tensor")
+    if A.is_contiguous():  # row-major buffer = A^T column-major; the valid triangle flips
+        Ab, lda, ul = A, max(n, 1), {"U": b"L", "L": b"U"}[uplo.upper()]
+    else:
+        Ab, lda = _colmajor_view(A)
+        ul = uplo.upper().encode()
+    W = torch.empty(n, dtype=torch.float64, device=A.device)
+    Qt = torch.empty((n, n), dtype=torch.float64, device=A.device) if o.want_vectors else None
+    q0b, ldq0 = None, max(n, 1)
+    if Q0 is not None:
+        q0b, ldq0 = _colmajor_view(Q0.to(torch.float64))
+    info = Info()
+    rc = lib().jacobi_eig(n, _ptr(Ab), lda, ul, _ptr(W), _ptr(Qt), max(n, 1), _ptr(q0b), ldq0,
+                          _ptr(work), work.numel() * work.element_size() if work is not None else 0,
+                          ctypes.byref(o), ctypes.byref(info), _stream())
+    if check:
+        _check(rc)
+    Q = Qt.t() if Qt is not None else None
+    return W, Q, info.as_dict()
+
+
+def jacobi_eig_workspace(n, opts=None):
+    o = opts if opts is not None else opts_default()
+    return lib().jacobi_eig_workspace(n, ctypes.byref(o))
+
+
+def jacobi_svd(G, opts=None, work=None, check=True):
+    """Thin SVD G = U diag(S) V^T of the float64 CUDA tensor G (m x n, m >= n)
+    by one-sided block Jacobi.  Returns (S, U, V, info), S descending."""
+    import torch
+    o = opts if opts is not None else opts_default()
+    m, n = G.shape
+    Gb, ldg = _colmajor_view(G)
+    S = torch.empty(n, dtype=torch.float64, device=G.device)
+    Ut = torch.empty((n, m), dtype=torch.float64, device=G.device) if o.want_vectors else None
+    Vt = torch.empty((n, n), dtype=torch.float64, device=G.device) if o.want_vectors else None
+    info = Info()
+    rc = lib().jacobi_svd(m, n, _ptr(Gb), ldg, _ptr(S), _ptr(Ut), max(m, 1), _ptr(Vt), max(n, 1),
+                          _ptr(work), work.numel() * work.element_size() if work is not None else 0,
+                          ctypes.byref(o), ctypes.byref(info), _stream())
+    if check:
+        _check(rc)
+    return S, (Ut.t() if Ut is not None else None), (Vt.t() if Vt is not None else None), info.as_dict()
+
+
+def jacobi_svd_workspace(m, n, opts=None):
+    o = opts if opts is not None else opts_default()
+    return lib().jacobi_svd_workspace(m, n, ctypes.byref(o))
+
+
+def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, check=True):
+    """Batched eigendecomposition.  `sizes` (host int sequence), `offsets`
+    (host int64 element offsets, len = batch), `packed` a float32 or float64
+    CUDA tensor holding each matrix column-major at its offset.  Returns
+    (W packed by prefix sums of n_k, Q packed at the offsets, list of info)."""
+    import numpy as np
+    import torch
+    o = opts if opts is not None else opts_default()
+    batch = len(sizes)
+    hn = (ctypes.c_int * batch)(*[int(v) for v in sizes])
+    ho = (ctypes.c_int64 * batch)(*[int(v) for v in offsets[:batch]])
+    dtype = F32 if packed.dtype == torch.float32 else F64
+    total_w = int(np.sum(np.asarray(sizes, dtype=np.int64)))
+    total_q = int(offsets[batch - 1]) + int(sizes[-1]) ** 2 if batch else 0
+    W = torch.empty(total_w, dtype=torch.float64, device=packed.device)
+    Q = torch.empty(total_q, dtype=torch.float64, device=packed.device)
+    infos = (Info * max(batch, 1))()
+    rc = lib().jacobi_eig_batched(batch, hn, ho, dtype, _ptr(packed), _ptr(W), _ptr(Q), _ptr(Q0),
+                                  _ptr(work), work.numel() * work.element_size() if work is not None else 0,
+                                  ctypes.byref(o), infos, _stream())
+    if check:
+        _check(rc)
+    return W, Q, [infos[k].as_dict() for k in range(batch)]
+
+
+def jacobi_schedule(N, ordering=ORDER_ROUND_ROBIN):
+    """The pair schedule (host computation): list of rounds of 0-based pairs."""
+    pairs = (ctypes.c_int * max(N * (N - 1), 2))()
+    sizes = (ctypes.c_int * max(N, 1))()
+    R = lib().jacobi_schedule(N, ordering, pairs, sizes)
+    if R < 0:
+        raise JacobiError(R, "invalid schedule arguments")
+    out, base = [], 0
+    for r in range(R):
+        k = sizes[r] if ordering == ORDER_ANTIDIAG else N // 2
+        out.append([(pairs[2 * (base + i)], pairs[2 * (base + i) + 1]) for i in range(k)])
+        base += k
+    return out
+
+
+def jacobi_subproblem_solve(Ahat, inner_sweeps=0):
+    """Solve count independent m2 x m2 symmetric subproblems (count x m2 x m2
+    float64 CUDA tensor, each read column-major = as given, symmetric).
+    Returns (V, D) with V[k] orthogonal and D[k] = V[k]^T Ahat[k] V[k]
+    (both as count x m2 x m2 tensors in the usual indexing)."""
+    import torch
+    count, m2, _ = Ahat.shape
+    A = Ahat.transpose(1, 2).contiguous()  # column-major per matrix
+    V = torch.empty_like(A)
+    D = torch.empty_like(A)
+    _check(lib().jacobi_subproblem_solve(count, m2, _ptr(A), _ptr(V), _ptr(D), inner_sweeps, _stream()))
+    return V.transpose(1, 2), D.transpose(1, 2)
+
+
+def jacobi_block_step(A, Q, b, pairs, V, D):
+    """One parallel step of Alg. 2 on explicit data (in place on copies):
+    returns (A_new, Q_new).  A, Q: n x n float64 CUDA tensors; V, D:
+    len(pairs) x 2b x 2b tensors in the usual indexing."""
+    import torch
+    n = A.shape[0]
+    Ac = A.t().contiguous()   # column-major A
+    Qc = Q.t().contiguous() if Q is not None else None
+    Vc = V.transpose(1, 2).contiguous()
+    Dc = D.transpose(1, 2).contiguous()
+    flat = [int(v) for pr in pairs for v in pr]
+    hp = (ctypes.c_int * len(flat))(*flat)
+    _check(lib().jacobi_block_step(n, b, _ptr(Ac), _ptr(Qc), len(pairs), hp, _ptr(Vc), _ptr(Dc), _stream()))
+    torch.cuda.synchronize()
+    return Ac.t(), (Qc.t() if Qc is not None else None)

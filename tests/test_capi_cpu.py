@@ -1,0 +1,89 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and its host-only logic (the pair schedule, argument checks,
+workspace queries) behaves; no GPU compute is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jacobi.h")
+
+
+def _jx():
+    from paper_2608_28952_amd import jacobi
+    if not os.path.exists(jacobi.LIB_PATH):
+        from paper_2608_28952_amd import build
+        build.build()
+    return jacobi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jacobi_[a-z_]+|jws_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    jx = _jx()
+    L = ctypes.CDLL(jx.LIB_PATH)
+    names = declared_functions()
+    assert "jacobi_eig" in names and "jacobi_svd" in names and "jacobi_eig_batched" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 64, 128])
+def test_round_robin_schedule_matches_oracle(N):
+    jx = _jx()
+    lib_rounds = jx.jacobi_schedule(N, jx.ORDER_ROUND_ROBIN)
+    ora_rounds = O.rr_list(N)
+    assert len(lib_rounds) == len(ora_rounds) == N - 1
+    for a, b in zip(lib_rounds, ora_rounds):
+        assert sorted(a) == sorted(b)
+
+
+@pytest.mark.parametrize("N", [2, 8, 16, 64])
+def test_antidiag_schedule_matches_oracle(N):
+    jx = _jx()
+    lib_rounds = jx.jacobi_schedule(N, jx.ORDER_ANTIDIAG)
+    ora_rounds = O.antidiag_list(N)
+    assert len(lib_rounds) == len(ora_rounds) == N
+    for a, b in zip(lib_rounds, ora_rounds):
+        assert sorted(a) == sorted(b)
+
+
+def test_schedule_rejects_odd_and_small():
+    jx = _jx()
+    with pytest.raises(jx.JacobiError):
+        jx.jacobi_schedule(7)
+    with pytest.raises(jx.JacobiError):
+        jx.jacobi_schedule(1)
+
+
+def test_opts_defaults_and_workspace():
+    jx = _jx()
+    o = jx.opts_default()
+    assert o.tol == 1e-14 and o.max_sweeps == 60 and o.inner_max_sweeps == 1 and o.sort == 1
+    w64 = jx.jacobi_eig_workspace(4096)
+    # upper block triangle (65 MiB) + Q + three refinement buffers
+    assert w64 > 4096 * 4096 * 8 * 4
+    assert jx.jacobi_eig_workspace(4096, jx.opts_default(want_vectors=0, refine=0)) < 80 * 2 ** 20
+    assert jx.jacobi_eig_workspace(100) > 0
+    assert jx.jacobi_eig_workspace(64, jx.opts_default(block=48)) == 0  # unsupported block
+
+
+def test_argument_errors_return_before_any_device_work():
+    jx = _jx()
+    L = jx.lib()
+    info = jx.Info()
+    o = jx.opts_default()
+    assert L.jacobi_eig(-1, None, 1, b"U", None, None, 1, None, 1, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -1
+    assert info.status == -1
+    assert L.jacobi_eig(4, ctypes.c_void_p(16), 2, b"U", None, None, 4, None, 4, None, 0, ctypes.byref(o), None, None) == -3
+    assert L.jacobi_eig(4, ctypes.c_void_p(16), 4, b"X", None, None, 4, None, 4, None, 0, ctypes.byref(o), None, None) == -4
+    assert L.jacobi_eig(0, None, 1, b"U", None, None, 1, None, 1, None, 0, ctypes.byref(o), None, None) == 0
+    assert "uplo" in jx.last_error() or jx.last_error() == ""
