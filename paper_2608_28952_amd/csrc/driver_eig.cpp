@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -158,6 +160,12 @@ struct EigState {
     int inner;
     double tol;
     int any_force;
+    // second stream for the Q updates, which overlap the next rounds'
+    // subproblem solves (the V_hat / flag buffers are double-buffered)
+    hipStream_t sq = nullptr;
+    hipEvent_t ev_v[2] = {nullptr, nullptr};   // V_hat(r) ready (on s)
+    hipEvent_t ev_q[2] = {nullptr, nullptr};   // Q update of the round using buffer i done (on sq)
+    bool q_pending[2] = {false, false};
     // profiling: skip flags of every round copied to pinned host memory
     int *h_flaglog = nullptr;
     int flog_cap = 0, flog_count = 0, flog_base = 0;
@@ -196,6 +204,11 @@ struct EigState {
             a.skip_thr = skip_thr;
             a.inner_sweeps = inner;
             a.force_skip = any_force ? force + (size_t)r * p.H : nullptr;
+            const int buf = r & 1;
+            if (sq && q_pending[buf]) {  // the Q update still reading this buffer
+                JX_HIP(hipStreamWaitEvent(s, ev_q[buf], 0));
+                q_pending[buf] = false;
+            }
             {
                 ProfScope ps(PROF_SUBPROBLEM, s, k1_flops, k1_bytes);
                 launch_subproblem(a, s);
@@ -212,10 +225,45 @@ struct EigState {
                 launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tiles, ntiles, s);
             }
             if (p.vectors) {
-                ProfScope ps(PROF_UPDATE_Q, s, (double)p.npad, 0.0, slot, p.H, m2);
-                launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), s);
+                hipStream_t qs = s;
+                if (sq) {
+                    JX_HIP(hipEventRecord(ev_v[buf], s));
+                    JX_HIP(hipStreamWaitEvent(sq, ev_v[buf], 0));
+                    qs = sq;
+                }
+                {
+                    ProfScope ps(PROF_UPDATE_Q, qs, (double)p.npad, 0.0, slot, p.H, m2);
+                    launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs);
+                }
+                if (sq) {
+                    JX_HIP(hipEventRecord(ev_q[buf], sq));
+                    q_pending[buf] = true;
+                }
             }
         }
+        // Q complete before anyone reads it (the refinement, the output)
+        for (int i = 0; i < 2; ++i)
+            if (sq && q_pending[i]) {
+                JX_HIP(hipStreamWaitEvent(s, ev_q[i], 0));
+                q_pending[i] = false;
+            }
+    }
+
+    void make_streams() {
+        if (!p.vectors) return;
+        JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            JX_HIP(hipEventCreateWithFlags(&ev_v[i], hipEventDisableTiming));
+            JX_HIP(hipEventCreateWithFlags(&ev_q[i], hipEventDisableTiming));
+        }
+    }
+    ~EigState() {
+        if (sq) (void)hipStreamSynchronize(sq);
+        for (int i = 0; i < 2; ++i) {
+            if (ev_v[i]) (void)hipEventDestroy(ev_v[i]);
+            if (ev_q[i]) (void)hipEventDestroy(ev_q[i]);
+        }
+        if (sq) (void)hipStreamDestroy(sq);
     }
 };
 
@@ -258,6 +306,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     st.h_scal = pin.ptr;
     st.inner = o.inner_max_sweeps;
     st.tol = o.tol;
+    st.make_streams();
     struct PinnedInts {
         int *ptr = nullptr;
         ~PinnedInts() { if (ptr) (void)hipHostFree(ptr); }
@@ -314,8 +363,12 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     if (!finite(off2) || !finite(dia2)) status = 2;
     const double skip_thr = o.tol * fro0 * std::sqrt(2.0 / ((double)p.N * (p.N - 1)));
     int sweeps = 0;
+    const bool verbose = std::getenv("JACOBI_VERBOSE") != nullptr;
     auto converge = [&](int cap) -> int {
         for (;;) {
+            if (verbose)
+                std::fprintf(stderr, "[jacobi_eig] sweep %d off/||A||_F = %.3e\n", sweeps,
+                             fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0);
             if (!finite(off2) || !finite(dia2)) return 2;
             if (std::sqrt(off2) <= o.tol * fro0) return 0;
             if (sweeps >= cap) return 1;
