@@ -843,3 +843,47 @@ int ora_cayley_inverse(int n, const double *W, double *S)
     free(B);
     return rc;
 }
+
+/*
+ * Sampled SVD checks for orders where the full products are too slow: for
+ * each listed column c, out[0] = max_c ||G v_c - s_c u_c||_2 / ||G||_F; for all
+ * listed pairs, out[1] = max |v_c^T v_d - delta_cd| and out[2] = max
+ * |u_c^T u_d - delta_cd| (columns with s > 0 only).  Long double.
+ */
+void ora_check_svd_sampled(int m, int n, const double *G, int ldg, const double *S, const double *U,
+                           int ldu, const double *V, int ldv, int ncols, const int *cols, double *out)
+{
+    long double nG = 0.0L;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i) nG += (long double)G[IDX(i, j, ldg)] * G[IDX(i, j, ldg)];
+    nG = sqrtl(nG);
+    double wr = 0.0, wv = 0.0, wu = 0.0;
+#pragma omp parallel for reduction(max : wr) schedule(dynamic, 1)
+    for (int t = 0; t < ncols; ++t) {
+        int c = cols[t];
+        long double r2 = 0.0L;
+        for (int i = 0; i < m; ++i) {
+            long double s = 0.0L;
+            for (int k = 0; k < n; ++k) s += (long double)G[IDX(i, k, ldg)] * V[IDX(k, c, ldv)];
+            s -= (long double)S[c] * U[IDX(i, c, ldu)];
+            r2 += s * s;
+        }
+        double r = (double)(sqrtl(r2) / (nG > 0 ? nG : 1.0L));
+        if (r > wr) wr = r;
+    }
+#pragma omp parallel for reduction(max : wv, wu) schedule(dynamic, 1)
+    for (int t = 0; t < ncols; ++t)
+        for (int q = 0; q < ncols; ++q) {
+            int c = cols[t], d = cols[q];
+            long double sv = 0.0L, su = 0.0L;
+            for (int k = 0; k < n; ++k) sv += (long double)V[IDX(k, c, ldv)] * V[IDX(k, d, ldv)];
+            for (int k = 0; k < m; ++k) su += (long double)U[IDX(k, c, ldu)] * U[IDX(k, d, ldu)];
+            if (c == d) { sv -= 1.0L; su -= 1.0L; }
+            double dv = (double)fabsl(sv), du = (double)fabsl(su);
+            if (dv > wv) wv = dv;
+            if (S[c] > 0.0 && S[d] > 0.0 && du > wu) wu = du;
+        }
+    out[0] = wr;
+    out[1] = wv;
+    out[2] = wu;
+}

@@ -212,3 +212,23 @@ def cayley_inverse(W):
     rc = lib().ora_cayley_inverse(n, _p(W), _p(S))
     assert rc == 0
     return S
+
+
+def check_svd_sampled(G, S, U, V, cols):
+    """Long double, sampled columns: (max ||G v_c - s_c u_c|| / ||G||_F,
+    max |V^T V - I| entry, max |U^T U - I| entry over the samples)."""
+    L = lib()
+    if not hasattr(L, "_svd_sampled_set"):
+        L.ora_check_svd_sampled.restype = None
+        L.ora_check_svd_sampled.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                            _dp, ctypes.c_int, ctypes.c_int, _ip, _dp]
+        L._svd_sampled_set = True
+    G = _f64(G)
+    U = _f64(U)
+    V = _f64(V)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    m, n = G.shape
+    out = np.zeros(3)
+    L.ora_check_svd_sampled(m, n, _p(G), m, _p(S), _p(U), m, _p(V), n, len(c), c.ctypes.data_as(_ip), _p(out))
+    return out

@@ -21,7 +21,7 @@ static jacobi_opts resolve(const jacobi_opts *o) {
     jacobi_opts r;
     jacobi_opts_default(&r);
     if (o) r = *o;
-    if (!(r.tol > 0.0)) r.tol = 1e-14;
+    if (!(r.tol > 0.0)) r.tol = 0.0;  // per-routine default
     if (r.max_sweeps <= 0) r.max_sweeps = 60;
     return r;
 }
@@ -45,7 +45,7 @@ extern "C" {
 
 int jacobi_opts_default(jacobi_opts *o) {
     if (!o) return -1;
-    o->tol = 1e-14;
+    o->tol = 0.0;
     o->max_sweeps = 60;
     o->block = 0;
     o->ordering = JACOBI_ORDER_ROUND_ROBIN;
@@ -110,6 +110,48 @@ int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *
         }
         const int rc = run_eig(n, dA, lda, uplo, dW, o.want_vectors ? dQ : nullptr, ldq, o.want_vectors ? dQ0 : nullptr,
                                ldq0, dWork, workBytes, o, info, s);
+        if (rc == -100) set_error("workspace too small");
+        if (info) info->status = rc;
+        return rc;
+    });
+}
+
+size_t jacobi_svd_workspace(int m, int n, const jacobi_opts *o) {
+    if (n <= 0 || m < n) return 256;
+    jacobi_opts r = resolve(o);
+    if (r.block != 0 && r.block != 32 && r.block != 64) return 0;
+    return plan_svd(m, n, r).total;
+}
+
+int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int ldu, double *dV, int ldv,
+               void *dWork, size_t workBytes, const jacobi_opts *opts, jacobi_info *info, jacobi_stream_t stream) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    jacobi_opts o = resolve(opts);
+    if (info) *info = jacobi_info{};
+    auto fail = [&](int code, const char *msg) {
+        set_error(msg);
+        if (info) info->status = code;
+        return code;
+    };
+    if (n < 0) return fail(-2, "n < 0");
+    if (m < n) return fail(-1, "m < n");
+    if (n > 0 && !dG) return fail(-3, "dG is NULL");
+    if (ldg < (m > 1 ? m : 1)) return fail(-4, "ldg < m");
+    if (n > 0 && !dS) return fail(-5, "dS is NULL");
+    if (o.want_vectors && n > 0 && (!dU || !dV)) return fail(-6, "dU / dV NULL but vectors were requested");
+    if (o.want_vectors && ldu < (m > 1 ? m : 1)) return fail(-7, "ldu < m");
+    if (o.want_vectors && ldv < (n > 1 ? n : 1)) return fail(-9, "ldv < n");
+    if (o.block != 0 && o.block != 32 && o.block != 64) return fail(-12, "opts->block must be 0, 32 or 64");
+    if (o.ordering != JACOBI_ORDER_ROUND_ROBIN && o.ordering != JACOBI_ORDER_ANTIDIAG)
+        return fail(-12, "opts->ordering invalid");
+    if (o.precision < 0 || o.precision > 2) return fail(-12, "opts->precision invalid");
+    if (n == 0) {
+        if (info) info->status = 0;
+        return 0;
+    }
+    return guarded(info, [&]() -> int {
+        const int rc = run_svd(m, n, dG, ldg, dS, o.want_vectors ? dU : nullptr, ldu, o.want_vectors ? dV : nullptr,
+                               ldv, dWork, workBytes, o, info, s);
         if (rc == -100) set_error("workspace too small");
         if (info) info->status = rc;
         return rc;

@@ -105,6 +105,10 @@ static void padded_rounds(int N, int ordering, std::vector<int> &pairs, std::vec
     }
 }
 
+void padded_rounds_pub(int N, int ordering, std::vector<int> &pairs, std::vector<int> &force) {
+    padded_rounds(N, ordering, pairs, force);
+}
+
 // ---------------------------------------------------------------------------
 // Plan and workspace
 // ---------------------------------------------------------------------------
@@ -305,7 +309,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     st.scal = reinterpret_cast<double *>(ws + p.off_scal);
     st.h_scal = pin.ptr;
     st.inner = o.inner_max_sweeps;
-    st.tol = o.tol;
+    st.tol = o.tol > 0.0 ? o.tol : 1e-14;
     st.make_streams();
     struct PinnedInts {
         int *ptr = nullptr;
@@ -361,7 +365,8 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     const double fro0 = std::sqrt(off2 + dia2);
     int status = 1;
     if (!finite(off2) || !finite(dia2)) status = 2;
-    const double skip_thr = o.tol * fro0 * std::sqrt(2.0 / ((double)p.N * (p.N - 1)));
+    const double tol = o.tol > 0.0 ? o.tol : 1e-14;
+    const double skip_thr = tol * fro0 * std::sqrt(2.0 / ((double)p.N * (p.N - 1)));
     int sweeps = 0;
     const bool verbose = std::getenv("JACOBI_VERBOSE") != nullptr;
     auto converge = [&](int cap) -> int {
@@ -370,7 +375,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
                 std::fprintf(stderr, "[jacobi_eig] sweep %d off/||A||_F = %.3e\n", sweeps,
                              fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0);
             if (!finite(off2) || !finite(dia2)) return 2;
-            if (std::sqrt(off2) <= o.tol * fro0) return 0;
+            if (std::sqrt(off2) <= tol * fro0) return 0;
             if (sweeps >= cap) return 1;
             st.sweep(skip_thr);
             ++sweeps;

@@ -99,6 +99,7 @@ struct SubArgs {
     int inner_sweeps;       // 0 = to inner convergence (cap 30)
     double *inner_off;      // optional per-pair |off(A_hat)| before the solve
     const int *force_skip;  // optional per pair: 1 = placeholder pair, never rotated
+    int *rot_count;         // optional: +1 per pair that is rotated (not skipped)
 };
 void launch_subproblem(const SubArgs &a, hipStream_t s);
 
@@ -106,6 +107,14 @@ void launch_subproblem(const SubArgs &a, hipStream_t s);
 // A[p,q] <- V_p^T A[p,q] V_q for p < q (pair indices of the round).
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
                      const int *flags, const int *tiles, int ntiles, hipStream_t s);
+// Gram blocks of the one-sided SVD: ahat[p] = G(:, [I,J])^T G(:, [I,J]) over the
+// first m_rows rows (nchunks equal row chunks, partial sums added in order).
+void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, int m_rows, int nchunks,
+                 double *partial, double *ahat, hipStream_t s);
+void launch_col_norms(int m, int n, const double *G, int ldg, double *sigma, hipStream_t s);
+void launch_scale_scatter(int m, int n, const double *G, int ldg, const double *sigma, const int *rank,
+                          double *U, int ldu, hipStream_t s);
+
 // One-sided update Q(:, [I,J]) <- Q(:, [I,J]) V_p for every pair p and every
 // 128-row chunk of Q (n_rows multiple of 128).
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,

@@ -55,7 +55,18 @@ struct EigPlan {
     size_t total;
 };
 
+struct SvdPlan {
+    int m, n, mpad, npad, b, N, H, R, nchunks;
+    bool vectors, refine;
+    size_t off_g, off_v, off_vhat, off_flags, off_pairs, off_force, off_partial, off_ahat, off_meas,
+        off_cnt, off_sigma, off_rank, off_g0, off_t1, off_t2;
+    size_t total;
+};
+
 EigPlan plan_eig(int n, const jacobi_opts &o);
+SvdPlan plan_svd(int m, int n, const jacobi_opts &o);
+int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int ldu, double *dV, int ldv,
+            void *dWork, size_t workBytes, const jacobi_opts &o, jacobi_info *info, hipStream_t s);
 int make_schedule(int N, int ordering, std::vector<int> &pairs, std::vector<int> &sizes);
 int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq,
             const double *dQ0, int ldq0, void *dWork, size_t workBytes, const jacobi_opts &o,

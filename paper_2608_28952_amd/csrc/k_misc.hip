@@ -316,3 +316,20 @@ void launch_write_pair_blocks(int count, int b, const int *pairs, const double *
 }
 
 }  // namespace jx
+
+namespace jx {
+namespace {
+// dst (mpad x npad) = src (m x n) with zero padding.
+__global__ void k_copy_rect(int m, int n, const double *__restrict__ src, int lds_, double *__restrict__ dst,
+                            int ldd, int mpad) {
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < mpad; i += gridDim.x * blockDim.x)
+        dst[(size_t)j * ldd + i] = (i < m && j < n) ? src[(size_t)j * lds_ + i] : 0.0;
+}
+}  // namespace
+void launch_copy_rect(int m, int n, const double *src, int lds_, double *dst, int ldd, int mpad, int npad,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_rect, dim3((mpad + 255) / 256, npad), dim3(256), 0, s, m, n, src, lds_, dst, ldd, mpad);
+    JX_LAUNCHED();
+}
+}  // namespace jx

@@ -173,10 +173,33 @@ __global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
     fro2 = block_sum<NT>(fro2, red);
 
     if (MODE != SUB_PLAIN) {
-        const double off = sqrt(off2);
-        if (tid == 0 && a.inner_off) a.inner_off[pr] = off;
-        const bool skip = !(off > a.skip_thr);
+        // eigenproblem: skip when off(A_hat) is small; Gram block of the SVD:
+        // skip when every column pair is nearly orthogonal,
+        // max |a_ij| / sqrt(a_ii a_jj) <= skip_thr (zero columns count as orthogonal)
+        double meas = sqrt(off2);
+        if (MODE == SUB_GRAM) {
+            __syncthreads();
+            double mx = 0.0;
+            for (int e = tid; e < M2 * M2; e += NT) {
+                const int rr = e % M2, cc = e / M2;
+                if (rr >= cc) continue;
+                const int u = slot_of(rr, M2), w = slot_of(cc, M2);
+                const double dd = As[u * (LD + 1)] * As[w * (LD + 1)];
+                const double v = As[min(u, w) * LD + max(u, w)];
+                if (dd > 0.0) mx = fmax(mx, fabs(v) / sqrt(dd));
+            }
+            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            __syncthreads();
+            if ((tid & 63) == 0) red[tid >> 6] = mx;
+            __syncthreads();
+            mx = 0.0;
+            for (int i = 0; i < NT / 64; ++i) mx = fmax(mx, red[i]);
+            meas = mx;
+        }
+        if (tid == 0 && a.inner_off) a.inner_off[pr] = meas;
+        const bool skip = !(meas > a.skip_thr);
         if (tid == 0 && a.flags) a.flags[pr] = skip ? 1 : 0;
+        if (tid == 0 && a.rot_count && !skip) atomicAdd(a.rot_count, 1);
         if (skip) return;  // V_hat = I, A_hat unchanged
     }
 

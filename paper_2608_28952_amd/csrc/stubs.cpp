@@ -4,15 +4,7 @@
 
 extern "C" {
 
-size_t jacobi_svd_workspace(int, int, const jacobi_opts *) { return 0; }
 size_t jacobi_eig_batched_workspace(int, const int *, int, const jacobi_opts *) { return 0; }
-
-int jacobi_svd(int, int, const double *, int, double *, double *, int, double *, int, void *, size_t,
-               const jacobi_opts *, jacobi_info *info, jacobi_stream_t) {
-    jx::set_error("jacobi_svd: not available in this build");
-    if (info) info->status = 3;
-    return 3;
-}
 
 int jacobi_eig_batched(int, const int *, const int64_t *, int, const void *, double *, double *,
                        const double *, void *, size_t, const jacobi_opts *, jacobi_info *info,

@@ -67,7 +67,7 @@ def test_schedule_rejects_odd_and_small():
 def test_opts_defaults_and_workspace():
     jx = _jx()
     o = jx.opts_default()
-    assert o.tol == 1e-14 and o.max_sweeps == 60 and o.inner_max_sweeps == 1 and o.sort == 1
+    assert o.tol == 0.0 and o.max_sweeps == 60 and o.inner_max_sweeps == 1 and o.sort == 1
     w64 = jx.jacobi_eig_workspace(4096)
     # upper block triangle (65 MiB) + Q + three refinement buffers
     assert w64 > 4096 * 4096 * 8 * 4
