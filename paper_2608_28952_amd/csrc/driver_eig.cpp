@@ -125,13 +125,21 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     p.H = p.N / 2;
     p.R = (o.ordering == JACOBI_ORDER_ANTIDIAG) ? p.N : p.N - 1;
     p.vectors = o.want_vectors != 0;
-    const bool mixed = o.precision != JACOBI_PREC_FP64;
-    p.refine = p.vectors && (o.refine == 1 || (o.refine < 0 && (n >= 256 || mixed)));
+    p.mixed = o.precision != JACOBI_PREC_FP64;
+    // the mixed ladder always ends with the FP64 recomputation from the
+    // original matrix, which needs Q even for eigenvalues only
+    p.refine = p.mixed || (p.vectors && (o.refine == 1 || (o.refine < 0 && n >= 256)));
+    p.need_q = p.vectors || p.mixed;
     const size_t npad = p.npad, nb = (size_t)p.N * (p.N + 1) / 2;
     const size_t m2sq = (size_t)(2 * p.b) * (2 * p.b);
     WorkspaceBuilder wb;
     p.off_ablk = wb.add(sizeof(double) * nb * p.b * p.b);
-    p.off_q = p.vectors ? wb.add(sizeof(double) * npad * npad) : 0;
+    p.off_q = p.need_q ? wb.add(sizeof(double) * npad * npad) : 0;
+    if (p.mixed) {
+        p.off_ablk32 = wb.add(sizeof(float) * nb * p.b * p.b);
+        p.off_q32 = wb.add(sizeof(float) * npad * npad);
+        p.off_v32 = wb.add(sizeof(float) * 2 * p.H * m2sq);
+    }
     p.off_v = wb.add(sizeof(double) * 2 * p.H * m2sq);
     p.off_flags = wb.add(sizeof(int) * 2 * p.H);
     p.off_pairs = wb.add(sizeof(int) * 2 * (size_t)p.R * p.H);
@@ -160,6 +168,8 @@ struct EigState {
     hipStream_t s;
     double *ablk, *Q, *V, *partial, *scal;
     int *flags, *pairs, *force, *tiles;
+    float *ablk32 = nullptr, *Q32 = nullptr, *V32 = nullptr;
+    bool f32 = false;  // current phase works on the FP32 copies
     double *h_scal;  // pinned
     int inner;
     double tol;
@@ -175,11 +185,13 @@ struct EigState {
     int flog_cap = 0, flog_count = 0, flog_base = 0;
 
     double *Vbuf(int r) const { return V + (size_t)(r & 1) * p.H * (2 * p.b) * (2 * p.b); }
+    float *Vbuf32(int r) const { return V32 + (size_t)(r & 1) * p.H * (2 * p.b) * (2 * p.b); }
     int *Fbuf(int r) const { return flags + (size_t)(r & 1) * p.H; }
 
     // {Xi(A)^2, sum of squared diagonal}
     void norms(double &off2, double &dia2) {
-        launch_block_norms(p.npad, p.b, ablk, partial, scal, s);
+        if (f32) launch_block_norms32(p.npad, p.b, ablk32, partial, scal, s);
+        else launch_block_norms(p.npad, p.b, ablk, partial, scal, s);
         JX_HIP(hipMemcpyAsync(h_scal, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         JX_HIP(hipStreamSynchronize(s));
         off2 = h_scal[0];
@@ -208,6 +220,10 @@ struct EigState {
             a.skip_thr = skip_thr;
             a.inner_sweeps = inner;
             a.force_skip = any_force ? force + (size_t)r * p.H : nullptr;
+            if (f32) {
+                a.ablk32 = ablk32;
+                a.vout32 = Vbuf32(r);
+            }
             const int buf = r & 1;
             if (sq && q_pending[buf]) {  // the Q update still reading this buffer
                 JX_HIP(hipStreamWaitEvent(s, ev_q[buf], 0));
@@ -226,9 +242,10 @@ struct EigState {
             }
             {
                 ProfScope ps(PROF_UPDATE_A, s, 0.0, 0.0, slot, p.H, m2);
-                launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tiles, ntiles, s);
+                if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tiles, ntiles, s);
+                else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tiles, ntiles, s);
             }
-            if (p.vectors) {
+            if (p.need_q) {
                 hipStream_t qs = s;
                 if (sq) {
                     JX_HIP(hipEventRecord(ev_v[buf], s));
@@ -237,7 +254,8 @@ struct EigState {
                 }
                 {
                     ProfScope ps(PROF_UPDATE_Q, qs, (double)p.npad, 0.0, slot, p.H, m2);
-                    launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs);
+                    if (f32) launch_update_q32(p.b, p.H, pr, Q32, p.npad, p.npad, Vbuf32(r), Fbuf(r), qs);
+                    else launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs);
                 }
                 if (sq) {
                     JX_HIP(hipEventRecord(ev_q[buf], sq));
@@ -254,7 +272,7 @@ struct EigState {
     }
 
     void make_streams() {
-        if (!p.vectors) return;
+        if (!p.need_q) return;
         JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
         for (int i = 0; i < 2; ++i) {
             JX_HIP(hipEventCreateWithFlags(&ev_v[i], hipEventDisableTiming));
@@ -299,7 +317,12 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
 
     EigState st{p, ws, s};
     st.ablk = reinterpret_cast<double *>(ws + p.off_ablk);
-    st.Q = p.vectors ? reinterpret_cast<double *>(ws + p.off_q) : nullptr;
+    st.Q = p.need_q ? reinterpret_cast<double *>(ws + p.off_q) : nullptr;
+    if (p.mixed) {
+        st.ablk32 = reinterpret_cast<float *>(ws + p.off_ablk32);
+        st.Q32 = reinterpret_cast<float *>(ws + p.off_q32);
+        st.V32 = reinterpret_cast<float *>(ws + p.off_v32);
+    }
     st.V = reinterpret_cast<double *>(ws + p.off_v);
     st.flags = reinterpret_cast<int *>(ws + p.off_flags);
     st.pairs = reinterpret_cast<int *>(ws + p.off_pairs);
@@ -340,7 +363,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     double *T1 = p.refine ? reinterpret_cast<double *>(ws + p.off_t1) : nullptr;
     double *T2 = p.refine ? reinterpret_cast<double *>(ws + p.off_t2) : nullptr;
     if (p.refine) launch_full_from_triangle(n, p.npad, dA, lda, uplo, A0, s);
-    if (dQ0 && p.vectors) {
+    if (dQ0 && p.need_q) {
         launch_copy_pad(n, p.npad, dQ0, ldq0, st.Q, p.npad, s);
         double *F = A0, *T = T1, *A1 = T2;
         DeviceBuffer tmp;
@@ -357,7 +380,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
         JX_HIP(hipStreamSynchronize(s));
     } else {
         launch_pack_sym(n, p.npad, p.b, dA, lda, uplo, st.ablk, s);
-        if (p.vectors) launch_set_identity(p.npad, p.npad, st.Q, p.npad, s);
+        if (p.need_q) launch_set_identity(p.npad, p.npad, st.Q, p.npad, s);
     }
 
     double off2, dia2;
@@ -367,26 +390,33 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     if (!finite(off2) || !finite(dia2)) status = 2;
     const double tol = o.tol > 0.0 ? o.tol : 1e-14;
     const double skip_thr = tol * fro0 * std::sqrt(2.0 / ((double)p.N * (p.N - 1)));
-    int sweeps = 0;
+    int sweeps = 0, sweeps32 = 0;
     const bool verbose = std::getenv("JACOBI_VERBOSE") != nullptr;
-    auto converge = [&](int cap) -> int {
+    // Sweeps until Xi(A) <= stop * ||A||_F.  Returns 0 (reached), 1 (cap),
+    // 2 (non-finite), 4 (FP32 phase stagnates: less than 2x decrease per sweep).
+    auto phase = [&](double stop, int cap) -> int {
+        double prev = -1.0;
         for (;;) {
             if (verbose)
-                std::fprintf(stderr, "[jacobi_eig] sweep %d off/||A||_F = %.3e\n", sweeps,
+                std::fprintf(stderr, "[jacobi_eig] sweep %d %s off/||A||_F = %.3e\n", sweeps, st.f32 ? "fp32" : "fp64",
                              fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0);
             if (!finite(off2) || !finite(dia2)) return 2;
-            if (std::sqrt(off2) <= tol * fro0) return 0;
+            const double rel = fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0;
+            if (rel <= stop) return 0;
+            // FP32 floor: past the linear phase a sweep should at least halve the off-norm
+            if (st.f32 && prev >= 0.0 && rel < 1e-3 && rel > 0.5 * prev) return 4;
             if (sweeps >= cap) return 1;
+            prev = rel;
             st.sweep(skip_thr);
             ++sweeps;
+            if (st.f32) ++sweeps32;
             st.norms(off2, dia2);
         }
     };
-    if (status != 2) status = converge(o.max_sweeps);
-
-    // orthogonality refinement: Q <- Q (3 I - Q^T Q) / 2, A1 = Q^T A0 Q in FP64,
-    // then sweeps to tol from A1 (whose rotations are tiny)
-    if (status == 0 && p.refine) {
+    // Orthogonality refinement and recomputation from the original matrix:
+    // Q <- Q (3 I - Q^T Q) / 2, A1 = Q^T A0 Q in FP64, A1 -> block storage.
+    const double switch_rel = 1e-5;
+    auto recompute = [&]() {
         const int np = p.npad;
         gemm_p('T', 'N', np, np, np, 1.0, st.Q, np, st.Q, np, 0.0, T1, np, s);    // M = Q^T Q
         JX_HIP(hipMemcpyAsync(T2, st.Q, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
@@ -396,7 +426,31 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
         gemm_p('T', 'N', np, np, np, 1.0, st.Q, np, T1, np, 0.0, T2, np, s);      // Q^T A0 Q
         launch_pack_sym(np, np, p.b, T2, np, 'U', st.ablk, s);
         st.norms(off2, dia2);
-        status = converge(o.max_sweeps + 4);
+    };
+    if (status != 2) {
+        if (p.mixed) {
+            // FP32 sweeps (subproblems still solved in FP64) to off <= 1e-5 or stagnation
+            const size_t nab = (size_t)p.N * (p.N + 1) / 2 * p.b * p.b;
+            launch_cast_to_f32(nab, st.ablk, st.ablk32, s);
+            launch_cast_to_f32((size_t)p.npad * p.npad, st.Q, st.Q32, s);
+            st.f32 = true;
+            st.norms(off2, dia2);
+            status = phase(switch_rel, o.max_sweeps);
+            st.f32 = false;
+            if (status != 2) {
+                launch_cast_to_f64((size_t)p.npad * p.npad, st.Q32, st.Q, s);
+                recompute();
+                status = phase(tol, o.max_sweeps + 8);
+            }
+        } else {
+            status = phase(tol, o.max_sweeps);
+        }
+        // final orthogonality refinement: the sweeps after it rotate by angles of
+        // the size of Q's orthogonality error and mostly skip
+        if (status == 0 && p.refine) {
+            recompute();
+            status = phase(tol, o.max_sweeps + 12);
+        }
     }
 
     // eigenvalues (first n diagonal entries), sorted; Q columns permuted alike
@@ -421,7 +475,8 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     }
     inf.status = status;
     inf.sweeps = sweeps;
-    inf.sweeps_by_prec[2] = sweeps;
+    inf.sweeps_by_prec[1] = sweeps32;
+    inf.sweeps_by_prec[2] = sweeps - sweeps32;
     inf.off_rel = fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;

@@ -43,7 +43,8 @@ SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
     p.H = p.N / 2;
     p.R = (o.ordering == JACOBI_ORDER_ANTIDIAG) ? p.N : p.N - 1;
     p.vectors = o.want_vectors != 0;
-    p.refine = o.refine == 1 || (o.refine < 0 && (n >= 256 || o.precision != JACOBI_PREC_FP64));
+    p.mixed = o.precision != JACOBI_PREC_FP64;
+    p.refine = p.mixed || o.refine == 1 || (o.refine < 0 && n >= 256);
     const size_t m2sq = (size_t)(2 * p.b) * (2 * p.b);
     WorkspaceBuilder wb;
     p.off_g = wb.add(sizeof(double) * (size_t)p.mpad * p.npad);
@@ -58,6 +59,11 @@ SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
     p.off_cnt = wb.add(sizeof(int) * 4);
     p.off_sigma = wb.add(sizeof(double) * p.npad);
     p.off_rank = wb.add(sizeof(int) * p.npad);
+    if (p.mixed) {
+        p.off_g32 = wb.add(sizeof(float) * (size_t)p.mpad * p.npad);
+        p.off_v32 = wb.add(sizeof(float) * (size_t)p.npad * p.npad);
+        p.off_vhat32 = wb.add(sizeof(float) * p.H * m2sq);
+    }
     if (p.refine) {
         p.off_g0 = wb.add(sizeof(double) * (size_t)p.mpad * p.npad);
         p.off_t1 = wb.add(sizeof(double) * (size_t)p.npad * p.npad);
@@ -120,7 +126,11 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
     std::vector<double> hmeas((size_t)p.R * p.H);
     const bool verbose = std::getenv("JACOBI_VERBOSE") != nullptr;
 
-    int sweeps = 0, status = 1;
+    float *G32 = p.mixed ? reinterpret_cast<float *>(ws + p.off_g32) : nullptr;
+    float *V32 = p.mixed ? reinterpret_cast<float *>(ws + p.off_v32) : nullptr;
+    float *Vh32 = p.mixed ? reinterpret_cast<float *>(ws + p.off_vhat32) : nullptr;
+    bool f32 = false;
+    int sweeps = 0, sweeps32 = 0, status = 1;
     double last_meas = 0.0;
     auto sweep_once = [&]() -> int {  // returns rotated pair count
         JX_HIP(hipMemsetAsync(cnt, 0, sizeof(int), s));
@@ -128,8 +138,11 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
             const int *pr = pairs + (size_t)2 * r * p.H;
             {
                 ProfScope ps(PROF_GRAM, s, (double)p.H * 2.0 * p.mpad * m2 * m2,
-                             (double)p.H * p.mpad * m2 * sizeof(double));
-                launch_gram(p.b, p.H, pr, G, p.mpad, p.mpad, p.nchunks, partial, ahat, s);
+                             (double)p.H * p.mpad * m2 * (f32 ? sizeof(float) : sizeof(double)));
+                if (f32)
+                    launch_gram32(p.b, p.H, pr, G32, p.mpad, p.mpad, p.nchunks, reinterpret_cast<float *>(partial),
+                                  ahat, s);
+                else launch_gram(p.b, p.H, pr, G, p.mpad, p.mpad, p.nchunks, partial, ahat, s);
             }
             SubArgs a{};
             a.mode = SUB_GRAM;
@@ -144,15 +157,21 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
             a.inner_off = meas + (size_t)r * p.H;
             a.force_skip = any_force ? force + (size_t)r * p.H : nullptr;
             a.rot_count = cnt;
+            if (f32) a.vout32 = Vh32;
             {
                 ProfScope ps(PROF_SUBPROBLEM, s, 0.0, 0.0);
                 launch_subproblem(a, s);
             }
             {
                 ProfScope ps(PROF_UPDATE_Q, s, (double)p.H * 2.0 * (p.mpad + p.npad) * m2 * m2,
-                             (double)p.H * 2.0 * (p.mpad + p.npad) * m2 * sizeof(double));
-                launch_update_q(p.b, p.H, pr, G, p.mpad, p.mpad, Vh, flags, s);
-                launch_update_q(p.b, p.H, pr, V, p.npad, p.npad, Vh, flags, s);
+                             (double)p.H * 2.0 * (p.mpad + p.npad) * m2 * (f32 ? sizeof(float) : sizeof(double)));
+                if (f32) {
+                    launch_update_q32(p.b, p.H, pr, G32, p.mpad, p.mpad, Vh32, flags, s);
+                    launch_update_q32(p.b, p.H, pr, V32, p.npad, p.npad, Vh32, flags, s);
+                } else {
+                    launch_update_q(p.b, p.H, pr, G, p.mpad, p.mpad, Vh, flags, s);
+                    launch_update_q(p.b, p.H, pr, V, p.npad, p.npad, Vh, flags, s);
+                }
             }
         }
         JX_HIP(hipMemcpyAsync(hcnt.ptr, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -162,30 +181,52 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
         for (size_t i = 0; i < hmeas.size(); ++i)
             if (!any_force || !hf[i]) last_meas = std::max(last_meas, hmeas[i]);
         if (verbose)
-            std::fprintf(stderr, "[jacobi_svd] sweep %d rotated pairs %d max cos %.3e\n", sweeps, hcnt.ptr[0],
-                         last_meas);
+            std::fprintf(stderr, "[jacobi_svd] sweep %d %s rotated pairs %d max cos %.3e\n", sweeps,
+                         f32 ? "fp32" : "fp64", hcnt.ptr[0], last_meas);
         return hcnt.ptr[0];
     };
-    auto converge = [&](int cap) -> int {
+    // Sweeps until a sweep rotates no pair (stop <= 0) or the largest relative
+    // cosine drops to stop.  Returns 0, 1 (cap), 2 (non-finite), 4 (FP32 stagnates).
+    auto phase = [&](double stop, int cap) -> int {
+        double prev = -1.0;
         for (;;) {
             if (sweeps >= cap) return 1;
             const int rot = sweep_once();
             ++sweeps;
+            if (f32) ++sweeps32;
             if (!std::isfinite(last_meas)) return 2;
-            if (rot == 0) return 0;
+            if (rot == 0 || (stop > 0.0 && last_meas <= stop)) return 0;
+            if (f32 && prev >= 0.0 && last_meas < 1e-3 && last_meas > 0.5 * prev) return 4;
+            prev = last_meas;
         }
     };
-    status = converge(o.max_sweeps);
-    if (status == 0 && p.refine) {
-        // V <- V (3 I - V^T V) / 2, G = G0 V in FP64 from the original, then
-        // sweeps to tol again (their rotations are tiny)
+    // V <- V (3 I - V^T V) / 2, G = G0 V in FP64 from the original
+    auto recompute = [&]() {
         const int np = p.npad;
         launch_gemm_f64('T', 'N', np, np, np, 1.0, V, np, V, np, 0.0, T1, np, s);
         JX_HIP(hipMemcpyAsync(T2, V, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
         launch_gemm_f64('N', 'N', np, np, np, -0.5, V, np, T1, np, 1.5, T2, np, s);
         JX_HIP(hipMemcpyAsync(V, T2, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
         launch_gemm_f64('N', 'N', p.mpad, np, np, 1.0, G0, p.mpad, V, np, 0.0, G, p.mpad, s);
-        status = converge(o.max_sweeps + 4);
+    };
+    const double switch_cos = 1e-5;
+    if (p.mixed) {
+        launch_cast_to_f32((size_t)p.mpad * p.npad, G, G32, s);
+        launch_set_identity32(p.npad, V32, p.npad, s);
+        f32 = true;
+        status = phase(switch_cos, o.max_sweeps);
+        f32 = false;
+        if (status != 2) {
+            launch_cast_to_f64((size_t)p.npad * p.npad, V32, V, s);
+            recompute();
+            status = phase(0.0, o.max_sweeps + 8);
+        }
+    } else {
+        status = phase(0.0, o.max_sweeps);
+    }
+    if (status == 0 && p.refine) {
+        recompute();
+        status = phase(0.0, o.max_sweeps + 12);
     }
     if (status != 2) {
         launch_col_norms(m, n, G, p.mpad, sigma, s);
@@ -205,7 +246,8 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
     }
     inf.status = status;
     inf.sweeps = sweeps;
-    inf.sweeps_by_prec[2] = sweeps;
+    inf.sweeps_by_prec[1] = sweeps32;
+    inf.sweeps_by_prec[2] = sweeps - sweeps32;
     inf.off_rel = last_meas;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;

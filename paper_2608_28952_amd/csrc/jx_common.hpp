@@ -68,6 +68,35 @@ __host__ __device__ __forceinline__ int vperm(int k, int i, int m2) {
     return (((k >> 2) * (m2 >> 4) + (i >> 4)) << 6) + ((k & 3) << 4) + (i & 15);
 }
 
+// FP32 counterpart for v_mfma_f32_16x16x4_f32, whose result rows are 4 g + v:
+// the contraction index of a step is k = 16 A + 4 g + s (A: 16-block, g: lane
+// group, s: step 0..3), and the 64 values of step (A, s) are contiguous.
+__host__ __device__ __forceinline__ int vperm32(int k, int i, int m2) {
+    return ((((k >> 4) << 2) + (k & 3)) * (m2 >> 4) + (i >> 4)) * 64 + ((k >> 2) & 3) * 16 + (i & 15);
+}
+
+// Per-type MFMA conventions of the rotation-apply kernels.
+template <class T>
+struct MfmaTraits;
+template <>
+struct MfmaTraits<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ d4 mma(double a, double b, d4 c) { return mfma_f64(a, b, c); }
+    // contraction index of step st (0..3 within a 16-block) for lane group g
+    static __host__ __device__ __forceinline__ int kstep(int st, int g) { return 4 * st + g; }
+    // result row of component v in lane group g (within a 16-row tile)
+    static __host__ __device__ __forceinline__ int rrow(int g, int v) { return g + 4 * v; }
+    static __host__ __device__ __forceinline__ int vidx(int k, int i, int m2) { return vperm(k, i, m2); }
+};
+template <>
+struct MfmaTraits<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ f4 mma(float a, float b, f4 c) { return mfma_f32(a, b, c); }
+    static __host__ __device__ __forceinline__ int kstep(int st, int g) { return 4 * g + st; }
+    static __host__ __device__ __forceinline__ int rrow(int g, int v) { return 4 * g + v; }
+    static __host__ __device__ __forceinline__ int vidx(int k, int i, int m2) { return vperm32(k, i, m2); }
+};
+
 // Upper block-triangle storage of the symmetric iterate: block (I, J), I <= J,
 // of order b, column-major, at block slot J (J + 1) / 2 + I.
 __host__ __device__ __forceinline__ size_t ublk(int I, int J) {
@@ -100,6 +129,8 @@ struct SubArgs {
     double *inner_off;      // optional per-pair |off(A_hat)| before the solve
     const int *force_skip;  // optional per pair: 1 = placeholder pair, never rotated
     int *rot_count;         // optional: +1 per pair that is rotated (not skipped)
+    float *ablk32;          // SUB_EIG with FP32 storage of A (instead of ablk)
+    float *vout32;          // V_hat written in FP32, vperm32 order (instead of vout)
 };
 void launch_subproblem(const SubArgs &a, hipStream_t s);
 
@@ -111,6 +142,8 @@ void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const do
 // first m_rows rows (nchunks equal row chunks, partial sums added in order).
 void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, int m_rows, int nchunks,
                  double *partial, double *ahat, hipStream_t s);
+void launch_gram32(int b, int npairs, const int *pairs, const float *G, int ldg, int m_rows, int nchunks,
+                   float *partial, double *ahat, hipStream_t s);
 void launch_col_norms(int m, int n, const double *G, int ldg, double *sigma, hipStream_t s);
 void launch_scale_scatter(int m, int n, const double *G, int ldg, const double *sigma, const int *rank,
                           double *U, int ldu, hipStream_t s);
@@ -119,6 +152,11 @@ void launch_scale_scatter(int m, int n, const double *G, int ldg, const double *
 // 128-row chunk of Q (n_rows multiple of 128).
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s);
+// FP32 versions (FP32 storage, FP32 MFMA with FP32 accumulation, V_hat in vperm32 order).
+void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
+                       const int *tiles, int ntiles, hipStream_t s);
+void launch_update_q32(int b, int npairs, const int *pairs, float *Q, int ldq, int n_rows, const float *vhat,
+                       const int *flags, hipStream_t s);
 
 // Layout conversion and reductions.
 void launch_pack_sym(int n, int npad, int b, const double *A, int lda, char uplo, double *ablk,
@@ -141,6 +179,12 @@ void launch_scatter_values(int n, const double *w, const int *rank, double *out,
 // out(:, rank[i]) = src(:, i) for the first `rows` rows of n columns.
 void launch_scatter_columns(int rows, int n, const double *src, int lds_, const int *rank,
                             double *out, int ldo, hipStream_t s);
+
+// Precision ladder helpers.
+void launch_cast_to_f32(size_t count, const double *src, float *dst, hipStream_t s);
+void launch_cast_to_f64(size_t count, const float *src, double *dst, hipStream_t s);
+void launch_set_identity32(int npad, float *Q, int ldq, hipStream_t s);
+void launch_block_norms32(int npad, int b, const float *ablk, double *partial, double *out, hipStream_t s);
 
 // Test helpers: column-major V_hat -> vperm order; D_hat -> pair blocks.
 void launch_vperm_from_colmajor(int count, int m2, const double *src, double *dst, hipStream_t s);

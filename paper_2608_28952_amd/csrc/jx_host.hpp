@@ -49,17 +49,17 @@ struct PinnedScalars {
 
 struct EigPlan {
     int n, npad, b, N, H, R;
-    bool vectors, refine;
+    bool vectors, refine, mixed, need_q;
     size_t off_ablk, off_q, off_v, off_flags, off_pairs, off_force, off_tiles, off_partial,
-        off_scal, off_w, off_rank, off_a0, off_t1, off_t2;
+        off_scal, off_w, off_rank, off_a0, off_t1, off_t2, off_ablk32, off_q32, off_v32;
     size_t total;
 };
 
 struct SvdPlan {
     int m, n, mpad, npad, b, N, H, R, nchunks;
-    bool vectors, refine;
+    bool vectors, refine, mixed;
     size_t off_g, off_v, off_vhat, off_flags, off_pairs, off_force, off_partial, off_ahat, off_meas,
-        off_cnt, off_sigma, off_rank, off_g0, off_t1, off_t2;
+        off_cnt, off_sigma, off_rank, off_g0, off_t1, off_t2, off_g32, off_v32, off_vhat32;
     size_t total;
 };
 

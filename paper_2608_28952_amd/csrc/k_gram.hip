@@ -15,16 +15,18 @@ namespace {
 
 constexpr int GKR = 16;  // rows per LDS stage
 
-template <int B>
+template <int B, class T>
 __global__ void __launch_bounds__(256, 2)
-k_gram_partial(const double *__restrict__ G, int ldg, const int *__restrict__ pairs, int rows_per_chunk,
-               double *__restrict__ partial) {
+k_gram_partial(const T *__restrict__ G, int ldg, const int *__restrict__ pairs, int rows_per_chunk,
+               T *__restrict__ partial) {
+    using MT = MfmaTraits<T>;
+    typedef typename MT::acc_t acc_t;
     constexpr int M2 = 2 * B;
     constexpr int LDX = M2 + 1;
     constexpr int HALF = M2 / 2;           // output rows/cols per wave
     constexpr int TI = HALF / 16;          // 16-tiles per wave and dimension
     constexpr int PER = GKR * M2 / 256;    // staged values per thread
-    __shared__ double xs[2][GKR * LDX];
+    __shared__ T xs[2][GKR * LDX];
     const int p = blockIdx.y, ch = blockIdx.x;
     const int I = pairs[2 * p], J = pairs[2 * p + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -32,14 +34,14 @@ k_gram_partial(const double *__restrict__ G, int ldg, const int *__restrict__ pa
     const int wi = w & 1, wj = w >> 1;
     const size_t r0 = (size_t)ch * rows_per_chunk;
 
-    d4 acc[TI][TI];
+    acc_t acc[TI][TI];
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
-        for (int b = 0; b < TI; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < TI; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     auto colof = [&](int c) { return c < B ? I * B + c : J * B + (c - B); };
-    double reg[PER];
+    T reg[PER];
     auto fetch = [&](size_t rr) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
@@ -48,7 +50,7 @@ k_gram_partial(const double *__restrict__ G, int ldg, const int *__restrict__ pa
             reg[m] = G[(size_t)colof(c) * ldg + rr + r];
         }
     };
-    auto stage = [&](double *dst) {
+    auto stage = [&](T *dst) {
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int e = tid + 256 * m;
@@ -62,11 +64,11 @@ k_gram_partial(const double *__restrict__ G, int ldg, const int *__restrict__ pa
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
         if (st + 1 < nst) fetch(r0 + (size_t)(st + 1) * GKR);
-        const double *X = xs[st & 1];
+        const T *X = xs[st & 1];
 #pragma unroll
         for (int kk = 0; kk < GKR; kk += 4) {
-            const int k = kk + g;
-            double af[TI], bf[TI];
+            const int k = kk + g;  // rows of the chunk: any order, the same for both operands
+            T af[TI], bf[TI];
 #pragma unroll
             for (int a = 0; a < TI; ++a) af[a] = X[k * LDX + HALF * wi + 16 * a + x];  // X^T(i, k)
 #pragma unroll
@@ -74,32 +76,33 @@ k_gram_partial(const double *__restrict__ G, int ldg, const int *__restrict__ pa
 #pragma unroll
             for (int a = 0; a < TI; ++a)
 #pragma unroll
-                for (int b = 0; b < TI; ++b) acc[a][b] = mfma_f64(af[a], bf[b], acc[a][b]);
+                for (int b = 0; b < TI; ++b) acc[a][b] = MT::mma(af[a], bf[b], acc[a][b]);
         }
         if (st + 1 < nst) stage(xs[(st + 1) & 1]);
         __syncthreads();
     }
-    // acc[a][b] lane (g, x) comp v = C(i, j), i = HALF wi + 16 a + g + 4 v,
+    // acc[a][b] lane (g, x) comp v = C(i, j), i = HALF wi + 16 a + rrow(g, v),
     // j = HALF wj + 16 b + x; stored at [i * M2 + j] (the transpose, equal by
     // symmetry; consecutive lanes write consecutive addresses)
-    double *out = partial + ((size_t)p * gridDim.x + ch) * M2 * M2;
+    T *out = partial + ((size_t)p * gridDim.x + ch) * M2 * M2;
 #pragma unroll
     for (int a = 0; a < TI; ++a)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int b = 0; b < TI; ++b)
-                out[(size_t)(HALF * wi + 16 * a + g + 4 * v) * M2 + HALF * wj + 16 * b + x] = acc[a][b][v];
+                out[(size_t)(HALF * wi + 16 * a + MT::rrow(g, v)) * M2 + HALF * wj + 16 * b + x] = acc[a][b][v];
 }
 
-// ahat[p] = sum over chunks c = 0 .. nch-1 of partial[p][c], in that order.
-__global__ void k_gram_reduce(int m2sq, int nch, const double *__restrict__ partial, double *__restrict__ ahat) {
+// ahat[p] = sum over chunks c = 0 .. nch-1 of partial[p][c], in that order (FP64).
+template <class T>
+__global__ void k_gram_reduce(int m2sq, int nch, const T *__restrict__ partial, double *__restrict__ ahat) {
     const int p = blockIdx.y;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m2sq) return;
-    const double *src = partial + (size_t)p * nch * m2sq + e;
+    const T *src = partial + (size_t)p * nch * m2sq + e;
     double s = 0.0;
-    for (int c = 0; c < nch; ++c) s += src[(size_t)c * m2sq];
+    for (int c = 0; c < nch; ++c) s += (double)src[(size_t)c * m2sq];
     ahat[(size_t)p * m2sq + e] = s;
 }
 
@@ -135,8 +138,9 @@ __global__ void __launch_bounds__(256) k_scale_scatter(int m, const double *__re
 
 }  // namespace
 
-void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, int m_rows, int nchunks,
-                 double *partial, double *ahat, hipStream_t s) {
+template <class T>
+static void launch_gram_t(int b, int npairs, const int *pairs, const T *G, int ldg, int m_rows, int nchunks,
+                          T *partial, double *ahat, hipStream_t s) {
     if (npairs <= 0) return;
     const int rows_per_chunk = m_rows / nchunks;
     if (rows_per_chunk % GKR || rows_per_chunk * nchunks != m_rows) {
@@ -144,13 +148,22 @@ void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, 
         throw HipFail{hipErrorInvalidValue};
     }
     dim3 grid(nchunks, npairs);
-    if (b == 64) hipLaunchKernelGGL(k_gram_partial<64>, grid, dim3(256), 0, s, G, ldg, pairs, rows_per_chunk, partial);
-    else if (b == 32) hipLaunchKernelGGL(k_gram_partial<32>, grid, dim3(256), 0, s, G, ldg, pairs, rows_per_chunk, partial);
+    if (b == 64) hipLaunchKernelGGL((k_gram_partial<64, T>), grid, dim3(256), 0, s, G, ldg, pairs, rows_per_chunk, partial);
+    else if (b == 32) hipLaunchKernelGGL((k_gram_partial<32, T>), grid, dim3(256), 0, s, G, ldg, pairs, rows_per_chunk, partial);
     else { set_error("gram: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
     JX_LAUNCHED();
     const int m2sq = 4 * b * b;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((m2sq + 255) / 256, npairs), dim3(256), 0, s, m2sq, nchunks, partial, ahat);
+    hipLaunchKernelGGL((k_gram_reduce<T>), dim3((m2sq + 255) / 256, npairs), dim3(256), 0, s, m2sq, nchunks, partial, ahat);
     JX_LAUNCHED();
+}
+
+void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, int m_rows, int nchunks,
+                 double *partial, double *ahat, hipStream_t s) {
+    launch_gram_t<double>(b, npairs, pairs, G, ldg, m_rows, nchunks, partial, ahat, s);
+}
+void launch_gram32(int b, int npairs, const int *pairs, const float *G, int ldg, int m_rows, int nchunks,
+                   float *partial, double *ahat, hipStream_t s) {
+    launch_gram_t<float>(b, npairs, pairs, G, ldg, m_rows, nchunks, partial, ahat, s);
 }
 
 void launch_col_norms(int m, int n, const double *G, int ldg, double *sigma, hipStream_t s) {

@@ -333,3 +333,74 @@ void launch_copy_rect(int m, int n, const double *src, int lds_, double *dst, in
     JX_LAUNCHED();
 }
 }  // namespace jx
+
+namespace jx {
+namespace {
+template <class S, class D>
+__global__ void k_cast(size_t count, const S *__restrict__ src, D *__restrict__ dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (D)src[i];
+}
+__global__ void k_set_identity32(int npad, float *Q, int ldq) {
+    const size_t j = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npad; i += gridDim.x * blockDim.x)
+        Q[j * ldq + i] = (i == (int)j) ? 1.0f : 0.0f;
+}
+__global__ void __launch_bounds__(256) k_block_norms32(int b, const float *__restrict__ ablk, double *__restrict__ partial) {
+    __shared__ double red[8];
+    const int s = blockIdx.x;
+    int j = (int)((sqrt(8.0 * s + 1.0) - 1.0) * 0.5);
+    while ((j + 1) * (j + 2) / 2 <= s) ++j;
+    while (j * (j + 1) / 2 > s) --j;
+    const int J = j, I = s - j * (j + 1) / 2;
+    const float *src = ablk + ublk(I, J) * (size_t)(b * b);
+    double off = 0.0, dia = 0.0;
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const double v = src[e];
+        if (I != J) off += 2.0 * v * v;
+        else if (e % b == e / b) dia += v * v;
+        else off += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) { off += __shfl_xor(off, o, 64); dia += __shfl_xor(dia, o, 64); }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[w] = off; red[4 + w] = dia; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        partial[2 * blockIdx.x + 1] = red[4] + red[5] + red[6] + red[7];
+    }
+}
+__global__ void __launch_bounds__(256) k_reduce_pairs2(int count, const double *__restrict__ partial, double *__restrict__ out) {
+    __shared__ double red[8];
+    double a = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) { a += partial[2 * i]; c += partial[2 * i + 1]; }
+    for (int o = 32; o > 0; o >>= 1) { a += __shfl_xor(a, o, 64); c += __shfl_xor(c, o, 64); }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[w] = a; red[4 + w] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) { out[0] = red[0] + red[1] + red[2] + red[3]; out[1] = red[4] + red[5] + red[6] + red[7]; }
+}
+}  // namespace
+
+void launch_cast_to_f32(size_t count, const double *src, float *dst, hipStream_t s) {
+    if (!count) return;
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(2048), dim3(256), 0, s, count, src, dst);
+    JX_LAUNCHED();
+}
+void launch_cast_to_f64(size_t count, const float *src, double *dst, hipStream_t s) {
+    if (!count) return;
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(2048), dim3(256), 0, s, count, src, dst);
+    JX_LAUNCHED();
+}
+void launch_set_identity32(int npad, float *Q, int ldq, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_identity32, dim3((npad + 255) / 256, npad), dim3(256), 0, s, npad, Q, ldq);
+    JX_LAUNCHED();
+}
+void launch_block_norms32(int npad, int b, const float *ablk, double *partial, double *out, hipStream_t s) {
+    const int N = npad / b, nb = N * (N + 1) / 2;
+    hipLaunchKernelGGL(k_block_norms32, dim3(nb), dim3(256), 0, s, b, ablk, partial);
+    JX_LAUNCHED();
+    hipLaunchKernelGGL(k_reduce_pairs2, dim3(1), dim3(256), 0, s, nb, partial, out);
+    JX_LAUNCHED();
+}
+}  // namespace jx

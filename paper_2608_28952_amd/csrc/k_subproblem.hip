@@ -144,16 +144,28 @@ __global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
     // ---- load the upper triangle of A_hat into LDS (slot order) -----------
     double off2 = 0.0, fro2 = 0.0;
     const double *srcp = nullptr;
+    const float *Fii = nullptr, *Fjj = nullptr, *Fij = nullptr;
     if (MODE == SUB_EIG) {
         const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
-        Wii = a.ablk + ublk(I, I) * (size_t)(B * B);
-        Wjj = a.ablk + ublk(J, J) * (size_t)(B * B);
-        Wij = a.ablk + ublk(I, J) * (size_t)(B * B);
+        if (a.ablk32) {
+            Fii = a.ablk32 + ublk(I, I) * (size_t)(B * B);
+            Fjj = a.ablk32 + ublk(J, J) * (size_t)(B * B);
+            Fij = a.ablk32 + ublk(I, J) * (size_t)(B * B);
+        } else {
+            Wii = a.ablk + ublk(I, I) * (size_t)(B * B);
+            Wjj = a.ablk + ublk(J, J) * (size_t)(B * B);
+            Wij = a.ablk + ublk(I, J) * (size_t)(B * B);
+        }
     } else {
         srcp = a.ahat + (size_t)pr * M2 * M2;
     }
     auto load = [&](int r, int c) -> double {
         if (MODE == SUB_EIG) {
+            if (Fii) {  // FP32 storage: the subproblem is still solved in FP64
+                if (c < B) return (double)Fii[c * B + r];
+                if (r < B) return (double)Fij[(c - B) * B + r];
+                return (double)Fjj[(c - B) * B + (r - B)];
+            }
             if (c < B) return Wii[c * B + r];
             if (r < B) return Wij[(c - B) * B + r];
             return Wjj[(c - B) * B + (r - B)];
@@ -389,26 +401,35 @@ __global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
             dd[e] = As[min(u, w) * LD + max(u, w)];
         }
     } else {
-        double *vo = a.vout + (size_t)pr * M2 * M2;
+        if (a.vout32) {
+            float *vo = a.vout32 + (size_t)pr * M2 * M2;
 #pragma unroll
-        for (int x = 0; x < 16; ++x) vo[vperm(r, 16 * g + x, M2)] = V[x];
+            for (int x = 0; x < 16; ++x) vo[vperm32(r, 16 * g + x, M2)] = (float)V[x];
+        } else {
+            double *vo = a.vout + (size_t)pr * M2 * M2;
+#pragma unroll
+            for (int x = 0; x < 16; ++x) vo[vperm(r, 16 * g + x, M2)] = V[x];
+        }
         if (MODE == SUB_EIG) {
             // A([I,J],[I,J]) <- D_hat (pointers recomputed: not kept live through the sweeps)
             const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
-            Wii = a.ablk + ublk(I, I) * (size_t)(B * B);
-            Wjj = a.ablk + ublk(J, J) * (size_t)(B * B);
-            Wij = a.ablk + ublk(I, J) * (size_t)(B * B);
+            const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
+                         oij = ublk(I, J) * (size_t)(B * B);
             for (int e = tid; e < M2 * M2; e += NT) {
                 const int rr = e % M2, cc = e / M2;
                 const int u = slot_of(rr, M2), w = slot_of(cc, M2);
                 const double v = As[min(u, w) * LD + max(u, w)];
+                size_t off;
                 if (cc < B) {
-                    if (rr < B) Wii[cc * B + rr] = v;
+                    if (rr >= B) continue;
+                    off = oii + cc * B + rr;
                 } else if (rr < B) {
-                    Wij[(cc - B) * B + rr] = v;
+                    off = oij + (cc - B) * B + rr;
                 } else {
-                    Wjj[(cc - B) * B + (rr - B)] = v;
+                    off = ojj + (cc - B) * B + (rr - B);
                 }
+                if (a.ablk32) a.ablk32[off] = (float)v;
+                else a.ablk[off] = v;
             }
         }
     }

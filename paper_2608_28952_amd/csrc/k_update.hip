@@ -45,9 +45,8 @@ struct UaCfg {
 // Fetch the PER values of X chunk `ch` (columns ch*KC .. +KC-1 of the tile)
 // that this thread stages.  Rows 0..B-1 come from block row Rr[0], rows
 // B..2B-1 from Rr[1]; the chunk lies in block column Cc.
-template <int B>
-__device__ __forceinline__ void fetch_chunk(const double *ablk, const int Rr[2], int Cc, int c0,
-                                            double *reg) {
+template <int B, class T>
+__device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int Cc, int c0, T *reg) {
     using U = UaCfg<B>;
     const int tid = threadIdx.x;
 #pragma unroll
@@ -56,13 +55,13 @@ __device__ __forceinline__ void fetch_chunk(const double *ablk, const int Rr[2],
 #pragma unroll
         for (int m = 0; m < U::PER / 2; ++m) {
             const int e = tid + 256 * m;  // 0 .. B*KC-1
-            double v;
+            T v;
             if (R < Cc) {
-                const double *src = ablk + ublk(R, Cc) * (size_t)(B * B);
+                const T *src = ablk + ublk(R, Cc) * (size_t)(B * B);
                 const int rl = e % B, cl = e / B;
                 v = src[(c0 + cl) * B + rl];
             } else {
-                const double *src = ablk + ublk(Cc, R) * (size_t)(B * B);
+                const T *src = ablk + ublk(Cc, R) * (size_t)(B * B);
                 const int cl = e % KC, rl = e / KC;
                 v = src[rl * B + c0 + cl];
             }
@@ -71,8 +70,8 @@ __device__ __forceinline__ void fetch_chunk(const double *ablk, const int Rr[2],
     }
 }
 
-template <int B>
-__device__ __forceinline__ void stage_chunk(double *xs, const int Rr[2], int Cc, const double *reg) {
+template <int B, class T>
+__device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, const T *reg) {
     using U = UaCfg<B>;
     const int tid = threadIdx.x;
 #pragma unroll
@@ -89,65 +88,68 @@ __device__ __forceinline__ void stage_chunk(double *xs, const int Rr[2], int Cc,
     }
 }
 
-template <int B>
+template <int B, class T>
 __global__ void __launch_bounds__(256, 2)
-k_update_a(const int *__restrict__ pairs, double *__restrict__ ablk, const double *__restrict__ vhat,
+k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
            const int *__restrict__ flags, const int *__restrict__ tiles) {
     using U = UaCfg<B>;
+    using MT = MfmaTraits<T>;
+    typedef typename MT::acc_t acc_t;
     constexpr int M2 = U::M2, RT = U::RT, CT = U::CT, WW = U::WW;
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
 
     const int p = tiles[2 * blockIdx.x], q = tiles[2 * blockIdx.x + 1];
     const bool idp = flags[p] != 0, idq = flags[q] != 0;
     if (idp && idq) return;
     const int Rr[2] = {pairs[2 * p], pairs[2 * p + 1]};
     const int Cq[2] = {pairs[2 * q], pairs[2 * q + 1]};
-    const double *vp = vhat + (size_t)p * M2 * M2;
-    const double *vq = vhat + (size_t)q * M2 * M2;
+    const T *vp = vhat + (size_t)p * M2 * M2;
+    const T *vq = vhat + (size_t)q * M2 * M2;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int wc0 = w * WW;
 
-    d4 acc[RT][CT];
+    acc_t acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < CT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     // ---------------- GEMM 1: T(:, wc0 .. wc0+WW-1) = X V_q ----------------
-    double reg[U::PER];
-    fetch_chunk<B>(ablk, Rr, Cq[0], 0, reg);
-    stage_chunk<B>(lds, Rr, Cq[0], reg);
+    T reg[U::PER];
+    fetch_chunk<B, T>(ablk, Rr, Cq[0], 0, reg);
+    stage_chunk<B, T>(lds, Rr, Cq[0], reg);
     __syncthreads();
     for (int ch = 0; ch < U::NCH; ++ch) {
-        double *xs = lds + (size_t)(ch & 1) * KC * U::XLD;
+        T *xs = lds + (size_t)(ch & 1) * KC * U::XLD;
         if (ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            fetch_chunk<B>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg);
+            fetch_chunk<B, T>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg);
         }
         // (V_q = I is applied as an exact identity operand: products with 1.0
         // and sums of exact zeros reproduce X bit for bit)
 #pragma unroll 1
         for (int st = 0; st < KC / 4; ++st) {
-            const int kl = 4 * st + g;
+            const int kl = MT::kstep(st, g);
             const int kg = ch * KC + kl;
-            double bf[CT];
+            T bf[CT];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int col = wc0 + 16 * ct + x;
-                bf[ct] = idq ? (kg == col ? 1.0 : 0.0) : vq[vperm(kg, col, M2)];
+                bf[ct] = idq ? (kg == col ? T(1) : T(0)) : vq[MT::vidx(kg, col, M2)];
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                const double af = xs[kl * U::XLD + 16 * rt + x];
+                const T af = xs[kl * U::XLD + 16 * rt + x];
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = mfma_f64(af, bf[ct], acc[rt][ct]);
+                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = MT::mma(af, bf[ct], acc[rt][ct]);
             }
         }
         if (ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            stage_chunk<B>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg);
+            stage_chunk<B, T>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg);
         }
         __syncthreads();
     }
@@ -158,34 +160,35 @@ k_update_a(const int *__restrict__ pairs, double *__restrict__ ablk, const doubl
     // unrolled so that the accumulator arrays are indexed with constants only.
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        double *os = lds;
+        T *os = lds;
 #pragma unroll 1
         for (int ot = 0; ot < RT / 2; ++ot) {
-            d4 o[CT];
+            acc_t o[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) o[ct] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int ct = 0; ct < CT; ++ct) o[ct] = acc_t{0, 0, 0, 0};
             // (V_p = I is applied as an exact identity operand, as for V_q)
             const int orow = h * B + 16 * ot + x;
-            const double *vrow = vp + vperm(0, orow, M2);
+            const T *vrow = vp + MT::vidx(0, orow, M2);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                double af[4];
+                T af[4];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {  // vperm(k, i) - vperm(0, i) depends on k only
-                    const int k = 16 * rt + 4 * s + g;
-                    af[s] = idp ? (k == orow ? 1.0 : 0.0) : vrow[vperm(k, 0, M2) - vperm(0, 0, M2)];
+                for (int s = 0; s < 4; ++s) {  // vidx(k, i) - vidx(0, i) depends on k only
+                    // row of T held in component s of lane group g
+                    const int k = 16 * rt + MT::rrow(g, s);
+                    af[s] = idp ? (k == orow ? T(1) : T(0)) : vrow[MT::vidx(k, 0, M2) - MT::vidx(0, 0, M2)];
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) o[ct] = mfma_f64(af[s], acc[rt][ct][s], o[ct]);
+                    for (int ct = 0; ct < CT; ++ct) o[ct] = MT::mma(af[s], acc[rt][ct][s], o[ct]);
                 __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    os[(wc0 + 16 * ct + x) * U::OLD + 16 * ot + g + 4 * v] = o[ct][v];
+                    os[(wc0 + 16 * ct + x) * U::OLD + 16 * ot + MT::rrow(g, v)] = o[ct][v];
         }
         __syncthreads();
         const int R = h ? Rr[1] : Rr[0];
@@ -193,13 +196,13 @@ k_update_a(const int *__restrict__ pairs, double *__restrict__ ablk, const doubl
         for (int cb = 0; cb < 2; ++cb) {
             const int Cc = cb ? Cq[1] : Cq[0];
             if (R < Cc) {
-                double *dst = ablk + ublk(R, Cc) * (size_t)(B * B);
+                T *dst = ablk + ublk(R, Cc) * (size_t)(B * B);
                 for (int e = tid; e < B * B; e += 256) {
                     const int rl = e % B, cl = e / B;
                     dst[e] = os[(cb * B + cl) * U::OLD + rl];
                 }
             } else {
-                double *dst = ablk + ublk(Cc, R) * (size_t)(B * B);
+                T *dst = ablk + ublk(Cc, R) * (size_t)(B * B);
                 for (int e = tid; e < B * B; e += 256) {
                     const int cl = e % B, rl = e / B;  // stored (Cc, R): element (cl, rl)
                     dst[e] = os[(cb * B + cl) * U::OLD + rl];
@@ -214,10 +217,12 @@ k_update_a(const int *__restrict__ pairs, double *__restrict__ ablk, const doubl
 // out^T = V_p^T X^T so that lanes hold consecutive rows of the column-major Q.
 // Waves in a 2 x 2 layout: wave (wi, wj) owns out columns b wi .. b wi + b-1
 // (of the 2b pair columns) and Q rows r0 + 64 wj .. r0 + 64 wj + 63.
-template <int B>
+template <int B, class T>
 __global__ void __launch_bounds__(256, 2)
-k_update_q(const int *__restrict__ pairs, double *__restrict__ Q, int ldq,
-           const double *__restrict__ vhat, const int *__restrict__ flags) {
+k_update_q(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
+           const T *__restrict__ vhat, const int *__restrict__ flags) {
+    using MT = MfmaTraits<T>;
+    typedef typename MT::acc_t acc_t;
     constexpr int M2 = 2 * B;
     constexpr int HALF = M2 / 2;     // out columns per wave
     constexpr int IT = HALF / 16;    // 16-tiles of out columns per wave
@@ -225,48 +230,48 @@ k_update_q(const int *__restrict__ pairs, double *__restrict__ Q, int ldq,
     const int p = blockIdx.y;
     if (flags[p]) return;
     const int I = pairs[2 * p], J = pairs[2 * p + 1];
-    const double *vp = vhat + (size_t)p * M2 * M2;
+    const T *vp = vhat + (size_t)p * M2 * M2;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int wi = w & 1, wj = w >> 1;
     const size_t r0 = (size_t)blockIdx.x * 128 + 64 * wj;
 
-    d4 acc[IT][JT];
+    acc_t acc[IT][JT];
 #pragma unroll
     for (int i = 0; i < IT; ++i)
 #pragma unroll
-        for (int j = 0; j < JT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < JT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     auto colof = [&](int k) { return k < B ? I * B + k : J * B + (k - B); };
 
-    double an[IT], bn[JT];
+    T an[IT], bn[JT];
     {
-        const int k = g;  // step 0: k = 4 * 0 + g
-        const double *qc = Q + (size_t)colof(k) * ldq + r0;
+        const int k = MT::kstep(0, g);
+        const T *qc = Q + (size_t)colof(k) * ldq + r0;
 #pragma unroll
-        for (int i = 0; i < IT; ++i) an[i] = vp[vperm(k, HALF * wi + 16 * i + x, M2)];
+        for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
 #pragma unroll
         for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
     }
 #pragma unroll 4
     for (int st = 0; st < M2 / 4; ++st) {
-        double a_[IT], b_[JT];
+        T a_[IT], b_[JT];
 #pragma unroll
         for (int i = 0; i < IT; ++i) a_[i] = an[i];
 #pragma unroll
         for (int j = 0; j < JT; ++j) b_[j] = bn[j];
         if (st + 1 < M2 / 4) {
-            const int k = 4 * (st + 1) + g;
-            const double *qc = Q + (size_t)colof(k) * ldq + r0;
+            const int k = 16 * ((st + 1) >> 2) + MT::kstep((st + 1) & 3, g);
+            const T *qc = Q + (size_t)colof(k) * ldq + r0;
 #pragma unroll
-            for (int i = 0; i < IT; ++i) an[i] = vp[vperm(k, HALF * wi + 16 * i + x, M2)];
+            for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
 #pragma unroll
             for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
         }
 #pragma unroll
         for (int i = 0; i < IT; ++i)
 #pragma unroll
-            for (int j = 0; j < JT; ++j) acc[i][j] = mfma_f64(a_[i], b_[j], acc[i][j]);
+            for (int j = 0; j < JT; ++j) acc[i][j] = MT::mma(a_[i], b_[j], acc[i][j]);
     }
     // the two waves sharing these rows read every pair column: wait for both
     // before the in-place store
@@ -275,24 +280,45 @@ k_update_q(const int *__restrict__ pairs, double *__restrict__ Q, int ldq,
     for (int i = 0; i < IT; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            double *qc = Q + (size_t)colof(HALF * wi + 16 * i + g + 4 * v) * ldq + r0;
+            T *qc = Q + (size_t)colof(HALF * wi + 16 * i + MT::rrow(g, v)) * ldq + r0;
 #pragma unroll
             for (int j = 0; j < JT; ++j) qc[16 * j + x] = acc[i][j][v];
         }
 }
 
-template <int B>
-void launch_ua_t(int npairs, const int *pairs, double *ablk, const double *vhat, const int *flags,
-                 const int *tiles, int ntiles, hipStream_t s) {
+template <int B, class T>
+void launch_ua_t(int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
+                 int ntiles, hipStream_t s) {
     using U = UaCfg<B>;
     static bool attr = false;
     if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a<B>),
+        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a<B, T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::LDS_BYTES));
         attr = true;
     }
     (void)npairs;
-    hipLaunchKernelGGL(k_update_a<B>, dim3(ntiles), dim3(256), U::LDS_BYTES, s, pairs, ablk, vhat, flags, tiles);
+    hipLaunchKernelGGL((k_update_a<B, T>), dim3(ntiles), dim3(256), U::LDS_BYTES, s, pairs, ablk, vhat, flags,
+                       tiles);
+    JX_LAUNCHED();
+}
+
+template <class T>
+void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
+               int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (b == 64) launch_ua_t<64, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
+    else if (b == 32) launch_ua_t<32, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
+    else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
+}
+
+template <class T>
+void launch_uq(int b, int npairs, const int *pairs, T *Q, int ldq, int n_rows, const T *vhat, const int *flags,
+               hipStream_t s) {
+    if (npairs <= 0 || n_rows <= 0) return;
+    dim3 grid(n_rows / 128, npairs);
+    if (b == 64) hipLaunchKernelGGL((k_update_q<64, T>), grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
+    else if (b == 32) hipLaunchKernelGGL((k_update_q<32, T>), grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
+    else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
     JX_LAUNCHED();
 }
 
@@ -300,20 +326,19 @@ void launch_ua_t(int npairs, const int *pairs, double *ablk, const double *vhat,
 
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
                      const int *flags, const int *tiles, int ntiles, hipStream_t s) {
-    if (ntiles <= 0) return;
-    if (b == 64) launch_ua_t<64>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
-    else if (b == 32) launch_ua_t<32>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
-    else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
+    launch_ua<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
 }
-
+void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
+                       const int *tiles, int ntiles, hipStream_t s) {
+    launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
+}
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s) {
-    if (npairs <= 0 || n_rows <= 0) return;
-    dim3 grid(n_rows / 128, npairs);
-    if (b == 64) hipLaunchKernelGGL(k_update_q<64>, grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
-    else if (b == 32) hipLaunchKernelGGL(k_update_q<32>, grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
-    else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
-    JX_LAUNCHED();
+    launch_uq<double>(b, npairs, pairs, Q, ldq, n_rows, vhat, flags, s);
+}
+void launch_update_q32(int b, int npairs, const int *pairs, float *Q, int ldq, int n_rows, const float *vhat,
+                       const int *flags, hipStream_t s) {
+    launch_uq<float>(b, npairs, pairs, Q, ldq, n_rows, vhat, flags, s);
 }
 
 }  // namespace jx

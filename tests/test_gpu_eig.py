@@ -295,3 +295,45 @@ def test_eig_n4096_graded_full_size(jx):
     res, orth = O.check_eig_sampled(A, W, Q, cols)
     # per-column residual bound consistent with ||A - QDQ^T||_F/||A||_F <= 1e-12
     assert res <= 1e-12 / np.sqrt(48) * 10 and orth <= 1e-13, (res, orth)
+
+
+# --------------------------------------------------------------------------
+# Precision ladder: FP32 sweeps (FP64 subproblems), FP64 recomputation, FP64 sweeps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,kind,b", [(320, "uniform", 32), (512, "graded", 64), (384, "normal", 64)])
+def test_eig_mixed_fp32_matches_oracle(jx, n, kind, b):
+    gen = {"uniform": inputs.eig_uniform, "graded": inputs.eig_graded, "normal": inputs.eig_normal}[kind]
+    A, lam = gen(n, 60 + n)
+    W, Q, info = eig_gpu(jx, A, precision=jx.PREC_MIXED_FP32, block=b)
+    assert info["status"] == 0, info
+    assert info["sweeps_by_prec"][1] > 0 and info["sweeps_by_prec"][2] > 0
+    print(f"mixed n={n} {kind}: fp32 sweeps {info['sweeps_by_prec'][1]}, fp64 sweeps {info['sweeps_by_prec'][2]}")
+    _check_against_oracle(A, W, Q)
+    if kind == "graded":
+        ora = O.eig(A, order=1)
+        big = np.abs(ora.W) >= 1e-6
+        assert np.max(np.abs(W - ora.W)[big] / np.abs(ora.W[big])) <= 1e-10
+
+
+def test_eig_mixed_values_only(jx):
+    A, _ = inputs.eig_uniform(256, 4)
+    W, Q, info = eig_gpu(jx, A, precision=jx.PREC_MIXED_FP32, want_vectors=0)
+    assert Q is None and info["status"] == 0
+    assert np.max(np.abs(W - O.eig(A).W)) <= 1e-12
+
+
+def test_eig_n4096_graded_mixed_fp32(jx):
+    n = 4096
+    A, lam = inputs.eig_graded(n, 2)
+    W, Q, info = eig_gpu(jx, A, precision=jx.PREC_MIXED_FP32)
+    assert info["status"] == 0, info
+    ref = np.sort(lam)
+    err = np.abs(W - ref)
+    big = np.abs(ref) >= 1e-6
+    print(f"mixed n=4096: sweeps {info['sweeps_by_prec']}, max abs err {err.max():.2e}, "
+          f"max rel err (|lam|>=1e-6) {np.max(err[big] / np.abs(ref[big])):.2e}")
+    assert err.max() <= 1e-12 and np.max(err[big] / np.abs(ref[big])) <= 1e-10
+    cols = np.random.default_rng(0).choice(n, 48, replace=False)
+    res, orth = O.check_eig_sampled(A, W, Q, cols)
+    assert res <= 1e-12 / np.sqrt(48) * 10 and orth <= 1e-13, (res, orth)

@@ -121,3 +121,30 @@ def test_svd_full_size_16384x2048(jx):
     cols = np.random.default_rng(1).choice(n, 24, replace=False)
     res, ov, ou = O.check_svd_sampled(G, S, U, V, cols)
     assert res <= 1e-13 and ov <= 1e-13, (res, ov, ou)
+
+
+@pytest.mark.parametrize("m,n", [(512, 128), (1000, 64), (2048, 256)])
+def test_svd_mixed_fp32_matches_oracle(jx, m, n):
+    G, sigma = inputs.svd_case(m, n, 30 + n)
+    S, U, V, info = svd_gpu(jx, G, precision=jx.PREC_MIXED_FP32)
+    assert info["status"] == 0, info
+    assert info["sweeps_by_prec"][1] > 0
+    ora = O.svd(G)
+    assert np.max(np.abs(S - ora.S)) <= 1e-12 * ora.S[0]
+    print(f"svd mixed {m}x{n}: sweeps {info['sweeps_by_prec']}, max rel {np.max(np.abs(S - ora.S) / ora.S):.2e}")
+    res, ov, ou = O.check_svd(G, S, U, V)
+    assert res <= 1e-12 and ov <= 1e-12 and ou <= 1e-12 / ora.S[-1]
+
+
+def test_svd_full_size_mixed_fp32(jx):
+    m, n = 16384, 2048
+    G, sigma = inputs.svd_case(m, n, 3)
+    S, U, V, info = svd_gpu(jx, G, precision=jx.PREC_MIXED_FP32)
+    assert info["status"] == 0, info
+    ref = np.sort(sigma)[::-1]
+    rel = np.max(np.abs(S - ref) / ref)
+    print(f"svd full mixed: sweeps {info['sweeps_by_prec']} max rel sigma err {rel:.2e}")
+    assert np.max(np.abs(S - ref)) <= 1e-12 * ref[0]
+    cols = np.random.default_rng(1).choice(n, 24, replace=False)
+    res, ov, ou = O.check_svd_sampled(G, S, U, V, cols)
+    assert res <= 1e-13 and ov <= 1e-13, (res, ov, ou)
