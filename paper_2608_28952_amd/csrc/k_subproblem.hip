@@ -1,48 +1,52 @@
 // k_subproblem.hip -- the subproblem solver of block Jacobi on gfx950.
 //
 // One workgroup diagonalises one 2b x 2b symmetric subproblem
-// A_hat = A([I,J],[I,J]) (Alg. 1 and the diagonalisation step of Alg. 2, §3)
-// by inner scalar Jacobi: sweeps of m2 - 1 rounds, each round rotating m2/2
-// disjoint index pairs at once (disjoint rotations commute, §3).  The exact
-// or approximate diagonalisation of the subproblem is left open by the paper
-// (§3, after Alg. 3); `inner_sweeps` caps the inner sweeps.
+// A_hat = A([I,J],[I,J]) (Alg. 1 and the diagonalisation step of Alg. 2, §3).
+// The paper leaves open whether the subproblem is diagonalised exactly or
+// approximately (§3, after Alg. 3); `inner_sweeps` caps the inner sweeps
+// (0 = until off(A_hat) <= eps ||A_hat||_F, at most 30).
 //
-// Data placement
-//   * A_hat: LDS, upper triangle only, row-major with stride LD = m2.  Index
-//     x is stored at slot pi(x) = ring order (pi(0) = 0, pi(x) = 1 + ring
-//     index of x): in round t the pair members p_k, q_k of consecutive k sit
-//     at consecutive slots (p: slot 1 + (k + t) mod (m2-1), q: slot
-//     1 + (t - k) mod (m2-1)), so the lanes of a wave touch addresses with odd
-//     strides (m2 + 1, m2 - 1) and the LDS banks are not in conflict.
-//   * V_hat: registers.  Thread (r, g) holds row r of V_hat at the 16
-//     "positions" 16 g .. 16 g + 15.  Positions are paired (2k, 2k+1) in every
-//     round; after a round the column content moves one step along the
-//     round-robin ring 1 <- 2 <- 4 <- ... <- m2-2 <- m2-1 <- m2-3 <- ... <- 3 <- 1
-//     (position 0 stays), so that every index pair meets once per sweep.  Two
-//     values per thread cross to the neighbouring lane (lane shuffles).  After
-//     m2 - 1 rounds the ring has turned once and positions equal indices.
-//   * Rotation parameters: computed by m2/2 threads per round into LDS, one
-//     array per quantity (c, s, t, a_pq, slot of p, slot of q).
+// Two solvers:
+//   * m2 = 32, 64: round-robin scalar Jacobi on the whole subproblem
+//     (scalar_sweeps below, one workgroup);
+//   * m2 = 128: two-level.  The 128 indices form 8 blocks of 16; a sweep of
+//     the subproblem is 7 rounds over disjoint block pairs (the same
+//     round-robin, at the block level).  Each round solves its four 32 x 32
+//     pair problems by one scalar sweep on two waves each, then applies
+//     the four rotations to A_hat (two-sided, per 32 x 32 tile) and to V_hat
+//     with FP64 MFMA.  This is the recursive use of block Jacobi (§4: a
+//     subproblem diagonalised by block Jacobi again) inside one subproblem.
 //
-// The 2x2 rotation of a pair (p, q) is the symmetric Schur form: with
-// theta = (a_qq - a_pp) / (2 a_pq), t = sgn(theta) / (|theta| + hypot(1, theta)),
-// c = 1 / sqrt(1 + t^2), s = t c, the plane rotation J = [[c, s], [-s, c]] on
-// (p, q) gives J^T A J a zero (p, q) entry and diagonal a_pp - t a_pq,
-// a_qq + t a_pq (Golub & Van Loan §8.5.2).
+// Scalar rotation (symmetric Schur form): with theta = (a_qq - a_pp) / (2 a_pq),
+// t = sgn(theta) / (|theta| + sqrt(1 + theta^2)), c = 1 / sqrt(1 + t^2), s = t c,
+// the plane rotation J = [[c, s], [-s, c]] on (p, q) gives J^T A J a zero
+// (p, q) entry and diagonal a_pp - t a_pq, a_qq + t a_pq (Golub & Van Loan
+// §8.5.2).
+//
+// Data placement of the scalar sweeps
+//   * A: LDS, upper triangle, row stride m2.  Index x sits at slot pi(x) =
+//     ring order (pi(0) = 0, pi(x) = 1 + ring index of x): in round t the
+//     members of consecutive pairs sit at consecutive slots, so the lanes of a
+//     wave touch addresses with odd strides (m2 + 1, m2 - 1): no bank conflicts.
+//   * V: registers; thread (r, g) holds row r of V at P consecutive
+//     positions P g .. P g + P - 1.  Positions are paired (2k, 2k+1) every round; after a
+//     round the column content moves one step along the ring
+//     1 <- 2 <- 4 <- ... <- m2-2 <- m2-1 <- m2-3 <- ... <- 3 <- 1 (0 stays), so
+//     that every index pair meets once per sweep; two values per thread cross
+//     to the neighbouring lane.  After m2 - 1 rounds positions equal indices.
+//   * Rotation parameters (c, s, t, a_pq per pair): LDS, two rounds.  The
+//     pivot a_pq of a round becomes zero and is not written: in the next round
+//     it lies in a known pair-block, which reads it as zero.  The pair-blocks
+//     that compute the next round's pivots also update the two diagonal
+//     entries of that pair and write the next round's parameters, so a round
+//     needs one barrier.
 #include "jx_common.hpp"
 
 namespace jx {
 
-template <int M2>
-struct SubCfg {
-    static constexpr int H = M2 / 2;             // pairs per inner round
-    static constexpr int G = M2 / 16;            // position groups per row
-    static constexpr int NT = M2 * G;            // threads
-    static constexpr int NW = NT / 64;           // waves
-    static constexpr int LD = M2;                // LDS row stride of A_hat (slots)
-    static constexpr int NOFF = H * (H - 1) / 2; // off-diagonal pair-blocks per round
-    static constexpr size_t LDS_BYTES = sizeof(double) * ((size_t)M2 * LD + 2 * 4 * H + NW + 2);
-};
+// ---------------------------------------------------------------------------
+// Ring bookkeeping
+// ---------------------------------------------------------------------------
 
 // Ring of positions 1 .. m2-1 in the order their content moves.
 __device__ __forceinline__ int ring_at(int i, int m2) {
@@ -55,14 +59,11 @@ __device__ __forceinline__ int ring_index(int x, int m2) {
     if ((x & 1) == 0) return x >> 1;
     return (2 * m2 - 1 - x) >> 1;
 }
-
 // LDS slot of index x (its place along the ring; 0 stays 0).
 __device__ __forceinline__ int slot_of(int x, int m2) { return x == 0 ? 0 : 1 + ring_index(x, m2); }
-
-// Slots of the two members of pair k in round t of a sweep (t < m2 - 1):
-// position 2k holds slot 1 + (k + t) mod (m2-1) (k >= 1; position 0 is slot 0),
-// position 2k+1 holds slot 1 + (t - k) mod (m2-1) (k >= 1; position 1 is
-// slot 1 + t).
+// Slots of the members of pair k in round t of a sweep (t < m2 - 1):
+// position 2k holds slot 1 + (k + t) mod (m2-1) (position 0: slot 0),
+// position 2k+1 holds slot 1 + (t - k) mod (m2-1).
 __device__ __forceinline__ int slot_p(int k, int t, int m2) {
     if (k == 0) return 0;
     int i = k + t;
@@ -73,6 +74,13 @@ __device__ __forceinline__ int slot_q(int k, int t, int m2) {
     int i = (k == 0) ? t : t - k;
     if (i < 0) i += m2 - 1;
     return 1 + i;
+}
+// Index found at position x in round t.
+__device__ __forceinline__ int index_at(int x, int t, int m2) {
+    if (x == 0) return 0;
+    int i = ring_index(x, m2) + t;
+    if (i >= m2 - 1) i -= m2 - 1;
+    return ring_at(i, m2);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -93,73 +101,296 @@ __device__ __forceinline__ double block_sum(double x, double *red) {
     return s;
 }
 
-// Rotation parameters of pair k (c, s, t, a_pq) from its diagonal and pivot.
-// t = sgn(theta) / (|theta| + sqrt(1 + theta^2)), theta = (a_qq - a_pp) / (2 a_pq);
-// for huge |theta| the square would overflow and t = 1 / (2 theta).
-__device__ __forceinline__ void rot_params(double app, double aqq, double apq, double *prm, int k, int H) {
-    double c = 1.0, s = 0.0, tt = 0.0;
-    if (apq != 0.0) {
-        const double th = (aqq - app) / (2.0 * apq);
-        const double ath = fabs(th);
-        tt = ath > 1e150 ? 0.5 / ath : 1.0 / (ath + sqrt(1.0 + th * th));
-        if (th < 0.0) tt = -tt;
-        c = 1.0 / sqrt(1.0 + tt * tt);
-        s = tt * c;
+// Orders the LDS accesses of one wave (stores of some lanes, loads of others):
+// waits for the wave's outstanding LDS operations, and nothing moves across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (WAVE) wave_lds_sync();
+    else __syncthreads();
+}
+
+// 1/x and 1/sqrt(x) from the hardware seeds (v_rcp_f64, v_rsq_f64) and two
+// Newton steps each: y <- y + y (1 - x y) and y <- y + y (1 - x y^2) / 2 (the
+// error squares every step), a few ulp for normal positive x.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, r, y);
+}
+
+// Rotation (c, s, t) that zeroes a_pq.  With d = a_qq - a_pp, e = 2 a_pq,
+// theta = d / e and r = sqrt(d^2 + e^2), the smaller root of t^2 + 2 theta t = 1
+// is t = sgn(theta) / (|theta| + sqrt(1 + theta^2)) = sgn(theta) |e| / (|d| + r)
+// (sgn(0) = +1), c = 1 / sqrt(1 + t^2), s = t c.  The second form needs one
+// reciprocal and two reciprocal square roots; where d^2 + e^2 leaves the
+// normal range the first form is used (for huge |theta|, t = 1 / (2 theta)).
+__device__ __forceinline__ void rot_cst(double app, double aqq, double apq, double &c, double &s, double &t) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double x = fma(d, d, e * e);
+    const double r = x * rsq_nr(x);
+    double tt = fabs(e) * rcp_nr(fabs(d) + r);
+    tt = (d != 0.0 && ((d < 0.0) != (e < 0.0))) ? -tt : tt;
+    double cc = rsq_nr(fma(tt, tt, 1.0));
+    if (!(x > 1e-280 && x < 1e280)) {  // rare: extreme magnitudes
+        tt = 0.0;
+        cc = 1.0;
+        if (apq != 0.0) {
+            const double th = d / e;
+            const double ath = fabs(th);
+            tt = ath > 1e150 ? 0.5 / ath : 1.0 / (ath + sqrt(1.0 + th * th));
+            if (th < 0.0) tt = -tt;
+            cc = 1.0 / sqrt(1.0 + tt * tt);
+        }
     }
+    if (apq == 0.0) { tt = 0.0; cc = 1.0; }
+    c = cc;
+    s = tt * cc;
+    t = tt;
+}
+
+// Rotation parameters of pair k (c, s, t, a_pq) into the parameter arrays.
+__device__ __forceinline__ void rot_params(double app, double aqq, double apq, double *prm, int k, int H) {
+    double c, s, t;
+    rot_cst(app, aqq, apq, c, s, t);
     prm[k] = c;
     prm[H + k] = s;
-    prm[2 * H + k] = tt;
+    prm[2 * H + k] = t;
     prm[3 * H + k] = apq;
 }
 
-// Round structure (one workgroup barrier per round).  The rotation
-// parameters of round t sit in an LDS buffer (c, s, t, a_pq per pair); every
-// thread applies its share of the 2x2 pair-block updates A_hat <- J^T A_hat J
-// (pair-blocks between different pairs) and of the V_hat rows.  The pivot
-// a_pq of a round becomes zero and is not written: in the next round it lies
-// in a known pair-block, which reads it as zero (cleared explicitly at the
-// end of a sweep).  The pair-blocks that compute the next round's pivots --
-// {k-1, k+1} for pair k, {0, 1} for pair 0, {H-2, H-1} for pair H-1 -- also
-// bring the two diagonal entries of that pair up to date (a_pp - t a_pq,
-// a_qq + t a_pq of their current rotation) and write the next round's
-// parameters, so no separate angle phase is needed.
-template <int M2, int MODE>
-__global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
-    using C = SubCfg<M2>;
-    constexpr int H = C::H, G = C::G, NT = C::NT, LD = C::LD, B = M2 / 2, R = M2 - 1;
-    extern __shared__ double smem[];
-    double *As = smem;                                   // M2 x LD slots
-    double *prm0 = As + (size_t)M2 * LD;                 // parameters, two rounds
-    double *red = prm0 + 8 * H;                          // reduction scratch
+// ---------------------------------------------------------------------------
+// Round-robin scalar Jacobi on an m2 x m2 matrix held in LDS (slot order)
+// ---------------------------------------------------------------------------
+// NT threads (tid 0 .. NT-1) cooperate, each holding P = m2^2 / NT positions
+// of one row of V; WAVE: the group is one wave (wave-level ordering instead
+// of workgroup barriers).  Runs `nsw` sweeps, or (conv) up to 30 sweeps until
+// off <= eps sqrt(fro2).  V receives this thread's part of the accumulated
+// rotation (row r = tid / G, columns P g .. P g + P - 1, g = tid mod G,
+// G = m2 / P); position space equals index space at the end of a sweep.
+template <int M2, int NT, bool WAVE>
+__device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, int nsw, bool conv, double fro2,
+                              double *V) {
+    constexpr int H = M2 / 2, P = M2 * M2 / NT, G = M2 / P, LD = M2, R = M2 - 1;
+    constexpr int NOFF = H * (H - 1) / 2;  // pair-blocks between different pairs
+    static_assert(P >= 4 && P % 2 == 0 && M2 % P == 0, "whole position pairs per thread");
+    const int r = tid / G, g = tid - (tid / G) * G;
+#pragma unroll
+    for (int x = 0; x < P; ++x) V[x] = (r == P * g + x) ? 1.0 : 0.0;
 
-    const int tid = threadIdx.x;
-    const int pr = blockIdx.x;
-    double *Wii = nullptr, *Wjj = nullptr, *Wij = nullptr;
-
-    if (MODE != SUB_PLAIN && a.force_skip && a.force_skip[pr]) {  // placeholder pair
-        if (tid == 0 && a.flags) a.flags[pr] = 1;
-        return;
+    // parameters of the first round
+    if (tid < H) {
+        const int up = slot_p(tid, 0, M2), uq = slot_q(tid, 0, M2);
+        rot_params(As[up * (LD + 1)], As[uq * (LD + 1)], As[min(up, uq) * LD + max(up, uq)], prm0, tid, H);
     }
+    group_sync<WAVE>();
 
-    // ---- load the upper triangle of A_hat into LDS (slot order) -----------
-    double off2 = 0.0, fro2 = 0.0;
-    const double *srcp = nullptr;
-    const float *Fii = nullptr, *Fjj = nullptr, *Fij = nullptr;
-    if (MODE == SUB_EIG) {
-        const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
-        if (a.ablk32) {
-            Fii = a.ablk32 + ublk(I, I) * (size_t)(B * B);
-            Fjj = a.ablk32 + ublk(J, J) * (size_t)(B * B);
-            Fij = a.ablk32 + ublk(I, J) * (size_t)(B * B);
-        } else {
-            Wii = a.ablk + ublk(I, I) * (size_t)(B * B);
-            Wjj = a.ablk + ublk(J, J) * (size_t)(B * B);
-            Wij = a.ablk + ublk(I, J) * (size_t)(B * B);
+    // This thread's pair-blocks (fixed for all rounds); their slots advance by
+    // one per round along 1 .. m2-1 (slot 0 stays), kept in registers.  Entry
+    // codes: 0 = (p1,p2), 1 = (p1,q2), 2 = (q1,p2), 3 = (q1,q2); member codes:
+    // 0 = p1, 1 = q1, 2 = p2, 3 = q2.  Packed: ikk = k1 | k2 << 8; icode =
+    // (stale + 1) | (kn + 1) << 3 | pivot entry << 10 | p' member << 12 |
+    // q' member << 14.
+    constexpr int MAXI = (NOFF + NT - 1) / NT;
+    static_assert(2 * H <= NT, "pivot pair-blocks must be first items");
+    int ikk[MAXI], isl[MAXI][4], icode[MAXI];
+#pragma unroll
+    for (int ii = 0; ii < MAXI; ++ii) {
+        const int it = tid + ii * NT;
+        int k1 = 0, d = 1;
+        if (it < H * (H / 2 - 1)) { d = it / H + 1; k1 = it - (d - 1) * H; }
+        else { d = H / 2; k1 = it - H * (H / 2 - 1); }
+        int k2 = k1 + d;
+        if (k2 >= H) k2 -= H;
+        const bool valid = it < NOFF;
+        if (!valid) { k1 = 0; k2 = 1; }
+        ikk[ii] = k1 | (k2 << 8);
+        isl[ii][0] = slot_p(k1, 0, M2);
+        isl[ii][1] = slot_q(k1, 0, M2);
+        isl[ii][2] = slot_p(k2, 0, M2);
+        isl[ii][3] = slot_q(k2, 0, M2);
+        const int lo = min(k1, k2), hi = max(k1, k2);
+        const bool fw = (k1 == lo);
+        // the previous round's pivot of pair k lies at (p of k-1, q of k+1) for
+        // 2 <= k <= H-2; pair 0: (p0, q1); pair 1: (q0, q2); pair H-1:
+        // (p(H-2), p(H-1))
+        int st = -1;
+        if (hi - lo == 2 && lo >= 1) st = fw ? 1 : 2;
+        else if (lo == 0 && hi == 2) st = 3;
+        else if (lo == 0 && hi == 1) st = fw ? 1 : 2;
+        else if (lo == H - 2 && hi == H - 1) st = 0;
+        // the next round's pivot of pair lo + 1 is (q_lo, p_hi); of pair 0,
+        // (p0, p1); of pair H-1, (q(H-2), q(H-1))
+        int kn = -1, pv = 0, mp = 0, mq = 0;
+        if (hi - lo == 2) {
+            kn = lo + 1; pv = fw ? 2 : 1; mp = fw ? 2 : 0; mq = fw ? 1 : 3;
+        } else if (lo == 0 && hi == 1) {
+            kn = 0; pv = 0; mp = fw ? 0 : 2; mq = fw ? 2 : 0;
+        } else if (lo == H - 2 && hi == H - 1) {
+            kn = H - 1; pv = 3; mp = fw ? 3 : 1; mq = fw ? 1 : 3;
         }
-    } else {
-        srcp = a.ahat + (size_t)pr * M2 * M2;
+        if (!valid) { st = -1; kn = -1; }
+        icode[ii] = (st + 1) | ((kn + 1) << 3) | (pv << 10) | (mp << 12) | (mq << 14);
     }
-    auto load = [&](int r, int c) -> double {
+
+    const double eps = 2.220446049250313e-16;
+    const int cap = conv ? 30 : nsw;
+    int gr = 0;  // rounds done (parameter buffer parity)
+    for (int swp = 0; swp < cap; ++swp) {
+        if (conv && swp > 0) {
+            double o = 0.0;
+            for (int e = tid; e < M2 * M2; e += NT) {
+                const int rr = e % M2, cc = e / M2;
+                if (rr < cc) { const double v = As[rr * LD + cc]; o += 2.0 * v * v; }
+            }
+            if constexpr (WAVE) o = wave_sum(o);
+            else o = block_sum<NT>(o, red);
+            if (sqrt(o) <= eps * sqrt(fro2)) break;
+        }
+        for (int t = 0; t < R; ++t, ++gr) {
+            const double *pc = prm0 + (gr & 1) * 4 * H;  // this round
+            double *pn = prm0 + ((gr + 1) & 1) * 4 * H;  // next round
+#pragma unroll
+            for (int ii = 0; ii < MAXI; ++ii) {
+                const bool valid = ii * NT + tid < NOFF;
+                const int k1 = ikk[ii] & 255, k2 = ikk[ii] >> 8;
+                const int code = icode[ii];
+                const int sp1 = isl[ii][0], sq1 = isl[ii][1], sp2 = isl[ii][2], sq2 = isl[ii][3];
+                const double c1 = pc[k1], s1 = pc[H + k1], c2 = pc[k2], s2 = pc[H + k2];
+                const int i11 = min(sp1, sp2) * LD + max(sp1, sp2);
+                const int i12 = min(sp1, sq2) * LD + max(sp1, sq2);
+                const int i21 = min(sq1, sp2) * LD + max(sq1, sp2);
+                const int i22 = min(sq1, sq2) * LD + max(sq1, sq2);
+                double x11 = As[i11], x12 = As[i12], x21 = As[i21], x22 = As[i22];
+                // producer operands (first item only; diagonal entries are
+                // written by their producer alone, never by an item)
+                const int kn = ((code >> 3) & 127) - 1;
+                const int pv = (code >> 10) & 3, mp = (code >> 12) & 3, mq = (code >> 14) & 3;
+                const int spn = mp == 0 ? sp1 : (mp == 1 ? sq1 : (mp == 2 ? sp2 : sq2));
+                const int sqn = mq == 0 ? sp1 : (mq == 1 ? sq1 : (mq == 2 ? sp2 : sq2));
+                const int pp = mp < 2 ? k1 : k2, pq_ = mq < 2 ? k1 : k2;
+                double dpo = 0.0, dqo = 0.0, tp = 0.0, tq = 0.0;
+                if (ii == 0) {
+                    dpo = As[spn * (LD + 1)];
+                    dqo = As[sqn * (LD + 1)];
+                    tp = pc[2 * H + pp] * pc[3 * H + pp];
+                    tq = pc[2 * H + pq_] * pc[3 * H + pq_];
+                }
+                if (ii == 0 && t > 0) {  // previous pivots: first item only (d <= 2)
+                    const int st = (code & 7) - 1;
+                    x11 = st == 0 ? 0.0 : x11;
+                    x12 = st == 1 ? 0.0 : x12;
+                    x21 = st == 2 ? 0.0 : x21;
+                    x22 = st == 3 ? 0.0 : x22;
+                }
+                // left: rows p1, q1; right: columns p2, q2
+                const double y11 = c1 * x11 - s1 * x21, y21 = s1 * x11 + c1 * x21;
+                const double y12 = c1 * x12 - s1 * x22, y22 = s1 * x12 + c1 * x22;
+                const double z11 = c2 * y11 - s2 * y12, z12 = s2 * y11 + c2 * y12;
+                const double z21 = c2 * y21 - s2 * y22, z22 = s2 * y21 + c2 * y22;
+                if (valid) {
+                    As[i11] = z11;
+                    As[i12] = z12;
+                    As[i21] = z21;
+                    As[i22] = z22;
+                }
+                if (ii == 0) {
+                    // diagonal of next round's pair kn after this round's
+                    // rotation (p-member a_pp - t a_pq, q-member a_qq + t a_pq),
+                    // then its parameters (computed by every lane, stored by producers)
+                    const double piv = pv == 0 ? z11 : (pv == 1 ? z12 : (pv == 2 ? z21 : z22));
+                    const double dp = dpo + ((mp & 1) ? tp : -tp);
+                    const double dq = dqo + ((mq & 1) ? tq : -tq);
+                    double cn, sn, tn;
+                    rot_cst(dp, dq, piv, cn, sn, tn);
+                    if (valid && kn >= 0) {
+                        As[spn * (LD + 1)] = dp;
+                        As[sqn * (LD + 1)] = dq;
+                        pn[kn] = cn;
+                        pn[H + kn] = sn;
+                        pn[2 * H + kn] = tn;
+                        pn[3 * H + kn] = piv;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int sl = isl[ii][m];
+                    isl[ii][m] = sl == 0 ? 0 : (sl == R ? 1 : sl + 1);
+                }
+            }
+            // V <- V J on this thread's P/2 position pairs, then one ring step
+#pragma unroll
+            for (int j = 0; j < P / 2; ++j) {
+                const int k = (P / 2) * g + j;
+                const double cc = pc[k], ss = pc[H + k];
+                const double e = V[2 * j], o = V[2 * j + 1];
+                V[2 * j] = cc * e - ss * o;
+                V[2 * j + 1] = ss * e + cc * o;
+            }
+            {
+                const double from_right = __shfl_down(V[0], 1, G);
+                const double from_left = __shfl_up(V[P - 1], 1, G);
+                const double e0 = V[0], e1 = V[2], olast = V[P - 1];
+#pragma unroll
+                for (int j = 0; j < P / 2 - 1; ++j) V[2 * j] = V[2 * j + 2];
+                V[P - 2] = (g < G - 1) ? from_right : olast;
+#pragma unroll
+                for (int j = P / 2 - 1; j > 0; --j) V[2 * j + 1] = V[2 * j - 1];
+                V[1] = (g > 0) ? from_left : e1;
+                if (g == 0) V[0] = e0;
+            }
+            group_sync<WAVE>();
+        }
+        // end of sweep: clear the last round's pivots (the diagonal is current)
+        if (tid < H) {
+            const int up = slot_p(tid, R - 1, M2), uq = slot_q(tid, R - 1, M2);
+            As[min(up, uq) * LD + max(up, uq)] = 0.0;
+        }
+        group_sync<WAVE>();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shared prologue and epilogue pieces
+// ---------------------------------------------------------------------------
+
+// Entry (r, c), r <= c, of this workgroup's A_hat in global memory.
+template <int M2, int MODE>
+struct HatSource {
+    static constexpr int B = M2 / 2;
+    const double *Wii = nullptr, *Wjj = nullptr, *Wij = nullptr, *src = nullptr;
+    const float *Fii = nullptr, *Fjj = nullptr, *Fij = nullptr;
+    __device__ HatSource(const SubArgs &a, int pr) {
+        if (MODE == SUB_EIG) {
+            const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
+            if (a.ablk32) {
+                Fii = a.ablk32 + ublk(I, I) * (size_t)(B * B);
+                Fjj = a.ablk32 + ublk(J, J) * (size_t)(B * B);
+                Fij = a.ablk32 + ublk(I, J) * (size_t)(B * B);
+            } else {
+                Wii = a.ablk + ublk(I, I) * (size_t)(B * B);
+                Wjj = a.ablk + ublk(J, J) * (size_t)(B * B);
+                Wij = a.ablk + ublk(I, J) * (size_t)(B * B);
+            }
+        } else {
+            src = a.ahat + (size_t)pr * M2 * M2;
+        }
+    }
+    __device__ double operator()(int r, int c) const {
         if (MODE == SUB_EIG) {
             if (Fii) {  // FP32 storage: the subproblem is still solved in FP64
                 if (c < B) return (double)Fii[c * B + r];
@@ -170,236 +401,119 @@ __global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
             if (r < B) return Wij[(c - B) * B + r];
             return Wjj[(c - B) * B + (r - B)];
         }
-        return srcp[(size_t)c * M2 + r];
-    };
-    for (int e = tid; e < M2 * M2; e += NT) {
-        const int r = e % M2, c = e / M2;
-        if (r > c) continue;
-        const double v = load(r, c);
-        const int u = slot_of(r, M2), w = slot_of(c, M2);
-        As[min(u, w) * LD + max(u, w)] = v;
-        if (r == c) fro2 += v * v;
-        else { off2 += 2.0 * v * v; fro2 += 2.0 * v * v; }
+        return src[(size_t)c * M2 + r];
+    }
+};
+
+// Skip test of a loaded subproblem; get(r, c) reads entry (r, c) from LDS.
+// Eigenproblem: skip when off(A_hat) <= skip_thr; Gram block of the SVD: skip
+// when max |a_ij| / sqrt(a_ii a_jj) <= skip_thr (zero columns count as
+// orthogonal).  Plain solves never skip.  Returns true when skipped.
+template <int M2, int NT, int MODE, class Get>
+__device__ bool skip_test(const SubArgs &a, int pr, double off2, double *red, Get get) {
+    if (MODE == SUB_PLAIN) return false;
+    const int tid = threadIdx.x;
+    double meas = sqrt(off2);
+    if (MODE == SUB_GRAM) {
+        __syncthreads();
+        double mx = 0.0;
+        for (int e = tid; e < M2 * M2; e += NT) {
+            const int rr = e % M2, cc = e / M2;
+            if (rr >= cc) continue;
+            const double dd = get(rr, rr) * get(cc, cc);
+            const double v = get(rr, cc);
+            if (dd > 0.0) mx = fmax(mx, fabs(v) / sqrt(dd));
+        }
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = mx;
+        __syncthreads();
+        mx = 0.0;
+        for (int i = 0; i < NT / 64; ++i) mx = fmax(mx, red[i]);
+        meas = mx;
+    }
+    if (tid == 0 && a.inner_off) a.inner_off[pr] = meas;
+    const bool skip = !(meas > a.skip_thr);
+    if (tid == 0 && a.flags) a.flags[pr] = skip ? 1 : 0;
+    if (tid == 0 && a.rot_count && !skip) atomicAdd(a.rot_count, 1);
+    return skip;
+}
+
+// Writes D_hat entry (rr, cc) to its place in the upper block storage
+// (entries of the lower triangle of the diagonal blocks are not stored).
+template <int M2>
+__device__ __forceinline__ void store_dhat(const SubArgs &a, size_t oii, size_t ojj, size_t oij, int rr, int cc,
+                                           double v) {
+    constexpr int B = M2 / 2;
+    size_t off;
+    if (cc < B) {
+        if (rr >= B) return;
+        off = oii + cc * B + rr;
+    } else if (rr < B) {
+        off = oij + (cc - B) * B + rr;
+    } else {
+        off = ojj + (cc - B) * B + (rr - B);
+    }
+    if (a.ablk32) a.ablk32[off] = (float)v;
+    else a.ablk[off] = v;
+}
+
+// ---------------------------------------------------------------------------
+// m2 = 32, 64: one workgroup runs the scalar sweeps on the whole subproblem
+// ---------------------------------------------------------------------------
+
+template <int M2>
+struct SubCfg {
+    static constexpr int H = M2 / 2, G = M2 / 16, NT = M2 * G, LD = M2;
+    static constexpr size_t LDS_BYTES = sizeof(double) * ((size_t)M2 * LD + 8 * H + NT / 64 + 2);
+};
+
+template <int M2, int MODE>
+__global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
+    using C = SubCfg<M2>;
+    constexpr int H = C::H, G = C::G, NT = C::NT, LD = C::LD, B = M2 / 2;
+    extern __shared__ double smem[];
+    double *As = smem;                    // M2 x LD slots
+    double *prm0 = As + (size_t)M2 * LD;  // rotation parameters, two rounds
+    double *red = prm0 + 8 * H;           // reduction scratch
+    const int tid = threadIdx.x, pr = blockIdx.x;
+
+    if (MODE != SUB_PLAIN && a.force_skip && a.force_skip[pr]) {  // placeholder pair
+        if (tid == 0 && a.flags) a.flags[pr] = 1;
+        return;
+    }
+    double off2 = 0.0, fro2 = 0.0;
+    {
+        const HatSource<M2, MODE> load(a, pr);
+        for (int e = tid; e < M2 * M2; e += NT) {
+            const int r = e % M2, c = e / M2;
+            if (r > c) continue;
+            const double v = load(r, c);
+            const int u = slot_of(r, M2), w = slot_of(c, M2);
+            As[min(u, w) * LD + max(u, w)] = v;
+            if (r == c) fro2 += v * v;
+            else { off2 += 2.0 * v * v; fro2 += 2.0 * v * v; }
+        }
     }
     off2 = block_sum<NT>(off2, red);
     fro2 = block_sum<NT>(fro2, red);
+    auto get = [&](int r, int c) {
+        const int u = slot_of(r, M2), w = slot_of(c, M2);
+        return As[min(u, w) * LD + max(u, w)];
+    };
+    if (skip_test<M2, NT, MODE>(a, pr, off2, red, get)) return;  // V_hat = I, A_hat unchanged
 
-    if (MODE != SUB_PLAIN) {
-        // eigenproblem: skip when off(A_hat) is small; Gram block of the SVD:
-        // skip when every column pair is nearly orthogonal,
-        // max |a_ij| / sqrt(a_ii a_jj) <= skip_thr (zero columns count as orthogonal)
-        double meas = sqrt(off2);
-        if (MODE == SUB_GRAM) {
-            __syncthreads();
-            double mx = 0.0;
-            for (int e = tid; e < M2 * M2; e += NT) {
-                const int rr = e % M2, cc = e / M2;
-                if (rr >= cc) continue;
-                const int u = slot_of(rr, M2), w = slot_of(cc, M2);
-                const double dd = As[u * (LD + 1)] * As[w * (LD + 1)];
-                const double v = As[min(u, w) * LD + max(u, w)];
-                if (dd > 0.0) mx = fmax(mx, fabs(v) / sqrt(dd));
-            }
-            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-            __syncthreads();
-            if ((tid & 63) == 0) red[tid >> 6] = mx;
-            __syncthreads();
-            mx = 0.0;
-            for (int i = 0; i < NT / 64; ++i) mx = fmax(mx, red[i]);
-            meas = mx;
-        }
-        if (tid == 0 && a.inner_off) a.inner_off[pr] = meas;
-        const bool skip = !(meas > a.skip_thr);
-        if (tid == 0 && a.flags) a.flags[pr] = skip ? 1 : 0;
-        if (tid == 0 && a.rot_count && !skip) atomicAdd(a.rot_count, 1);
-        if (skip) return;  // V_hat = I, A_hat unchanged
-    }
-
-    // ---- V_hat rows in position space -----------------------------------------
-    const int r = tid / G, g = tid - (tid / G) * G;
     double V[16];
-#pragma unroll
-    for (int x = 0; x < 16; ++x) V[x] = (r == 16 * g + x) ? 1.0 : 0.0;
+    scalar_sweeps<M2, NT, false>(As, prm0, red, tid, a.inner_sweeps > 0 ? a.inner_sweeps : 30,
+                                 a.inner_sweeps <= 0, fro2, V);
 
-    // parameters of the first round
-    if (tid < H) {
-        const int up = slot_p(tid, 0, M2), uq = slot_q(tid, 0, M2);
-        rot_params(As[up * (LD + 1)], As[uq * (LD + 1)], As[min(up, uq) * LD + max(up, uq)], prm0, tid, H);
-    }
-    __syncthreads();
-
-    // ---- this thread's pair-blocks (fixed for all rounds) ------------------------
-    // Slots of pair k advance by one per round along 1 .. m2-1 (slot 0 stays),
-    // so they are kept in registers.  sel codes: entry 0 = (p1,p2), 1 = (p1,q2),
-    // 2 = (q1,p2), 3 = (q1,q2); member codes: 0 = p1, 1 = q1, 2 = p2, 3 = q2.
-    constexpr int MAXI = (C::NOFF + NT - 1) / NT;
-    static_assert(2 * H <= NT, "pivot pair-blocks must be first items");
-    // packed per item: ikk = k1 | k2 << 8; icode = (stale + 1) | (kn + 1) << 3 |
-    // pivot entry << 10 | p' member << 12 | q' member << 14
-    int ikk[MAXI], isl[MAXI][4], icode[MAXI];
-#pragma unroll
-    for (int ii = 0; ii < MAXI; ++ii) {
-        const int it = tid + ii * NT;
-        int k1 = 0, d = 1;
-        if (it < H * (H / 2 - 1)) { d = it / H + 1; k1 = it - (d - 1) * H; }
-        else { d = H / 2; k1 = it - H * (H / 2 - 1); }
-        int k2 = k1 + d;
-        if (k2 >= H) k2 -= H;
-        const bool valid = it < C::NOFF;
-        if (!valid) { k1 = 0; k2 = 1; }
-        ikk[ii] = k1 | (k2 << 8);
-        isl[ii][0] = slot_p(k1, 0, M2);
-        isl[ii][1] = slot_q(k1, 0, M2);
-        isl[ii][2] = slot_p(k2, 0, M2);
-        isl[ii][3] = slot_q(k2, 0, M2);
-        const int lo = min(k1, k2), hi = max(k1, k2);
-        const bool fw = (k1 == lo);
-        // previous round's pivot lying in this pair-block
-        int st = -1;
-        if (hi - lo == 2 && lo >= 1) st = fw ? 1 : 2;          // (p_lo, q_hi)
-        else if (lo == 0 && hi == 2) st = 3;                    // (q0, q2)
-        else if (lo == 0 && hi == 1) st = fw ? 1 : 2;           // (p0, q1)
-        else if (lo == H - 2 && hi == H - 1) st = 0;            // (p(H-2), p(H-1))
-
-        // next round's pivot computed by this pair-block: pair kn, pivot entry,
-        // members p' (imp) and q' (imq)
-        int kn = -1, pv = 0, mp = 0, mq = 0;
-        if (hi - lo == 2) {                       // (q_lo, p_hi) -> pair lo + 1
-            kn = lo + 1;
-            pv = fw ? 2 : 1;
-            mp = fw ? 2 : 0;                      // p_hi
-            mq = fw ? 1 : 3;                      // q_lo
-        } else if (lo == 0 && hi == 1) {          // (p0, p1) -> pair 0
-            kn = 0; pv = 0;
-            mp = fw ? 0 : 2;                      // p0
-            mq = fw ? 2 : 0;                      // p1
-        } else if (lo == H - 2 && hi == H - 1) {  // (q(H-2), q(H-1)) -> pair H-1
-            kn = H - 1; pv = 3;
-            mp = fw ? 3 : 1;                      // q(H-1)
-            mq = fw ? 1 : 3;                      // q(H-2)
-        }
-        if (!valid) { st = -1; kn = -1; }
-        icode[ii] = (st + 1) | ((kn + 1) << 3) | (pv << 10) | (mp << 12) | (mq << 14);
-    }
-
-    const int nsw = a.inner_sweeps > 0 ? a.inner_sweeps : 30;
-    const double eps = 2.220446049250313e-16;
-    int gr = 0;  // rounds done (parameter buffer parity)
-    for (int swp = 0; swp < nsw; ++swp) {
-        if (a.inner_sweeps <= 0 && swp > 0) {
-            double o = 0.0;
-            for (int e = tid; e < M2 * M2; e += NT) {
-                const int rr = e % M2, cc = e / M2;
-                if (rr < cc) { const double v = As[rr * LD + cc]; o += 2.0 * v * v; }
-            }
-            o = block_sum<NT>(o, red);
-            if (sqrt(o) <= eps * sqrt(fro2)) break;
-        }
-        for (int t = 0; t < R; ++t, ++gr) {
-            const double *pc = prm0 + (gr & 1) * 4 * H;        // this round
-            double *pn = prm0 + ((gr + 1) & 1) * 4 * H;        // next round
-#pragma unroll
-            for (int ii = 0; ii < MAXI; ++ii) {
-                if (ii * NT + tid < C::NOFF) {
-                    const int k1 = ikk[ii] & 255, k2 = ikk[ii] >> 8;
-                    const int code = icode[ii];
-                    const int sp1 = isl[ii][0], sq1 = isl[ii][1], sp2 = isl[ii][2], sq2 = isl[ii][3];
-                    const double c1 = pc[k1], s1 = pc[H + k1], c2 = pc[k2], s2 = pc[H + k2];
-                    const int i11 = min(sp1, sp2) * LD + max(sp1, sp2);
-                    const int i12 = min(sp1, sq2) * LD + max(sp1, sq2);
-                    const int i21 = min(sq1, sp2) * LD + max(sq1, sp2);
-                    const int i22 = min(sq1, sq2) * LD + max(sq1, sq2);
-                    double x11 = As[i11], x12 = As[i12], x21 = As[i21], x22 = As[i22];
-                    // (pair-blocks holding a previous or next pivot all have
-                    // d <= 2, i.e. it < 2H <= NT: only the first item)
-                    if (ii == 0 && t > 0) {
-                        const int st = (code & 7) - 1;
-                        x11 = st == 0 ? 0.0 : x11;
-                        x12 = st == 1 ? 0.0 : x12;
-                        x21 = st == 2 ? 0.0 : x21;
-                        x22 = st == 3 ? 0.0 : x22;
-                    }
-                    // left: rows p1, q1; right: columns p2, q2
-                    const double y11 = c1 * x11 - s1 * x21, y21 = s1 * x11 + c1 * x21;
-                    const double y12 = c1 * x12 - s1 * x22, y22 = s1 * x12 + c1 * x22;
-                    const double z11 = c2 * y11 - s2 * y12, z12 = s2 * y11 + c2 * y12;
-                    const double z21 = c2 * y21 - s2 * y22, z22 = s2 * y21 + c2 * y22;
-                    As[i11] = z11;
-                    As[i12] = z12;
-                    As[i21] = z21;
-                    As[i22] = z22;
-                    const int kn = ((code >> 3) & 127) - 1;
-                    if (ii == 0 && kn >= 0) {
-                        // diagonal of the members of next round's pair kn after this
-                        // round's rotation (p-member: a_pp - t a_pq, q-member: a_qq + t a_pq)
-                        // and next round's parameters of pair kn
-                        const int pv = (code >> 10) & 3, mp = (code >> 12) & 3, mq = (code >> 14) & 3;
-                        const double piv = pv == 0 ? z11 : (pv == 1 ? z12 : (pv == 2 ? z21 : z22));
-                        const int sp_ = isl[ii][0] * (mp == 0) + isl[ii][1] * (mp == 1) + isl[ii][2] * (mp == 2) +
-                                        isl[ii][3] * (mp == 3);
-                        const int sq_ = isl[ii][0] * (mq == 0) + isl[ii][1] * (mq == 1) + isl[ii][2] * (mq == 2) +
-                                        isl[ii][3] * (mq == 3);
-                        const int pp = mp < 2 ? k1 : k2, pq_ = mq < 2 ? k1 : k2;
-                        const double tp = pc[2 * H + pp] * pc[3 * H + pp];
-                        const double tq = pc[2 * H + pq_] * pc[3 * H + pq_];
-                        const double dp = As[sp_ * (LD + 1)] + ((mp & 1) ? tp : -tp);
-                        const double dq = As[sq_ * (LD + 1)] + ((mq & 1) ? tq : -tq);
-                        As[sp_ * (LD + 1)] = dp;
-                        As[sq_ * (LD + 1)] = dq;
-                        rot_params(dp, dq, piv, pn, kn, H);
-                    }
-                }
-                // slots advance one step along the ring (slot 0 stays)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int sl = isl[ii][m];
-                    isl[ii][m] = sl == 0 ? 0 : (sl == R ? 1 : sl + 1);
-                }
-            }
-
-            // -- V_hat <- V_hat J on this thread's 8 position pairs
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int k = 8 * g + j;
-                const double cc = pc[k], ss = pc[H + k];
-                const double e = V[2 * j], o = V[2 * j + 1];
-                V[2 * j] = cc * e - ss * o;
-                V[2 * j + 1] = ss * e + cc * o;
-            }
-            // -- one ring step of the column content
-            {
-                const double from_right = __shfl_down(V[0], 1, G);
-                const double from_left = __shfl_up(V[15], 1, G);
-                const double e0 = V[0], e1 = V[2], o7 = V[15];
-#pragma unroll
-                for (int j = 0; j < 7; ++j) V[2 * j] = V[2 * j + 2];
-                V[14] = (g < G - 1) ? from_right : o7;
-#pragma unroll
-                for (int j = 7; j > 0; --j) V[2 * j + 1] = V[2 * j - 1];
-                V[1] = (g > 0) ? from_left : e1;
-                if (g == 0) V[0] = e0;
-            }
-            __syncthreads();
-        }
-        // end of sweep: clear the last round's pivots (the diagonal is current;
-        // positions equal indices again after m2 - 1 ring steps)
-        if (tid < H) {
-            const int up = slot_p(tid, R - 1, M2), uq = slot_q(tid, R - 1, M2);
-            As[min(up, uq) * LD + max(up, uq)] = 0.0;
-        }
-        __syncthreads();
-    }
-
-    // ---- results ------------------------------------------------------------
+    const int r = tid / G, g = tid - (tid / G) * G;
     if (MODE == SUB_PLAIN) {
         double *vo = a.vout + (size_t)pr * M2 * M2;
 #pragma unroll
         for (int x = 0; x < 16; ++x) vo[(size_t)(16 * g + x) * M2 + r] = V[x];
         double *dd = a.dout + (size_t)pr * M2 * M2;
-        for (int e = tid; e < M2 * M2; e += NT) {
-            const int u = slot_of(e % M2, M2), w = slot_of(e / M2, M2);
-            dd[e] = As[min(u, w) * LD + max(u, w)];
-        }
+        for (int e = tid; e < M2 * M2; e += NT) dd[e] = get(e % M2, e / M2);
     } else {
         if (a.vout32) {
             float *vo = a.vout32 + (size_t)pr * M2 * M2;
@@ -410,30 +524,257 @@ __global__ void __launch_bounds__(SubCfg<M2>::NT) k_subproblem(SubArgs a) {
 #pragma unroll
             for (int x = 0; x < 16; ++x) vo[vperm(r, 16 * g + x, M2)] = V[x];
         }
-        if (MODE == SUB_EIG) {
-            // A([I,J],[I,J]) <- D_hat (pointers recomputed: not kept live through the sweeps)
+        if (MODE == SUB_EIG) {  // A([I,J],[I,J]) <- D_hat
             const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
             const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
                          oij = ublk(I, J) * (size_t)(B * B);
             for (int e = tid; e < M2 * M2; e += NT) {
                 const int rr = e % M2, cc = e / M2;
-                const int u = slot_of(rr, M2), w = slot_of(cc, M2);
-                const double v = As[min(u, w) * LD + max(u, w)];
-                size_t off;
-                if (cc < B) {
-                    if (rr >= B) continue;
-                    off = oii + cc * B + rr;
-                } else if (rr < B) {
-                    off = oij + (cc - B) * B + rr;
-                } else {
-                    off = ojj + (cc - B) * B + (rr - B);
-                }
-                if (a.ablk32) a.ablk32[off] = (float)v;
-                else a.ablk[off] = v;
+                store_dhat<M2>(a, oii, ojj, oij, rr, cc, get(rr, cc));
             }
         }
     }
 }
+
+// ---------------------------------------------------------------------------
+// m2 = 128: two-level solver
+// ---------------------------------------------------------------------------
+// 512 threads (8 waves).  LDS: the upper triangle of A_hat packed row by row
+// (Ap), and per 32 x 32 pair problem a slot array, its rotation parameters
+// and its rotation W (row-major, stride 33).
+// V_hat is kept transposed in registers, Vt = V_hat^T: wave w owns columns
+// 16 w .. 16 w + 15 of Vt (rows of V_hat) as 8 MFMA result tiles of 16 rows.
+// Tile p holds the rows of the block at ring position p of the current round,
+// so block pair k (positions 2k, 2k+1) is always the tiles 2k, 2k+1; after
+// each round the tiles move one step along the block ring (7 steps: back to
+// block order).
+namespace tl {
+constexpr int M2 = 128, NB = 8, BS = 16, NT = 512;
+constexpr int AP = M2 * (M2 + 1) / 2;           // packed upper triangle
+constexpr int SW = 32 * 32 + 8 * 16 + 32 * 33;  // per pair problem: slots, parameters, W
+constexpr int WOFF = 32 * 32 + 8 * 16;          // offset of W in a solver region
+constexpr size_t LDS_BYTES = sizeof(double) * ((size_t)AP + 4 * SW + 16);
+__device__ __forceinline__ int pk(int i, int j) {  // i <= j
+    return i * (2 * M2 - 1 - i) / 2 + j;
+}
+__device__ __forceinline__ int pkm(int i, int j) { return i <= j ? pk(i, j) : pk(j, i); }
+}  // namespace tl
+
+template <int MODE>
+__global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
+    using namespace tl;
+    constexpr int B = M2 / 2;
+    extern __shared__ double smem[];
+    double *Ap = smem;
+    double *red = Ap + AP + 4 * SW;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = lane >> 4, x = lane & 15;
+    const int pr = blockIdx.x;
+
+    if (MODE != SUB_PLAIN && a.force_skip && a.force_skip[pr]) {  // placeholder pair
+        if (tid == 0 && a.flags) a.flags[pr] = 1;
+        return;
+    }
+    double off2 = 0.0, fro2 = 0.0;
+    {
+        const HatSource<M2, MODE> load(a, pr);
+        for (int e = tid; e < M2 * M2; e += NT) {
+            const int r = e % M2, c = e / M2;
+            if (r > c) continue;
+            const double v = load(r, c);
+            Ap[pk(r, c)] = v;
+            if (r == c) fro2 += v * v;
+            else { off2 += 2.0 * v * v; fro2 += 2.0 * v * v; }
+        }
+    }
+    off2 = block_sum<NT>(off2, red);
+    fro2 = block_sum<NT>(fro2, red);
+    auto get = [&](int r, int c) { return Ap[pkm(r, c)]; };
+    if (skip_test<M2, NT, MODE>(a, pr, off2, red, get)) return;
+
+    // Vt = I: tile tt, lane (g, x), component v holds Vt(16 tt + g + 4 v, 16 wv + x)
+    d4 vt[NB];
+#pragma unroll
+    for (int tt = 0; tt < NB; ++tt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) vt[tt][v] = (16 * tt + g + 4 * v == 16 * wv + x) ? 1.0 : 0.0;
+
+    const double eps = 2.220446049250313e-16;
+    const bool conv = a.inner_sweeps <= 0;
+    const int cap = conv ? 30 : a.inner_sweeps;
+    for (int swp = 0; swp < cap; ++swp) {
+        if (conv && swp > 0) {
+            double o = 0.0;
+            for (int e = tid; e < M2 * M2; e += NT) {
+                const int rr = e % M2, cc = e / M2;
+                if (rr < cc) { const double v = Ap[pk(rr, cc)]; o += 2.0 * v * v; }
+            }
+            o = block_sum<NT>(o, red);
+            if (sqrt(o) <= eps * sqrt(fro2)) break;
+        }
+        for (int t = 0; t < NB - 1; ++t) {
+            // ---- phase 1: waves k, k+4 diagonalise (one sweep) the 32 x 32
+            //      problem of block pair k (waves k and k+4 run on different
+            //      SIMDs, and so do the four waves holding the rotation
+            //      producers); local index l < 16 is row l of block ba,
+            //      l >= 16 row l - 16 of block bb
+            {
+                const int k = wv & 3, lt = ((wv >> 2) << 6) | lane;
+                double *S = Ap + AP + k * SW;  // slots
+                double *prm = S + 32 * 32;     // parameters
+                double *W = S + WOFF;          // rotation, row-major stride 33
+                const int ba = index_at(2 * k, t, NB), bb = index_at(2 * k + 1, t, NB);
+                for (int e = lt; e < 32 * 32; e += 128) {
+                    const int r = e & 31, c = e >> 5;
+                    if (r > c) continue;
+                    const int gr = r < BS ? BS * ba + r : BS * bb + (r - BS);
+                    const int gc = c < BS ? BS * ba + c : BS * bb + (c - BS);
+                    const int u = slot_of(r, 32), w = slot_of(c, 32);
+                    S[min(u, w) * 32 + max(u, w)] = Ap[pkm(gr, gc)];
+                }
+                __syncthreads();
+                double Vl[8];
+                scalar_sweeps<32, 128, false>(S, prm, nullptr, lt, 1, false, 0.0, Vl);
+                // W(r, 8 h + xx) = Vl[xx], r = lt / 4, h = lt mod 4; D back into A_hat
+                const int r = lt >> 2, h = lt & 3;
+#pragma unroll
+                for (int xx = 0; xx < 8; ++xx) W[r * 33 + 8 * h + xx] = Vl[xx];
+                for (int e = lt; e < 32 * 32; e += 128) {
+                    const int rr = e & 31, cc = e >> 5;
+                    if (rr > cc) continue;
+                    const int gr = rr < BS ? BS * ba + rr : BS * bb + (rr - BS);
+                    const int gc = cc < BS ? BS * ba + cc : BS * bb + (cc - BS);
+                    const int u = slot_of(rr, 32), w = slot_of(cc, 32);
+                    Ap[pkm(gr, gc)] = S[min(u, w) * 32 + max(u, w)];
+                }
+            }
+            __syncthreads();
+
+            // ---- phase 2a: waves 0..5, tile (p, q), p < q:
+            //      A_hat(p, q) <- W_p^T A_hat(p, q) W_q
+            if (wv < 6) {
+                const int p = wv < 3 ? 0 : (wv < 5 ? 1 : 2);
+                const int q = wv < 3 ? wv + 1 : (wv < 5 ? wv - 1 : 3);
+                const double *Wp = Ap + AP + p * SW + WOFF;
+                const double *Wq = Ap + AP + q * SW + WOFF;
+                const int pa = index_at(2 * p, t, NB), pb = index_at(2 * p + 1, t, NB);
+                const int qa = index_at(2 * q, t, NB), qb = index_at(2 * q + 1, t, NB);
+                auto gp = [&](int l) { return l < BS ? BS * pa + l : BS * pb + (l - BS); };
+                auto gq = [&](int l) { return l < BS ? BS * qa + l : BS * qb + (l - BS); };
+                // T = X W_q, X(i, k) = A_hat(gp(i), gq(k)); T[i][j] lane (g, x)
+                // component v = T(16 i + g + 4 v, 16 j + x)
+                d4 T[2][2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) T[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int k0 = 0; k0 < 32; k0 += 4) {
+                    const int k = k0 + g;
+                    const double b0 = Wq[k * 33 + x], b1 = Wq[k * 33 + 16 + x];
+                    const double a0 = Ap[pkm(gp(x), gq(k))], a1 = Ap[pkm(gp(16 + x), gq(k))];
+                    T[0][0] = mfma_f64(a0, b0, T[0][0]);
+                    T[0][1] = mfma_f64(a0, b1, T[0][1]);
+                    T[1][0] = mfma_f64(a1, b0, T[1][0]);
+                    T[1][1] = mfma_f64(a1, b1, T[1][1]);
+                }
+                // out = W_p^T T; step (ti, s) contracts over row 16 ti + g + 4 s of T
+                d4 O[2][2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) O[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = 16 * ti + g + 4 * s;
+                        const double a0 = Wp[k * 33 + x], a1 = Wp[k * 33 + 16 + x];
+                        O[0][0] = mfma_f64(a0, T[ti][0][s], O[0][0]);
+                        O[0][1] = mfma_f64(a0, T[ti][1][s], O[0][1]);
+                        O[1][0] = mfma_f64(a1, T[ti][0][s], O[1][0]);
+                        O[1][1] = mfma_f64(a1, T[ti][1][s], O[1][1]);
+                    }
+                // every read of this tile fed T, so it can be overwritten in place
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) Ap[pkm(gp(16 * i + g + 4 * v), gq(16 * j + x))] = O[i][j][v];
+            }
+
+            // ---- phase 2b: all waves, Vt rows of block pair k <- W_k^T (those rows)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double *Wk = Ap + AP + k * SW + WOFF;
+                d4 n0 = d4{0.0, 0.0, 0.0, 0.0}, n1 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int rr = 16 * ti + g + 4 * s;
+                        const double a0 = Wk[rr * 33 + x], a1 = Wk[rr * 33 + 16 + x];
+                        const double bv = vt[2 * k + ti][s];
+                        n0 = mfma_f64(a0, bv, n0);
+                        n1 = mfma_f64(a1, bv, n1);
+                    }
+                vt[2 * k] = n0;
+                vt[2 * k + 1] = n1;
+            }
+            __syncthreads();
+            // ---- tiles follow the block ring: 1 <- 2 <- 4 <- 6 <- 7 <- 5 <- 3 <- 1
+            {
+                const d4 o1 = vt[1];
+                vt[1] = vt[2];
+                vt[2] = vt[4];
+                vt[4] = vt[6];
+                vt[6] = vt[7];
+                vt[7] = vt[5];
+                vt[5] = vt[3];
+                vt[3] = o1;
+            }
+        }
+    }
+
+    // ---- results: V_hat(16 wv + x, 16 tt + g + 4 v) = vt[tt][v]
+    if (MODE == SUB_PLAIN) {
+        double *vo = a.vout + (size_t)pr * M2 * M2;
+#pragma unroll
+        for (int tt = 0; tt < NB; ++tt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) vo[(size_t)(16 * tt + g + 4 * v) * M2 + 16 * wv + x] = vt[tt][v];
+        double *dd = a.dout + (size_t)pr * M2 * M2;
+        for (int e = tid; e < M2 * M2; e += NT) dd[e] = Ap[pkm(e % M2, e / M2)];
+    } else {
+        if (a.vout32) {
+            float *vo = a.vout32 + (size_t)pr * M2 * M2;
+#pragma unroll
+            for (int tt = 0; tt < NB; ++tt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) vo[vperm32(16 * wv + x, 16 * tt + g + 4 * v, M2)] = (float)vt[tt][v];
+        } else {
+            double *vo = a.vout + (size_t)pr * M2 * M2;
+#pragma unroll
+            for (int tt = 0; tt < NB; ++tt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) vo[vperm(16 * wv + x, 16 * tt + g + 4 * v, M2)] = vt[tt][v];
+        }
+        if (MODE == SUB_EIG) {  // A([I,J],[I,J]) <- D_hat
+            const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
+            const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
+                         oij = ublk(I, J) * (size_t)(B * B);
+            for (int e = tid; e < M2 * M2; e += NT) {
+                const int rr = e % M2, cc = e / M2;
+                store_dhat<M2>(a, oii, ojj, oij, rr, cc, Ap[pkm(rr, cc)]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
 
 template <int M2, int MODE>
 static void launch_sub_t(const SubArgs &a, hipStream_t s) {
@@ -449,11 +790,23 @@ static void launch_sub_t(const SubArgs &a, hipStream_t s) {
 }
 
 template <int MODE>
+static void launch_sub2_t(const SubArgs &a, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_subproblem2<MODE>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl::LDS_BYTES));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_subproblem2<MODE>), dim3(a.count), dim3(tl::NT), tl::LDS_BYTES, s, a);
+    JX_LAUNCHED();
+}
+
+template <int MODE>
 static void launch_sub_m(const SubArgs &a, hipStream_t s) {
     switch (a.m2) {
         case 32: launch_sub_t<32, MODE>(a, s); break;
         case 64: launch_sub_t<64, MODE>(a, s); break;
-        case 128: launch_sub_t<128, MODE>(a, s); break;
+        case 128: launch_sub2_t<MODE>(a, s); break;
         default: set_error("subproblem order must be 32, 64 or 128"); throw HipFail{hipErrorInvalidValue};
     }
 }
