@@ -62,9 +62,10 @@ enum jacobi_prec {
 enum jacobi_dtype { JACOBI_F32 = 0, JACOBI_F64 = 1 };
 
 typedef struct {
-    double tol;           /* eig: stop when Xi(A) <= tol * ||A||_F (default 1e-14);
+    double tol;           /* 0 (default) = the routine's own default.
+                             eig: stop when Xi(A) <= tol * ||A||_F (1e-14);
                              svd: stop when every column pair has
-                             |g_i^T g_j| <= tol * |g_i| |g_j| (default sqrt(m) * eps) */
+                             |g_i^T g_j| <= tol * |g_i| |g_j| (sqrt(m) * eps) */
     int max_sweeps;       /* default 60 */
     int block;            /* b; 0 = default (64 for n > 512, smaller below) */
     int ordering;         /* enum jacobi_order */
@@ -76,7 +77,8 @@ typedef struct {
     int refine;           /* 1 = orthogonality refinement of Q/V (Newton-Schulz,
                              then a recomputed FP64 A = Q^T A0 Q or G = G0 V and
                              FP64 sweeps to tol); -1 = automatic (default: on
-                             for n >= 512 or mixed precision) */
+                             for n >= 256 -- eig: with eigenvectors -- and in
+                             mixed precision) */
     int sort;             /* 1 = eigenvalues ascending / sigma descending (default) */
     int want_vectors;     /* 0 = eigenvalues (singular values) only; default 1 */
 } jacobi_opts;
@@ -129,20 +131,61 @@ int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, 
 
 /*
  * Batched symmetric eigendecomposition of `batch` independent matrices of
- * orders h_n[k] (1 <= h_n[k] <= 256), one persistent launch.
- *   h_offA[k]  element offset of matrix k in dA and dQ (host array, int64);
- *              matrix k is column-major with leading dimension h_n[k]
+ * orders h_n[k] (0 <= h_n[k] <= 256; order 0 is skipped), one graph launch
+ * (spec addition: batching, not in the paper; the per-matrix method is
+ * the block Jacobi of §3 with the round-robin ordering, applied inside one
+ * workgroup).
+ *   h_n, h_offA  host arrays: orders and element offsets (int64) of matrix k in
+ *              dA and dQ; matrix k is column-major with leading dimension
+ *              h_n[k]; only its upper triangle is read
  *   dtype      JACOBI_F32 or JACOBI_F64: element type of dA
  *   dW         out: eigenvalues, matrix k at offset sum_{i<k} h_n[i]
- *   dQ         out: FP64 eigenvectors at the offsets h_offA
- *   dQ0        optional FP64 warm starts at the offsets h_offA (NULL = cold);
- *              a warm start that does not lower the off-norm is replaced by
- *              the cold start (info[k].fallback_used)
- *   info       NULL or an array of `batch` records
+ *              (ascending when opts->sort)
+ *   dQ         out: FP64 eigenvectors (columns) at the offsets h_offA; may be
+ *              NULL when opts->want_vectors == 0
+ *   dQ0        optional FP64 warm starts in the layout of dQ (NULL = cold): the
+ *              FP64 refinement starts from Q0 (two Newton-Schulz steps, then
+ *              Q0^T A Q0); a warm start that does not lower the off-norm is
+ *              replaced by the cold start (info[k].fallback_used = 1)
+ *   opts       tol (0 = 1e-14: off(A) <= tol ||A||_F per matrix), max_sweeps
+ *              (FP64 sweeps), block (0 = tuned per size bucket, or 8 / 16 =
+ *              the block size of the two-level scheme), precision
+ *              (JACOBI_PREC_FP64: FP64 sweeps only; otherwise an FP32 phase
+ *              precedes the FP64 refinement where the tuning table says so),
+ *              want_vectors, sort.  ordering, inner_max_sweeps and refine are
+ *              not used.
+ *   dWork      workspace of jacobi_eig_batched_workspace() bytes, or NULL (the
+ *              library allocates it; the graph is then not cached)
+ *   info       NULL or an array of `batch` records: status, sweeps,
+ *              sweeps_by_prec[1] (FP32) / [2] (FP64), fallback_used, off_rel
+ * Returns the largest per-matrix status (0, 1 not converged, 2 non-finite
+ * input), a negative argument index (1-based; -11 for opts->block), -100 for a
+ * short workspace, or 3 for a HIP error.  The graph (queue reset, then per
+ * size class a persistent FP32 kernel and a persistent FP64 kernel, classes on
+ * parallel streams) is cached for calls with the same sizes, offsets, pointers
+ * and options.
  */
 int jacobi_eig_batched(int batch, const int *h_n, const int64_t *h_offA, int dtype, const void *dA,
                        double *dW, double *dQ, const double *dQ0, void *dWork, size_t workBytes,
                        const jacobi_opts *opts, jacobi_info *info, jacobi_stream_t stream);
+
+/*
+ * Tuning table of jacobi_eig_batched: per element type and size bucket
+ * (0: n <= 32, 1: <= 64, 2: <= 128, 3: <= 192, 4: <= 256) the block size bs
+ * (8 or 16) and whether the FP32 phase runs (mixed).  The active table is the
+ * JSON file named by the environment variable JACOBI_TUNE_FILE when it parses
+ * and was written for the current device, else built-in defaults.
+ *   jacobi_batched_tuning: returns 1 (from the file), 0 (defaults) or -1.
+ *   jacobi_batched_autotune: times every (bs, mixed) candidate on a seeded
+ *     calibration batch of `per_bucket` random symmetric matrices per bucket
+ *     (fastest candidate whose every matrix converges), writes the table and
+ *     the timings as JSON to `path`, and makes it active for this process.
+ *     Returns 0, -1 (arguments), -4 (file not written) or 3 (HIP error).
+ *   jacobi_batched_graph_stats: cached-graph hits and graphs built so far.
+ */
+int jacobi_batched_tuning(int dtype, int bucket, int *bs, int *mixed);
+int jacobi_batched_autotune(int dtype, int per_bucket, unsigned seed, const char *path);
+int jacobi_batched_graph_stats(int *hits, int *builds);
 
 /* Text of the last error of the calling thread ("" if none). */
 const char *jacobi_last_error(void);

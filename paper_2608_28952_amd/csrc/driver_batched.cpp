@@ -1,0 +1,639 @@
+// driver_batched.cpp -- host side of jacobi_eig_batched: size classes, LPT
+// order, workspace layout, the captured hipGraph (one launch per call, cached),
+// per-matrix results, and the autotuner of the class parameters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <list>
+#include <mutex>
+#include <random>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "jx_common.hpp"
+#include "jx_host.hpp"
+
+namespace jx {
+
+namespace {
+
+constexpr int NBUCKET = 5;  // n in 1-32, 33-64, 65-128, 129-192, 193-256
+int bucket_of(int n) { return n <= 32 ? 0 : n <= 64 ? 1 : n <= 128 ? 2 : n <= 192 ? 3 : 4; }
+
+// Parameters of one size bucket: block size of the two-level scheme and
+// whether the FP32 phase runs before the FP64 refinement.
+struct Tune {
+    int bs;
+    int mixed;
+};
+
+struct TuneTable {
+    Tune t[2][NBUCKET];  // [dtype][bucket]
+    bool from_file = false;
+};
+
+TuneTable default_table() {
+    TuneTable d;
+    for (int dt = 0; dt < 2; ++dt)
+        for (int b = 0; b < NBUCKET; ++b) d.t[dt][b] = Tune{b <= 1 ? 8 : 16, 1};
+    return d;
+}
+
+std::mutex g_mu;
+TuneTable g_table = default_table();
+std::string g_table_src;  // path the active table was read from ("" = defaults)
+bool g_table_init = false;
+
+std::string device_key() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::ostringstream o;
+    o << p.gcnArchName << "/" << p.multiProcessorCount;
+    return o.str();
+}
+
+// Minimal reader of the cache format written by save_table (one JSON object).
+bool parse_table(const std::string &txt, TuneTable &out) {
+    auto find_int_list = [&](const std::string &key, std::vector<int> &v) {
+        const size_t k = txt.find("\"" + key + "\"");
+        if (k == std::string::npos) return false;
+        const size_t a = txt.find('[', k), b = txt.find(']', k);
+        if (a == std::string::npos || b == std::string::npos || b < a) return false;
+        std::stringstream ss(txt.substr(a + 1, b - a - 1));
+        std::string item;
+        v.clear();
+        while (std::getline(ss, item, ',')) {
+            char *end = nullptr;
+            const long x = std::strtol(item.c_str(), &end, 10);
+            if (end == item.c_str()) return false;
+            v.push_back((int)x);
+        }
+        return true;
+    };
+    const size_t kd = txt.find("\"device\"");
+    if (kd == std::string::npos) return false;
+    const size_t q1 = txt.find('"', txt.find(':', kd));
+    const size_t q2 = q1 == std::string::npos ? q1 : txt.find('"', q1 + 1);
+    if (q2 == std::string::npos || txt.substr(q1 + 1, q2 - q1 - 1) != device_key()) return false;
+    TuneTable t = default_table();
+    const char *names[2][2] = {{"f32_bs", "f32_mixed"}, {"f64_bs", "f64_mixed"}};
+    for (int dt = 0; dt < 2; ++dt) {
+        std::vector<int> bs, mx;
+        if (!find_int_list(names[dt][0], bs) || !find_int_list(names[dt][1], mx)) return false;
+        if ((int)bs.size() != NBUCKET || (int)mx.size() != NBUCKET) return false;
+        for (int b = 0; b < NBUCKET; ++b) {
+            if ((bs[b] != 8 && bs[b] != 16) || (mx[b] != 0 && mx[b] != 1)) return false;
+            t.t[dt][b] = Tune{bs[b], mx[b]};
+        }
+    }
+    t.from_file = true;
+    out = t;
+    return true;
+}
+
+std::string table_json(const TuneTable &t, const std::vector<double> &times) {
+    std::ostringstream o;
+    o << "{\n  \"device\": \"" << device_key() << "\",\n";
+    const char *names[2][2] = {{"f32_bs", "f32_mixed"}, {"f64_bs", "f64_mixed"}};
+    for (int dt = 0; dt < 2; ++dt) {
+        o << "  \"" << names[dt][0] << "\": [";
+        for (int b = 0; b < NBUCKET; ++b) o << (b ? ", " : "") << t.t[dt][b].bs;
+        o << "],\n  \"" << names[dt][1] << "\": [";
+        for (int b = 0; b < NBUCKET; ++b) o << (b ? ", " : "") << t.t[dt][b].mixed;
+        o << "],\n";
+    }
+    o << "  \"buckets\": \"1-32, 33-64, 65-128, 129-192, 193-256\",\n  \"calibration_ms\": [";
+    for (size_t i = 0; i < times.size(); ++i) o << (i ? ", " : "") << times[i];
+    o << "]\n}\n";
+    return o.str();
+}
+
+// The active table: the file named by JACOBI_TUNE_FILE when it parses and was
+// written for this device, else the defaults.
+TuneTable active_table() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const char *env = std::getenv("JACOBI_TUNE_FILE");
+    const std::string path = env ? env : "";
+    if (!g_table_init || path != g_table_src) {
+        g_table = default_table();
+        if (!path.empty()) {
+            std::ifstream f(path);
+            std::stringstream ss;
+            ss << f.rdbuf();
+            TuneTable t;
+            if (f && parse_table(ss.str(), t)) g_table = t;
+        }
+        g_table_src = path;
+        g_table_init = true;
+    }
+    return g_table;
+}
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct ClassPlan {
+    int bs, m2, mixed;
+    std::vector<int> ids;  // LPT order
+    size_t off_ids;        // element offset in the int arena
+};
+
+struct BatchPlan {
+    int batch;
+    std::vector<ClassPlan> classes;
+    std::vector<int64_t> offWs, offW;
+    size_t ws_elems = 0;  // sum of M2^2
+    bool any_mixed = false;
+    // workspace byte offsets
+    size_t o_int, o_i64, o_offrel, o_a32, o_q32, o_a64, o_q64, o_t64, o_u64, total;
+    size_t n_int;
+};
+
+BatchPlan make_plan(int batch, const int *h_n, int dtype, const jacobi_opts &o, const TuneTable &tt) {
+    BatchPlan p;
+    p.batch = batch;
+    p.offWs.assign(batch, 0);
+    p.offW.assign(batch, 0);
+    const int dt = dtype == JACOBI_F64 ? 1 : 0;
+    const bool allow_mixed = o.precision != JACOBI_PREC_FP64;
+    int64_t w = 0;
+    for (int k = 0; k < batch; ++k) {
+        p.offW[k] = w;
+        w += h_n[k];
+    }
+    for (int k = 0; k < batch; ++k) {
+        const int n = h_n[k];
+        if (n <= 0) continue;
+        Tune t = tt.t[dt][bucket_of(n)];
+        if (o.block == 8 || o.block == 16) t.bs = o.block;
+        const int mixed = allow_mixed ? t.mixed : 0;
+        const int pp = 2 * t.bs;
+        const int m2 = (n + pp - 1) / pp * pp;
+        int ci = -1;
+        for (size_t c = 0; c < p.classes.size(); ++c)
+            if (p.classes[c].bs == t.bs && p.classes[c].m2 == m2 && p.classes[c].mixed == mixed) ci = (int)c;
+        if (ci < 0) {
+            p.classes.push_back(ClassPlan{t.bs, m2, mixed, {}, 0});
+            ci = (int)p.classes.size() - 1;
+        }
+        p.classes[ci].ids.push_back(k);
+        if (mixed) p.any_mixed = true;
+    }
+    // LPT: classes by decreasing order, matrices by decreasing n (stable)
+    std::sort(p.classes.begin(), p.classes.end(), [](const ClassPlan &a, const ClassPlan &b) { return a.m2 > b.m2; });
+    size_t ints = 0;
+    for (auto &c : p.classes) {
+        std::stable_sort(c.ids.begin(), c.ids.end(), [&](int a, int b) { return h_n[a] > h_n[b]; });
+        c.off_ids = ints;
+        ints += c.ids.size();
+        for (int k : c.ids) {
+            p.offWs[k] = (int64_t)p.ws_elems;
+            p.ws_elems += (size_t)c.m2 * c.m2;
+        }
+    }
+    // int arena: ids | n | stat (4 per matrix) | queues (64 ints per class)
+    p.n_int = ints + batch + 4 * (size_t)batch + 64 * p.classes.size();
+    WorkspaceBuilder wb;
+    p.o_int = wb.add(sizeof(int) * p.n_int);
+    p.o_i64 = wb.add(sizeof(int64_t) * 3 * (size_t)batch);
+    p.o_offrel = wb.add(sizeof(double) * batch);
+    const size_t e = std::max<size_t>(p.ws_elems, 1);
+    p.o_a32 = p.any_mixed ? wb.add(sizeof(float) * e) : 0;
+    p.o_q32 = p.any_mixed ? wb.add(sizeof(float) * e) : 0;
+    p.o_a64 = wb.add(sizeof(double) * e);
+    p.o_q64 = wb.add(sizeof(double) * e);
+    p.o_t64 = wb.add(sizeof(double) * e);
+    p.o_u64 = wb.add(sizeof(double) * e);
+    p.total = wb.total();
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Graph cache
+// ---------------------------------------------------------------------------
+struct GraphEntry {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::list<GraphEntry> g_graphs;  // most recent first
+constexpr size_t GRAPH_CACHE = 8;
+int g_graph_hits = 0, g_graph_builds = 0;
+
+std::string graph_key(const BatchPlan &p, const int *h_n, const int64_t *h_off, int dtype, const void *dA,
+                      const double *dW, const double *dQ, const double *dQ0, const char *ws, const jacobi_opts &o) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    for (int k = 0; k < p.batch; ++k) {
+        mix((uint64_t)h_n[k]);
+        mix((uint64_t)h_off[k]);
+    }
+    for (const auto &c : p.classes) {
+        mix((uint64_t)c.bs);
+        mix((uint64_t)c.mixed);
+    }
+    std::ostringstream k;
+    k << p.batch << ":" << h << ":" << dtype << ":" << dA << ":" << dW << ":" << dQ << ":" << dQ0 << ":"
+      << (const void *)ws << ":" << o.tol << ":" << o.max_sweeps << ":" << o.want_vectors << ":" << o.sort;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    k << ":dev" << dev;
+    return k.str();
+}
+
+// Enqueue the whole batched solve on `cs` (captured): queue reset, then per
+// class [low-precision phase] -> FP64 refinement.  Everything goes to the one
+// capturing stream, so every node of the graph is ordered after the reset;
+// each persistent class kernel fills the GPU by itself.
+struct Grids {
+    int lp, hp;
+};
+
+// Persistent grid sizes per class (queried before any capture).
+std::vector<Grids> class_grids(const BatchPlan &p, bool warm) {
+    int cus = 0, dev = 0;
+    JX_HIP(hipGetDevice(&dev));
+    JX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    std::vector<Grids> g;
+    for (const auto &c : p.classes) {
+        const int cnt = (int)c.ids.size();
+        Grids x{0, 0};
+        if (c.mixed && !warm) x.lp = std::min(cnt, std::max(1, batched_blocks_per_cu(c.bs, c.m2, true)) * cus);
+        x.hp = std::min(cnt, std::max(1, batched_blocks_per_cu(c.bs, c.m2, false)) * cus);
+        g.push_back(x);
+    }
+    return g;
+}
+
+void record_batch(const BatchPlan &p, const std::vector<Grids> &grids, int dtype, const void *dA, double *dW,
+                  double *dQ, const double *dQ0, char *ws, const jacobi_opts &o, double tol, hipStream_t cs) {
+    int *ints = reinterpret_cast<int *>(ws + p.o_int);
+    int *n_arr = ints + (p.n_int - 64 * p.classes.size() - 4 * (size_t)p.batch - p.batch);
+    int *stat = n_arr + p.batch;
+    int *queues = stat + 4 * (size_t)p.batch;
+    const int64_t *i64 = reinterpret_cast<const int64_t *>(ws + p.o_i64);
+
+    launch_fill_int(stat, 4 * p.batch, 0, cs);
+    launch_fill_int(queues, 64 * (int)p.classes.size(), 0, cs);
+    const size_t nc = p.classes.size();
+    for (size_t c = 0; c < nc; ++c) {
+        const ClassPlan &cp = p.classes[c];
+        hipStream_t s = cs;
+        BatchArgs a{};
+        a.count = (int)cp.ids.size();
+        a.m2 = cp.m2;
+        a.ids = ints + cp.off_ids;
+        a.n = n_arr;
+        a.offA = i64;
+        a.offW = i64 + p.batch;
+        a.offWs = i64 + 2 * (size_t)p.batch;
+        a.dtype = dtype;
+        a.A_in = dA;
+        a.Q0 = dQ0;
+        a.A32 = p.any_mixed ? reinterpret_cast<float *>(ws + p.o_a32) : nullptr;
+        a.Q32 = p.any_mixed ? reinterpret_cast<float *>(ws + p.o_q32) : nullptr;
+        a.A64 = reinterpret_cast<double *>(ws + p.o_a64);
+        a.Q64 = reinterpret_cast<double *>(ws + p.o_q64);
+        a.T64 = reinterpret_cast<double *>(ws + p.o_t64);
+        a.U64 = reinterpret_cast<double *>(ws + p.o_u64);
+        a.W_out = dW;
+        a.Q_out = dQ;
+        a.queue = queues + 64 * c;
+        a.stat = stat;
+        a.offrel = reinterpret_cast<double *>(ws + p.o_offrel);
+        a.tol = tol;
+        a.max_sweeps = o.max_sweeps;
+        a.lp_max_sweeps = grids[c].lp > 0 ? 30 : 0;
+        a.lp_switch = 1e-5;
+        a.want_vectors = o.want_vectors;
+        a.sort = o.sort;
+        if (grids[c].lp > 0) {
+            launch_batched_lp(a, cp.bs, grids[c].lp, s);
+            launch_fill_int(a.queue, 1, 0, s);
+        }
+        launch_batched_hp(a, cp.bs, grids[c].hp, s);
+    }
+}
+
+int run_batched(int batch, const int *h_n, const int64_t *h_off, int dtype, const void *dA, double *dW, double *dQ,
+                const double *dQ0, void *dWork, size_t workBytes, const jacobi_opts &o, jacobi_info *info,
+                hipStream_t stream, const TuneTable &tt) {
+    const auto t0 = std::chrono::steady_clock::now();
+    BatchPlan p = make_plan(batch, h_n, dtype, o, tt);
+    if (p.classes.empty()) {  // nothing of positive order: no device work
+        for (int k = 0; k < batch && info; ++k) {
+            info[k] = jacobi_info{};
+            info[k].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return 0;
+    }
+    DeviceBuffer own;
+    char *ws = static_cast<char *>(dWork);
+    if (!ws) {
+        own.alloc(p.total);
+        ws = own.ptr;
+    } else if (workBytes < p.total) {
+        return -100;
+    }
+    const double tol = o.tol > 0.0 ? o.tol : 1e-14;
+
+    // plan arrays -> device (ordered before the graph on `stream`)
+    std::vector<int> ints(p.n_int, 0);
+    for (const auto &c : p.classes) std::copy(c.ids.begin(), c.ids.end(), ints.begin() + c.off_ids);
+    const size_t n_at = p.n_int - 64 * p.classes.size() - 4 * (size_t)batch - batch;
+    for (int k = 0; k < batch; ++k) ints[n_at + k] = h_n[k];
+    std::vector<int64_t> i64(3 * (size_t)batch);
+    for (int k = 0; k < batch; ++k) {
+        i64[k] = h_off[k];
+        i64[batch + k] = p.offW[k];
+        i64[2 * (size_t)batch + k] = p.offWs[k];
+    }
+    JX_HIP(hipMemcpyAsync(ws + p.o_int, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, stream));
+    JX_HIP(hipMemcpyAsync(ws + p.o_i64, i64.data(), sizeof(int64_t) * i64.size(), hipMemcpyHostToDevice, stream));
+    JX_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope below
+
+    if (!p.classes.empty()) {
+        // One graph launch per call.  Graphs on caller-owned workspaces are
+        // cached (their key holds every pointer and size they embed); a graph
+        // on library-owned memory is used once.
+        const std::vector<Grids> grids = class_grids(p, dQ0 != nullptr);
+        const bool cacheable = own.ptr == nullptr;
+        const std::string key = graph_key(p, h_n, h_off, dtype, dA, dW, dQ, dQ0, ws, o);
+        std::lock_guard<std::mutex> lk(g_mu);
+        hipGraphExec_t exec = nullptr;
+        if (cacheable)
+            for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+                if (it->key == key) {
+                    g_graphs.splice(g_graphs.begin(), g_graphs, it);
+                    exec = g_graphs.front().exec;
+                    ++g_graph_hits;
+                    break;
+                }
+        GraphEntry ge;
+        if (!exec) {
+            hipStream_t cs;
+            JX_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            ge.key = key;
+            JX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                record_batch(p, grids, dtype, dA, dW, dQ, dQ0, ws, o, tol, cs);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipStreamDestroy(cs);
+                throw;
+            }
+            JX_HIP(hipStreamEndCapture(cs, &ge.graph));
+            JX_HIP(hipStreamDestroy(cs));
+            JX_HIP(hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+            ++g_graph_builds;
+            exec = ge.exec;
+            if (cacheable) {
+                g_graphs.push_front(ge);
+                while (g_graphs.size() > GRAPH_CACHE) {
+                    (void)hipGraphExecDestroy(g_graphs.back().exec);
+                    (void)hipGraphDestroy(g_graphs.back().graph);
+                    g_graphs.pop_back();
+                }
+            }
+        }
+        JX_HIP(hipGraphLaunch(exec, stream));
+        if (!cacheable) {
+            JX_HIP(hipStreamSynchronize(stream));
+            (void)hipGraphExecDestroy(ge.exec);
+            (void)hipGraphDestroy(ge.graph);
+        }
+    }
+    JX_HIP(hipStreamSynchronize(stream));
+
+    std::vector<int> stat(4 * (size_t)batch, 0);
+    std::vector<double> offrel(batch, 0.0);
+    if (batch > 0) {
+        const size_t stat_at = n_at + batch;
+        JX_HIP(hipMemcpy(stat.data(), ws + p.o_int + sizeof(int) * stat_at, sizeof(int) * stat.size(),
+                         hipMemcpyDeviceToHost));
+        JX_HIP(hipMemcpy(offrel.data(), ws + p.o_offrel, sizeof(double) * batch, hipMemcpyDeviceToHost));
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = 0;
+    for (int k = 0; k < batch; ++k) {
+        int st = h_n[k] <= 0 ? 0 : stat[4 * k + 2];
+        worst = std::max(worst, st);
+        if (info) {
+            jacobi_info &f = info[k];
+            f.status = st;
+            f.sweeps_by_prec[0] = 0;
+            f.sweeps_by_prec[1] = h_n[k] > 0 ? stat[4 * k + 0] : 0;
+            f.sweeps_by_prec[2] = h_n[k] > 0 ? stat[4 * k + 1] : 0;
+            f.sweeps = f.sweeps_by_prec[1] + f.sweeps_by_prec[2];
+            f.fallback_used = h_n[k] > 0 ? stat[4 * k + 3] : 0;
+            f.off_rel = h_n[k] > 0 ? offrel[k] : 0.0;
+            f.seconds = secs;
+        }
+    }
+    return worst;
+}
+
+// Validation shared by the entry point and the workspace query.
+int check_args(int batch, const int *h_n, const int64_t *h_off, int dtype) {
+    if (batch < 0) return -1;
+    if (batch > 0 && !h_n) return -2;
+    for (int k = 0; k < batch; ++k)
+        if (h_n[k] < 0 || h_n[k] > 256) return -2;
+    if (batch > 0 && !h_off) return -3;
+    for (int k = 0; k < batch && h_off; ++k)
+        if (h_off[k] < 0) return -3;
+    if (dtype != JACOBI_F32 && dtype != JACOBI_F64) return -4;
+    return 0;
+}
+
+jacobi_opts resolve_b(const jacobi_opts *o) {
+    jacobi_opts r;
+    jacobi_opts_default(&r);
+    if (o) r = *o;
+    if (!(r.tol > 0.0)) r.tol = 0.0;
+    if (r.max_sweeps <= 0) r.max_sweeps = 60;
+    return r;
+}
+
+}  // namespace
+
+}  // namespace jx
+
+using namespace jx;
+
+extern "C" {
+
+size_t jacobi_eig_batched_workspace(int batch, const int *h_n, int dtype, const jacobi_opts *o) {
+    if (batch < 0 || (batch > 0 && !h_n) || (dtype != JACOBI_F32 && dtype != JACOBI_F64)) return 256;
+    for (int k = 0; k < batch; ++k)
+        if (h_n[k] < 0 || h_n[k] > 256) return 256;
+    const jacobi_opts r = resolve_b(o);
+    TuneTable tt;
+    try {
+        tt = active_table();
+    } catch (...) {
+        tt = default_table();
+    }
+    return make_plan(batch, h_n, dtype, r, tt).total;
+}
+
+int jacobi_eig_batched(int batch, const int *h_n, const int64_t *h_offA, int dtype, const void *dA, double *dW,
+                       double *dQ, const double *dQ0, void *dWork, size_t workBytes, const jacobi_opts *opts,
+                       jacobi_info *info, jacobi_stream_t stream) {
+    set_error("");
+    int rc = check_args(batch, h_n, h_offA, dtype);
+    const jacobi_opts o = resolve_b(opts);
+    if (rc == 0 && batch > 0 && !dA) rc = -5;
+    if (rc == 0 && batch > 0 && !dW) rc = -6;
+    if (rc == 0 && batch > 0 && o.want_vectors && !dQ) rc = -7;
+    if (rc == 0 && opts && opts->block != 0 && opts->block != 8 && opts->block != 16) rc = -11;
+    if (rc != 0) {
+        set_error("jacobi_eig_batched: invalid argument " + std::to_string(-rc));
+        if (info)
+            for (int k = 0; k < batch; ++k) info[k].status = rc;
+        return rc;
+    }
+    try {
+        const TuneTable tt = active_table();
+        rc = run_batched(batch, h_n, h_offA, dtype, dA, dW, o.want_vectors ? dQ : nullptr, dQ0, dWork, workBytes, o,
+                         info, (hipStream_t)stream, tt);
+        if (rc == -100) set_error("workspace too small");
+        return rc;
+    } catch (const HipFail &) {
+        if (info)
+            for (int k = 0; k < batch; ++k) info[k].status = 3;
+        return 3;
+    }
+}
+
+int jacobi_batched_tuning(int dtype, int bucket, int *bs, int *mixed) {
+    if ((dtype != JACOBI_F32 && dtype != JACOBI_F64) || bucket < 0 || bucket >= NBUCKET || !bs || !mixed) return -1;
+    TuneTable t;
+    try {
+        t = active_table();
+    } catch (...) {
+        return 3;
+    }
+    const Tune &x = t.t[dtype == JACOBI_F64 ? 1 : 0][bucket];
+    *bs = x.bs;
+    *mixed = x.mixed;
+    return t.from_file ? 1 : 0;
+}
+
+int jacobi_batched_graph_stats(int *hits, int *builds) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (hits) *hits = g_graph_hits;
+    if (builds) *builds = g_graph_builds;
+    return 0;
+}
+
+int jacobi_batched_autotune(int dtype, int per_bucket, unsigned seed, const char *path) {
+    if ((dtype != JACOBI_F32 && dtype != JACOBI_F64) || per_bucket <= 0 || !path) return -1;
+    set_error("");
+    try {
+        const int lo[NBUCKET] = {1, 33, 65, 129, 193}, hi[NBUCKET] = {32, 64, 128, 192, 256};
+        TuneTable best = active_table();
+        const int dt = dtype == JACOBI_F64 ? 1 : 0;
+        std::vector<double> times;
+        std::mt19937_64 rng(seed);
+        hipStream_t s;
+        JX_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        for (int b = 0; b < NBUCKET; ++b) {
+            // calibration batch: sizes uniform in the bucket, entries N(0,1), symmetric
+            std::vector<int> ns(per_bucket);
+            std::vector<int64_t> off(per_bucket);
+            int64_t tot = 0;
+            std::uniform_int_distribution<int> un(lo[b], hi[b]);
+            for (int k = 0; k < per_bucket; ++k) {
+                ns[k] = un(rng);
+                off[k] = tot;
+                tot += (int64_t)ns[k] * ns[k];
+            }
+            std::normal_distribution<double> nd(0.0, 1.0);
+            std::vector<double> h64(tot);
+            for (int k = 0; k < per_bucket; ++k) {
+                const int n = ns[k];
+                for (int j = 0; j < n; ++j)
+                    for (int i = 0; i <= j; ++i) {
+                        const double v = nd(rng);
+                        h64[off[k] + (int64_t)j * n + i] = v;
+                        h64[off[k] + (int64_t)i * n + j] = v;
+                    }
+            }
+            std::vector<float> h32(h64.begin(), h64.end());
+            const size_t esz = dtype == JACOBI_F64 ? 8 : 4;
+            DeviceBuffer dA, dW, dQ;
+            int64_t wtot = 0;
+            for (int k = 0; k < per_bucket; ++k) wtot += ns[k];
+            dA.alloc(esz * tot);
+            dW.alloc(sizeof(double) * wtot);
+            dQ.alloc(sizeof(double) * tot);
+            JX_HIP(hipMemcpy(dA.ptr, dtype == JACOBI_F64 ? (const void *)h64.data() : (const void *)h32.data(),
+                             esz * tot, hipMemcpyHostToDevice));
+            double best_ms = 1e300;
+            for (int bs : {8, 16})
+                for (int mixed : {1, 0}) {
+                    TuneTable cand = best;
+                    cand.t[dt][b] = Tune{bs, mixed};
+                    jacobi_opts o;
+                    jacobi_opts_default(&o);
+                    o.precision = JACOBI_PREC_MIXED_FP32;
+                    BatchPlan p = make_plan(per_bucket, ns.data(), dtype, o, cand);
+                    DeviceBuffer ws;
+                    ws.alloc(p.total);
+                    std::vector<jacobi_info> inf(per_bucket);
+                    double ms = 1e300;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        const auto t0 = std::chrono::steady_clock::now();
+                        const int rc = run_batched(per_bucket, ns.data(), off.data(), dtype, dA.ptr, (double *)dW.ptr,
+                                                   (double *)dQ.ptr, nullptr, ws.ptr, p.total, o, inf.data(), s, cand);
+                        const double t = std::chrono::duration<double, std::milli>(
+                                             std::chrono::steady_clock::now() - t0)
+                                             .count();
+                        if (rc != 0) {
+                            ms = 1e300;  // a candidate that misses the accuracy is never chosen
+                            break;
+                        }
+                        if (rep > 0) ms = std::min(ms, t);
+                    }
+                    times.push_back(ms >= 1e300 ? -1.0 : ms);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best.t[dt][b] = Tune{bs, mixed};
+                    }
+                }
+        }
+        JX_HIP(hipStreamDestroy(s));
+        // the other dtype keeps its current entries
+        std::ofstream f(path);
+        f << table_json(best, times);
+        f.close();
+        if (!f) {
+            set_error(std::string("jacobi_batched_autotune: cannot write ") + path);
+            return -4;
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_table = best;
+        g_table.from_file = true;
+        g_table_src = std::getenv("JACOBI_TUNE_FILE") ? std::getenv("JACOBI_TUNE_FILE") : "";
+        g_table_init = true;
+        return 0;
+    } catch (const HipFail &) {
+        return 3;
+    }
+}
+
+}  // extern "C"

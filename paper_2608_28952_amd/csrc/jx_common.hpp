@@ -134,6 +134,41 @@ struct SubArgs {
 };
 void launch_subproblem(const SubArgs &a, hipStream_t s);
 
+// Batched solver (k_batched.hip): one persistent launch per size class.  A
+// class holds the matrices whose order pads to M2 = 2 * bs * npp (npp pair
+// problems of order 2 bs per middle round); every matrix has its own padded
+// M2 x M2 column-major workspace (A and Q in the phase's type, two FP64
+// temporaries for the refinement GEMMs).
+struct BatchArgs {
+    int count;               // matrices of this class
+    int m2;                  // padded order
+    const int *ids;          // class-local order (LPT: n descending) -> matrix id
+    const int *n;            // per matrix id: order
+    const int64_t *offA;     // per matrix id: element offset in A_in / Q_out (ld = n)
+    const int64_t *offW;     // per matrix id: offset in W_out
+    const int64_t *offWs;    // per matrix id: element offset of its M2 x M2 workspace slots
+    int dtype;               // JACOBI_F32 / JACOBI_F64 (A_in)
+    const void *A_in;
+    const double *Q0;        // optional warm starts (layout of Q_out)
+    float *A32, *Q32;        // FP32 phase
+    double *A64, *Q64, *T64, *U64;  // FP64 phase
+    double *W_out, *Q_out;
+    int *queue;              // [0]: next class-local slot (zeroed before the launch)
+    int *stat;               // per matrix id: sweeps32, sweeps64, status, fallback
+    double *offrel;          // per matrix id: final off(A) / ||A||_F
+    double tol;              // FP64 stop: off(A) <= tol ||A||_F
+    int max_sweeps;          // FP64 sweeps
+    int lp_max_sweeps;       // FP32 sweeps (0: no FP32 phase)
+    double lp_switch;        // FP32 phase ends at off(A) <= lp_switch ||A||_F
+    int want_vectors, sort;
+};
+void launch_batched_lp(const BatchArgs &a, int bs, int grid, hipStream_t s);
+void launch_batched_hp(const BatchArgs &a, int bs, int grid, hipStream_t s);
+void launch_fill_int(int *p, int count, int value, hipStream_t s);
+int batched_threads(int bs, int m2);      // threads of the class kernel
+int batched_blocks_per_cu(int bs, int m2, bool lp);  // resident workgroups per CU
+size_t batched_lds_bytes(int bs, int m2); // dynamic LDS of the class kernel
+
 // Fused two-sided update of the off-diagonal pair tiles of one round:
 // A[p,q] <- V_p^T A[p,q] V_q for p < q (pair indices of the round).
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,

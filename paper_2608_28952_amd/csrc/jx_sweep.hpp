@@ -1,0 +1,353 @@
+// jx_sweep.hpp -- round-robin scalar Jacobi held in LDS, shared by the
+// subproblem solver (k_subproblem.hip) and the batched solver (k_batched.hip).
+//
+// Scalar rotation (symmetric Schur form): with theta = (a_qq - a_pp) / (2 a_pq),
+// t = sgn(theta) / (|theta| + sqrt(1 + theta^2)), c = 1 / sqrt(1 + t^2), s = t c,
+// the plane rotation J = [[c, s], [-s, c]] on (p, q) gives J^T A J a zero
+// (p, q) entry and diagonal a_pp - t a_pq, a_qq + t a_pq (Golub & Van Loan
+// §8.5.2).
+//
+// Data placement of the scalar sweeps
+//   * A: LDS, upper triangle, row stride m2.  Index x sits at slot pi(x) =
+//     ring order (pi(0) = 0, pi(x) = 1 + ring index of x): in round t the
+//     members of consecutive pairs sit at consecutive slots, so the lanes of a
+//     wave touch addresses with odd strides (m2 + 1, m2 - 1): no bank conflicts.
+//   * V: registers; thread (r, g) holds row r of V at P consecutive
+//     positions P g .. P g + P - 1.  Positions are paired (2k, 2k+1) every round; after a
+//     round the column content moves one step along the ring
+//     1 <- 2 <- 4 <- ... <- m2-2 <- m2-1 <- m2-3 <- ... <- 3 <- 1 (0 stays), so
+//     that every index pair meets once per sweep; two values per thread cross
+//     to the neighbouring lane.  After m2 - 1 rounds positions equal indices.
+//   * Rotation parameters (c, s, t, a_pq per pair): LDS, two rounds.  The
+//     pivot a_pq of a round becomes zero and is not written: in the next round
+//     it lies in a known pair-block, which reads it as zero.  The pair-blocks
+//     that compute the next round's pivots also update the two diagonal
+//     entries of that pair and write the next round's parameters, so a round
+//     needs one barrier.
+#pragma once
+
+#include "jx_common.hpp"
+
+namespace jx {
+
+// ---------------------------------------------------------------------------
+// Ring bookkeeping
+// ---------------------------------------------------------------------------
+
+// Ring of positions 1 .. m2-1 in the order their content moves.
+__device__ __forceinline__ int ring_at(int i, int m2) {
+    if (i == 0) return 1;
+    if (i < m2 / 2) return 2 * i;
+    return 2 * m2 - 1 - 2 * i;
+}
+__device__ __forceinline__ int ring_index(int x, int m2) {
+    if (x == 1) return 0;
+    if ((x & 1) == 0) return x >> 1;
+    return (2 * m2 - 1 - x) >> 1;
+}
+// LDS slot of index x (its place along the ring; 0 stays 0).
+__device__ __forceinline__ int slot_of(int x, int m2) { return x == 0 ? 0 : 1 + ring_index(x, m2); }
+// Slots of the members of pair k in round t of a sweep (t < m2 - 1):
+// position 2k holds slot 1 + (k + t) mod (m2-1) (position 0: slot 0),
+// position 2k+1 holds slot 1 + (t - k) mod (m2-1).
+__device__ __forceinline__ int slot_p(int k, int t, int m2) {
+    if (k == 0) return 0;
+    int i = k + t;
+    if (i >= m2 - 1) i -= m2 - 1;
+    return 1 + i;
+}
+__device__ __forceinline__ int slot_q(int k, int t, int m2) {
+    int i = (k == 0) ? t : t - k;
+    if (i < 0) i += m2 - 1;
+    return 1 + i;
+}
+// Index found at position x in round t.
+__device__ __forceinline__ int index_at(int x, int t, int m2) {
+    if (x == 0) return 0;
+    int i = ring_index(x, m2) + t;
+    if (i >= m2 - 1) i -= m2 - 1;
+    return ring_at(i, m2);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum x over the workgroup (fixed order); every thread gets the result.
+template <int NT>
+__device__ __forceinline__ double block_sum(double x, double *red) {
+    x = wave_sum(x);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = x;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    return s;
+}
+
+// Orders the LDS accesses of one wave (stores of some lanes, loads of others):
+// waits for the wave's outstanding LDS operations, and nothing moves across.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (WAVE) wave_lds_sync();
+    else __syncthreads();
+}
+
+// 1/x and 1/sqrt(x) from the hardware seeds (v_rcp_f64, v_rsq_f64) and two
+// Newton steps each: y <- y + y (1 - x y) and y <- y + y (1 - x y^2) / 2 (the
+// error squares every step), a few ulp for normal positive x.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, r, y);
+}
+
+// Rotation (c, s, t) that zeroes a_pq.  With d = a_qq - a_pp, e = 2 a_pq,
+// theta = d / e and r = sqrt(d^2 + e^2), the smaller root of t^2 + 2 theta t = 1
+// is t = sgn(theta) / (|theta| + sqrt(1 + theta^2)) = sgn(theta) |e| / (|d| + r)
+// (sgn(0) = +1), c = 1 / sqrt(1 + t^2), s = t c.  The second form needs one
+// reciprocal and two reciprocal square roots; where d^2 + e^2 leaves the
+// normal range the first form is used (for huge |theta|, t = 1 / (2 theta)).
+__device__ __forceinline__ void rot_cst(double app, double aqq, double apq, double &c, double &s, double &t) {
+    const double d = aqq - app, e = 2.0 * apq;
+    const double x = fma(d, d, e * e);
+    const double r = x * rsq_nr(x);
+    double tt = fabs(e) * rcp_nr(fabs(d) + r);
+    tt = (d != 0.0 && ((d < 0.0) != (e < 0.0))) ? -tt : tt;
+    double cc = rsq_nr(fma(tt, tt, 1.0));
+    if (!(x > 1e-280 && x < 1e280)) {  // rare: extreme magnitudes
+        tt = 0.0;
+        cc = 1.0;
+        if (apq != 0.0) {
+            const double th = d / e;
+            const double ath = fabs(th);
+            tt = ath > 1e150 ? 0.5 / ath : 1.0 / (ath + sqrt(1.0 + th * th));
+            if (th < 0.0) tt = -tt;
+            cc = 1.0 / sqrt(1.0 + tt * tt);
+        }
+    }
+    if (apq == 0.0) { tt = 0.0; cc = 1.0; }
+    c = cc;
+    s = tt * cc;
+    t = tt;
+}
+
+// Rotation parameters of pair k (c, s, t, a_pq) into the parameter arrays.
+__device__ __forceinline__ void rot_params(double app, double aqq, double apq, double *prm, int k, int H) {
+    double c, s, t;
+    rot_cst(app, aqq, apq, c, s, t);
+    prm[k] = c;
+    prm[H + k] = s;
+    prm[2 * H + k] = t;
+    prm[3 * H + k] = apq;
+}
+
+// ---------------------------------------------------------------------------
+// Round-robin scalar Jacobi on an m2 x m2 matrix held in LDS (slot order)
+// ---------------------------------------------------------------------------
+// NT threads (tid 0 .. NT-1) cooperate, each holding P = m2^2 / NT positions
+// of one row of V; WAVE: the group is one wave (wave-level ordering instead
+// of workgroup barriers).  Runs `nsw` sweeps, or (conv) up to 30 sweeps until
+// off <= eps sqrt(fro2).  V receives this thread's part of the accumulated
+// rotation (row r = tid / G, columns P g .. P g + P - 1, g = tid mod G,
+// G = m2 / P); position space equals index space at the end of a sweep.
+template <int M2, int NT, bool WAVE>
+__device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, int nsw, bool conv, double fro2,
+                              double *V) {
+    constexpr int H = M2 / 2, P = M2 * M2 / NT, G = M2 / P, LD = M2, R = M2 - 1;
+    constexpr int NOFF = H * (H - 1) / 2;  // pair-blocks between different pairs
+    static_assert(P >= 4 && P % 2 == 0 && M2 % P == 0, "whole position pairs per thread");
+    const int r = tid / G, g = tid - (tid / G) * G;
+#pragma unroll
+    for (int x = 0; x < P; ++x) V[x] = (r == P * g + x) ? 1.0 : 0.0;
+
+    // parameters of the first round
+    if (tid < H) {
+        const int up = slot_p(tid, 0, M2), uq = slot_q(tid, 0, M2);
+        rot_params(As[up * (LD + 1)], As[uq * (LD + 1)], As[min(up, uq) * LD + max(up, uq)], prm0, tid, H);
+    }
+    group_sync<WAVE>();
+
+    // This thread's pair-blocks (fixed for all rounds); their slots advance by
+    // one per round along 1 .. m2-1 (slot 0 stays), kept in registers.  Entry
+    // codes: 0 = (p1,p2), 1 = (p1,q2), 2 = (q1,p2), 3 = (q1,q2); member codes:
+    // 0 = p1, 1 = q1, 2 = p2, 3 = q2.  Packed: ikk = k1 | k2 << 8; icode =
+    // (stale + 1) | (kn + 1) << 3 | pivot entry << 10 | p' member << 12 |
+    // q' member << 14.
+    constexpr int MAXI = (NOFF + NT - 1) / NT;
+    static_assert(2 * H <= NT, "pivot pair-blocks must be first items");
+    int ikk[MAXI], isl[MAXI][4], icode[MAXI];
+#pragma unroll
+    for (int ii = 0; ii < MAXI; ++ii) {
+        const int it = tid + ii * NT;
+        int k1 = 0, d = 1;
+        if (it < H * (H / 2 - 1)) { d = it / H + 1; k1 = it - (d - 1) * H; }
+        else { d = H / 2; k1 = it - H * (H / 2 - 1); }
+        int k2 = k1 + d;
+        if (k2 >= H) k2 -= H;
+        const bool valid = it < NOFF;
+        if (!valid) { k1 = 0; k2 = 1; }
+        ikk[ii] = k1 | (k2 << 8);
+        isl[ii][0] = slot_p(k1, 0, M2);
+        isl[ii][1] = slot_q(k1, 0, M2);
+        isl[ii][2] = slot_p(k2, 0, M2);
+        isl[ii][3] = slot_q(k2, 0, M2);
+        const int lo = min(k1, k2), hi = max(k1, k2);
+        const bool fw = (k1 == lo);
+        // the previous round's pivot of pair k lies at (p of k-1, q of k+1) for
+        // 2 <= k <= H-2; pair 0: (p0, q1); pair 1: (q0, q2); pair H-1:
+        // (p(H-2), p(H-1))
+        int st = -1;
+        if (hi - lo == 2 && lo >= 1) st = fw ? 1 : 2;
+        else if (lo == 0 && hi == 2) st = 3;
+        else if (lo == 0 && hi == 1) st = fw ? 1 : 2;
+        else if (lo == H - 2 && hi == H - 1) st = 0;
+        // the next round's pivot of pair lo + 1 is (q_lo, p_hi); of pair 0,
+        // (p0, p1); of pair H-1, (q(H-2), q(H-1))
+        int kn = -1, pv = 0, mp = 0, mq = 0;
+        if (hi - lo == 2) {
+            kn = lo + 1; pv = fw ? 2 : 1; mp = fw ? 2 : 0; mq = fw ? 1 : 3;
+        } else if (lo == 0 && hi == 1) {
+            kn = 0; pv = 0; mp = fw ? 0 : 2; mq = fw ? 2 : 0;
+        } else if (lo == H - 2 && hi == H - 1) {
+            kn = H - 1; pv = 3; mp = fw ? 3 : 1; mq = fw ? 1 : 3;
+        }
+        if (!valid) { st = -1; kn = -1; }
+        icode[ii] = (st + 1) | ((kn + 1) << 3) | (pv << 10) | (mp << 12) | (mq << 14);
+    }
+
+    const double eps = 2.220446049250313e-16;
+    const int cap = conv ? 30 : nsw;
+    int gr = 0;  // rounds done (parameter buffer parity)
+    for (int swp = 0; swp < cap; ++swp) {
+        if (conv && swp > 0) {
+            double o = 0.0;
+            for (int e = tid; e < M2 * M2; e += NT) {
+                const int rr = e % M2, cc = e / M2;
+                if (rr < cc) { const double v = As[rr * LD + cc]; o += 2.0 * v * v; }
+            }
+            if constexpr (WAVE) o = wave_sum(o);
+            else o = block_sum<NT>(o, red);
+            if (sqrt(o) <= eps * sqrt(fro2)) break;
+        }
+        for (int t = 0; t < R; ++t, ++gr) {
+            const double *pc = prm0 + (gr & 1) * 4 * H;  // this round
+            double *pn = prm0 + ((gr + 1) & 1) * 4 * H;  // next round
+#pragma unroll
+            for (int ii = 0; ii < MAXI; ++ii) {
+                const bool valid = ii * NT + tid < NOFF;
+                const int k1 = ikk[ii] & 255, k2 = ikk[ii] >> 8;
+                const int code = icode[ii];
+                const int sp1 = isl[ii][0], sq1 = isl[ii][1], sp2 = isl[ii][2], sq2 = isl[ii][3];
+                const double c1 = pc[k1], s1 = pc[H + k1], c2 = pc[k2], s2 = pc[H + k2];
+                const int i11 = min(sp1, sp2) * LD + max(sp1, sp2);
+                const int i12 = min(sp1, sq2) * LD + max(sp1, sq2);
+                const int i21 = min(sq1, sp2) * LD + max(sq1, sp2);
+                const int i22 = min(sq1, sq2) * LD + max(sq1, sq2);
+                double x11 = As[i11], x12 = As[i12], x21 = As[i21], x22 = As[i22];
+                // producer operands (first item only; diagonal entries are
+                // written by their producer alone, never by an item)
+                const int kn = ((code >> 3) & 127) - 1;
+                const int pv = (code >> 10) & 3, mp = (code >> 12) & 3, mq = (code >> 14) & 3;
+                const int spn = mp == 0 ? sp1 : (mp == 1 ? sq1 : (mp == 2 ? sp2 : sq2));
+                const int sqn = mq == 0 ? sp1 : (mq == 1 ? sq1 : (mq == 2 ? sp2 : sq2));
+                const int pp = mp < 2 ? k1 : k2, pq_ = mq < 2 ? k1 : k2;
+                double dpo = 0.0, dqo = 0.0, tp = 0.0, tq = 0.0;
+                if (ii == 0) {
+                    dpo = As[spn * (LD + 1)];
+                    dqo = As[sqn * (LD + 1)];
+                    tp = pc[2 * H + pp] * pc[3 * H + pp];
+                    tq = pc[2 * H + pq_] * pc[3 * H + pq_];
+                }
+                if (ii == 0 && t > 0) {  // previous pivots: first item only (d <= 2)
+                    const int st = (code & 7) - 1;
+                    x11 = st == 0 ? 0.0 : x11;
+                    x12 = st == 1 ? 0.0 : x12;
+                    x21 = st == 2 ? 0.0 : x21;
+                    x22 = st == 3 ? 0.0 : x22;
+                }
+                // left: rows p1, q1; right: columns p2, q2
+                const double y11 = c1 * x11 - s1 * x21, y21 = s1 * x11 + c1 * x21;
+                const double y12 = c1 * x12 - s1 * x22, y22 = s1 * x12 + c1 * x22;
+                const double z11 = c2 * y11 - s2 * y12, z12 = s2 * y11 + c2 * y12;
+                const double z21 = c2 * y21 - s2 * y22, z22 = s2 * y21 + c2 * y22;
+                if (valid) {
+                    As[i11] = z11;
+                    As[i12] = z12;
+                    As[i21] = z21;
+                    As[i22] = z22;
+                }
+                if (ii == 0) {
+                    // diagonal of next round's pair kn after this round's
+                    // rotation (p-member a_pp - t a_pq, q-member a_qq + t a_pq),
+                    // then its parameters (computed by every lane, stored by producers)
+                    const double piv = pv == 0 ? z11 : (pv == 1 ? z12 : (pv == 2 ? z21 : z22));
+                    const double dp = dpo + ((mp & 1) ? tp : -tp);
+                    const double dq = dqo + ((mq & 1) ? tq : -tq);
+                    double cn, sn, tn;
+                    rot_cst(dp, dq, piv, cn, sn, tn);
+                    if (valid && kn >= 0) {
+                        As[spn * (LD + 1)] = dp;
+                        As[sqn * (LD + 1)] = dq;
+                        pn[kn] = cn;
+                        pn[H + kn] = sn;
+                        pn[2 * H + kn] = tn;
+                        pn[3 * H + kn] = piv;
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int sl = isl[ii][m];
+                    isl[ii][m] = sl == 0 ? 0 : (sl == R ? 1 : sl + 1);
+                }
+            }
+            // V <- V J on this thread's P/2 position pairs, then one ring step
+#pragma unroll
+            for (int j = 0; j < P / 2; ++j) {
+                const int k = (P / 2) * g + j;
+                const double cc = pc[k], ss = pc[H + k];
+                const double e = V[2 * j], o = V[2 * j + 1];
+                V[2 * j] = cc * e - ss * o;
+                V[2 * j + 1] = ss * e + cc * o;
+            }
+            {
+                const double from_right = __shfl_down(V[0], 1, G);
+                const double from_left = __shfl_up(V[P - 1], 1, G);
+                const double e0 = V[0], e1 = V[2], olast = V[P - 1];
+#pragma unroll
+                for (int j = 0; j < P / 2 - 1; ++j) V[2 * j] = V[2 * j + 2];
+                V[P - 2] = (g < G - 1) ? from_right : olast;
+#pragma unroll
+                for (int j = P / 2 - 1; j > 0; --j) V[2 * j + 1] = V[2 * j - 1];
+                V[1] = (g > 0) ? from_left : e1;
+                if (g == 0) V[0] = e0;
+            }
+            group_sync<WAVE>();
+        }
+        // end of sweep: clear the last round's pivots (the diagonal is current)
+        if (tid < H) {
+            const int up = slot_p(tid, R - 1, M2), uq = slot_q(tid, R - 1, M2);
+            As[min(up, uq) * LD + max(up, uq)] = 0.0;
+        }
+        group_sync<WAVE>();
+    }
+}
+
+}  // namespace jx

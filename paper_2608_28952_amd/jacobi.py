@@ -69,6 +69,9 @@ def lib():
                                          _vp, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Opts),
                                          ctypes.POINTER(Info), _vp]
         L.jacobi_schedule.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip]
+        L.jacobi_batched_tuning.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip]
+        L.jacobi_batched_graph_stats.argtypes = [_ip, _ip]
+        L.jacobi_batched_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_char_p]
         L.jacobi_subproblem_solve.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
         L.jacobi_block_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         _lib = L
@@ -179,22 +182,29 @@ def jacobi_svd_workspace(m, n, opts=None):
     return lib().jacobi_svd_workspace(m, n, ctypes.byref(o))
 
 
-def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, check=True):
+def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, check=True, out=None):
     """Batched eigendecomposition.  `sizes` (host int sequence), `offsets`
     (host int64 element offsets, len = batch), `packed` a float32 or float64
-    CUDA tensor holding each matrix column-major at its offset.  Returns
-    (W packed by prefix sums of n_k, Q packed at the offsets, list of info)."""
+    CUDA tensor holding each matrix column-major at its offset.  `out` may
+    give preallocated (W, Q) float64 tensors (a call with the same sizes,
+    pointers and options then replays the cached graph).  Returns (W packed by
+    prefix sums of n_k, Q packed at the offsets, list of info)."""
     import numpy as np
     import torch
     o = opts if opts is not None else opts_default()
     batch = len(sizes)
-    hn = (ctypes.c_int * batch)(*[int(v) for v in sizes])
-    ho = (ctypes.c_int64 * batch)(*[int(v) for v in offsets[:batch]])
+    hn = (ctypes.c_int * max(batch, 1))(*[int(v) for v in sizes])
+    ho = (ctypes.c_int64 * max(batch, 1))(*[int(v) for v in offsets[:batch]])
     dtype = F32 if packed.dtype == torch.float32 else F64
     total_w = int(np.sum(np.asarray(sizes, dtype=np.int64)))
-    total_q = int(offsets[batch - 1]) + int(sizes[-1]) ** 2 if batch else 0
-    W = torch.empty(total_w, dtype=torch.float64, device=packed.device)
-    Q = torch.empty(total_q, dtype=torch.float64, device=packed.device)
+    total_q = max((int(offsets[k]) + int(sizes[k]) ** 2 for k in range(batch)), default=0)
+    if out is not None:
+        W, Q = out
+        if W.numel() < total_w or (Q is not None and Q.numel() < total_q):
+            raise ValueError("output tensors too small")
+    else:
+        W = torch.empty(total_w, dtype=torch.float64, device=packed.device)
+        Q = torch.empty(total_q, dtype=torch.float64, device=packed.device)
     infos = (Info * max(batch, 1))()
     rc = lib().jacobi_eig_batched(batch, hn, ho, dtype, _ptr(packed), _ptr(W), _ptr(Q), _ptr(Q0),
                                   _ptr(work), work.numel() * work.element_size() if work is not None else 0,
@@ -202,6 +212,36 @@ def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, ch
     if check:
         _check(rc)
     return W, Q, [infos[k].as_dict() for k in range(batch)]
+
+
+def batched_workspace(sizes, dtype_f64=False, opts=None):
+    """Device workspace bytes of jacobi_eig_batched for these sizes."""
+    o = opts if opts is not None else opts_default()
+    hn = (ctypes.c_int * max(len(sizes), 1))(*[int(v) for v in sizes])
+    return int(lib().jacobi_eig_batched_workspace(len(sizes), hn, F64 if dtype_f64 else F32, ctypes.byref(o)))
+
+
+def batched_tuning(dtype_f64, bucket):
+    """(bs, mixed, from_file) of a size bucket (0: n<=32, 1: <=64, 2: <=128,
+    3: <=192, 4: <=256) in the active tuning table."""
+    bs, mixed = ctypes.c_int(), ctypes.c_int()
+    rc = lib().jacobi_batched_tuning(F64 if dtype_f64 else F32, bucket, ctypes.byref(bs), ctypes.byref(mixed))
+    if rc < 0 or rc > 1:
+        raise JacobiError(rc, "invalid tuning query")
+    return bs.value, mixed.value, rc == 1
+
+
+def batched_graph_stats():
+    """(cached-graph hits, graphs built) since the library was loaded."""
+    h, b = ctypes.c_int(), ctypes.c_int()
+    lib().jacobi_batched_graph_stats(ctypes.byref(h), ctypes.byref(b))
+    return h.value, b.value
+
+
+def batched_autotune(path, dtype_f64=False, per_bucket=32, seed=0):
+    """Time the candidate class parameters on a seeded calibration batch per
+    size bucket, write the JSON cache to `path` and make it active."""
+    _check(lib().jacobi_batched_autotune(F64 if dtype_f64 else F32, per_bucket, seed, str(path).encode()))
 
 
 def jacobi_schedule(N, ordering=ORDER_ROUND_ROBIN):

@@ -87,3 +87,40 @@ def test_argument_errors_return_before_any_device_work():
     assert L.jacobi_eig(4, ctypes.c_void_p(16), 4, b"X", None, None, 4, None, 4, None, 0, ctypes.byref(o), None, None) == -4
     assert L.jacobi_eig(0, None, 1, b"U", None, None, 1, None, 1, None, 0, ctypes.byref(o), None, None) == 0
     assert "uplo" in jx.last_error() or jx.last_error() == ""
+
+
+def test_batched_argument_errors_and_workspace():
+    jx = _jx()
+    L = jx.lib()
+    o = jx.opts_default()
+    n = (ctypes.c_int * 3)(16, 300, 20)
+    off = (ctypes.c_int64 * 3)(0, 256, 90256)
+    infos = (jx.Info * 3)()
+    call = lambda b, hn, ho, dt, opts: L.jacobi_eig_batched(b, hn, ho, dt, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                                            ctypes.c_void_p(16), None, None, 0, ctypes.byref(opts),
+                                                            infos, None)
+    assert call(-1, n, off, jx.F32, o) == -1
+    assert call(3, n, off, jx.F32, o) == -2                       # an order above 256
+    n[1] = 40
+    assert call(3, n, None, jx.F32, o) == -3
+    assert call(3, n, off, 7, o) == -4
+    bad = jx.opts_default(block=12)
+    assert call(3, n, off, jx.F32, bad) == -11
+    assert infos[0].status == -11
+    assert call(0, n, off, jx.F32, o) == 0                          # empty batch
+    # workspace: padded M2^2 slots per matrix, FP32 copies only with an FP32 phase
+    mixed = jx.opts_default(precision=jx.PREC_MIXED_FP32)
+    w64 = jx.batched_workspace([16, 40, 20], False, jx.opts_default())
+    w32 = jx.batched_workspace([16, 40, 20], False, mixed)
+    assert w32 > w64 > 4 * 8 * (16 * 16 + 48 * 48 + 32 * 32)
+    assert jx.batched_workspace([256] * 4, False, mixed) > jx.batched_workspace([255] * 4, False, mixed) - 1
+
+
+def test_batched_tuning_defaults_without_cache(monkeypatch):
+    jx = _jx()
+    monkeypatch.delenv("JACOBI_TUNE_FILE", raising=False)
+    for b in range(5):
+        bs, mixed, from_file = jx.batched_tuning(False, b)
+        assert bs in (8, 16) and mixed in (0, 1) and from_file is False
+    with pytest.raises(Exception):
+        jx.batched_tuning(False, 5)
