@@ -187,6 +187,59 @@ int jacobi_batched_tuning(int dtype, int bucket, int *bs, int *mixed);
 int jacobi_batched_autotune(int dtype, int per_bucket, unsigned seed, const char *path);
 int jacobi_batched_graph_stats(int *hits, int *builds);
 
+/* ------------------------------------------------------------------------ */
+/* Learned warm start (spec addition; the paper has no learned part)   */
+/* ------------------------------------------------------------------------ */
+/*
+ * A small network maps the parameters theta (8) of a matrix family
+ * A(theta) = A0 + sum_k theta_k B_k (order 64) to the 2016 strictly upper
+ * coordinates (row-major (0,1), (0,2), ..., (62,63)) of a skew generator S; the
+ * warm start is Q0 = Qref cay(S), cay(S) = (I - S)^{-1} (I + S), handed to
+ * jacobi_eig_batched as dQ0.  Network: 8 -> 256 -> 256 -> 2016, GELU (tanh
+ * form) on the hidden layers, linear output; GEMMs on BF16 MFMA with FP32
+ * accumulation.
+ *
+ * Parameter vector (jws_param_count() FP32 values; the gradient and the BF16
+ * copy use the same layout): W1 (16 x 256, rows 8..15 zero: the input is
+ * padded to 16 features), W2 (256 x 256), W3 (256 x 2016), all row-major
+ * K x N, then b1 (256), b2 (256), b3 (2016).  The forward and backward read
+ * the weights from the BF16 copy and the biases from the FP32 vector (dBias
+ * = its b1, i.e. element offset 16*256 + 256*256 + 256*2016).
+ * Activations: dActs holds jws_acts_bytes(batch) bytes of BF16 values per
+ * call (inputs and pre-activations kept for the backward, and its scratch);
+ * a backward must use the buffer of the forward of the same batch.
+ * All pointers are device pointers owned by the caller; row-major B x
+ * features.  The calls enqueue on `stream` and return without waiting.
+ * Returns 0, -i (argument i invalid) or 3 (HIP error).
+ */
+size_t jws_param_count(void);
+size_t jws_acts_bytes(int batch);
+/* dOut (B x 2016 FP32) = network(dTheta (B x 8 FP32)) */
+int jws_mlp_forward(int batch, const float *dTheta, const uint16_t *dWbf16, const float *dBias, float *dOut,
+                    uint16_t *dActs, jacobi_stream_t stream);
+/* Gradients of a loss with dL/dOut = dGradOut: dGradW (weight part of the
+ * parameter layout, FP32) and dGradB (b1 | b2 | b3).  dGradOut and the
+ * back-propagated dL/dZ are rounded to BF16 for the MFMA products. */
+int jws_mlp_backward(int batch, const uint16_t *dActs, const float *dGradOut, const uint16_t *dWbf16, float *dGradW,
+                     float *dGradB, jacobi_stream_t stream);
+/* Mean squared error over B x 2016 outputs: dLoss[0] (FP64) and, if dGradOut
+ * is not NULL, dGradOut = 2 (dOut - dTarget) / (B * 2016). */
+int jws_mse(int batch, const float *dOut, const float *dTarget, float *dGradOut, double *dLoss,
+            jacobi_stream_t stream);
+/* One Adam step (bias-corrected, Kingma & Ba) on nparams FP32 values; the
+ * BF16 copy is refreshed (round to nearest, ties to even).  step >= 1. */
+int jws_adam_step(int nparams, float *dMaster, uint16_t *dWbf16, const float *dGrad, float *dM, float *dV, float lr,
+                  float beta1, float beta2, float eps, int step, jacobi_stream_t stream);
+/* BF16 copy (nearest, ties to even) of count FP32 values. */
+int jws_to_bf16(size_t count, const float *dSrc, uint16_t *dDst, jacobi_stream_t stream);
+/* dS: batch column-major n x n skew matrices whose strictly upper entries
+ * (row-major order) are dCoords * dStd + dMean (dMean / dStd may be NULL). */
+int jws_skew_from_coords(int batch, int n, const float *dCoords, const float *dMean, const float *dStd, double *dS,
+                         jacobi_stream_t stream);
+/* dQ0[k] = dQref (I - dS[k])^{-1} (I + dS[k]) for batch skew-symmetric FP64
+ * column-major n x n matrices, n <= 64. */
+int jws_cayley_batched(int batch, int n, const double *dS, const double *dQref, double *dQ0, jacobi_stream_t stream);
+
 /* Text of the last error of the calling thread ("" if none). */
 const char *jacobi_last_error(void);
 

@@ -123,11 +123,33 @@ def coords_from_skew(S):
     return S[np.triu_indices(S.shape[0], 1)]
 
 
+def greedy_match(W):
+    """Column permutation c pairing row i with column c[i]: repeatedly take the
+    largest remaining |W_ij| (plain loops; ties by lowest flat index)."""
+    n = W.shape[0]
+    c = [-1] * n
+    rows, cols = set(range(n)), set(range(n))
+    A = np.abs(W)
+    for _ in range(n):
+        best, bi, bj = -1.0, -1, -1
+        for i in sorted(rows):
+            for j in sorted(cols):
+                if A[i, j] > best:
+                    best, bi, bj = A[i, j], i, j
+        c[bi] = bj
+        rows.discard(bi)
+        cols.discard(bj)
+    return c
+
+
 def canonical_generator(Qref, Q):
-    """Target of one training sample: W = Qref^T Q with column signs making
-    diag(W) >= 0, the column of smallest |W_jj| flipped when det W = -1, then
-    S = (W - I)(W + I)^{-1} skew-symmetrised.  Returns (S, W)."""
+    """Target of one training sample: W = Qref^T Q with its columns permuted so
+    that column i is the one greedy_match pairs with Qref's column i, column
+    signs with diag(W) >= 0, the column of smallest |W_jj| flipped when
+    det W = -1, then S = (W - I)(W + I)^{-1} made exactly skew.
+    Returns (S, W)."""
     W = Qref.T @ Q
+    W = W[:, greedy_match(W)]
     s = np.where(np.diag(W) < 0.0, -1.0, 1.0)
     W = W * s
     if np.linalg.det(W) < 0.0:

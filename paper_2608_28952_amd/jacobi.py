@@ -72,6 +72,18 @@ def lib():
         L.jacobi_batched_tuning.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip]
         L.jacobi_batched_graph_stats.argtypes = [_ip, _ip]
         L.jacobi_batched_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_char_p]
+        L.jws_param_count.restype = ctypes.c_size_t
+        L.jws_param_count.argtypes = []
+        L.jws_acts_bytes.restype = ctypes.c_size_t
+        L.jws_acts_bytes.argtypes = [ctypes.c_int]
+        L.jws_mlp_forward.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.jws_mlp_backward.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.jws_mse.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+        L.jws_adam_step.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_int, _vp]
+        L.jws_to_bf16.argtypes = [ctypes.c_size_t, _vp, _vp, _vp]
+        L.jws_skew_from_coords.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+        L.jws_cayley_batched.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
         L.jacobi_subproblem_solve.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
         L.jacobi_block_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         _lib = L

@@ -1,0 +1,386 @@
+"""Learned warm start for batched Jacobi on a parametrised matrix family.
+
+A spec addition (the paper's method has no learned part): for the
+family A(theta) = A0 + sum_k theta_k B_k (order 64, theta in R^8), a small
+network proposes Q0 = Qref cay(S(theta)) and the batched Jacobi solver
+finishes from Q0^T A Q0; a proposal that does not lower the off-norm falls
+back to the cold start inside the solver.
+
+Every numerical step runs in the library's kernels (through the C-ABI):
+the batched FP64 solver generates the training solutions, the network is
+trained with jws_mlp_forward / jws_mlp_backward / jws_mse / jws_adam_step,
+and proposals use jws_skew_from_coords and jws_cayley_batched.  PyTorch holds
+device memory; the canonical training targets are prepared on the host with
+numpy (one pass over the generated solutions, not on the solve path).
+
+    python -m paper_2608_28952_amd.warmstart [--train 262144] [--epochs 40]
+"""
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import inputs
+from . import jacobi as jx
+
+N = 64
+NC = N * (N - 1) // 2  # 2016 generator coordinates
+NIN, K1, HID = 8, 16, 256
+OFF_W1, OFF_W2, OFF_W3 = 0, K1 * HID, K1 * HID + HID * HID
+OFF_B1 = OFF_W3 + HID * NC
+NPARAM = OFF_B1 + 2 * HID + NC
+IU = np.triu_indices(N, 1)
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _s():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _chk(rc, what):
+    if rc != 0:
+        raise jx.JacobiError(rc, f"{what}: {jx.last_error()}")
+
+
+# ---------------------------------------------------------------------------
+# Family, solutions and targets
+# ---------------------------------------------------------------------------
+class Family:
+    """A0, B_1..B_8 (seeded symmetric N(0, 1/n)) and Qref = eigenvectors of A0
+    (ascending eigenvalues), computed by the library's eigensolver."""
+
+    def __init__(self, seed=5):
+        import torch
+        self.A0, self.B = inputs.warmstart_family(seed, N, NIN)
+        A0 = torch.from_numpy(np.ascontiguousarray(self.A0)).cuda()
+        _, Qref, _ = jx.jacobi_eig(A0)
+        self.Qref = Qref.contiguous()                    # n x n (row-major view of the matrix)
+        self.Qref_cm = Qref.t().contiguous()             # column-major storage for the kernels
+        self.Bt = torch.from_numpy(np.ascontiguousarray(self.B)).cuda()   # 8 x n x n
+        self.A0t = A0
+
+    def matrices(self, theta):
+        """theta: m x 8 (numpy or CUDA tensor) -> m x n x n FP64 CUDA tensor
+        (symmetric, so row- and column-major storage coincide)."""
+        import torch
+        th = torch.as_tensor(theta, dtype=torch.float64, device="cuda")
+        return self.A0t.unsqueeze(0) + torch.tensordot(th, self.Bt, dims=([1], [0]))
+
+
+def solve(A, Q0=None, precision=None, max_sweeps=60):
+    """Batched FP64 solve of m x n x n matrices; returns (W m x n, Q m x n x n
+    with Q[k] the eigenvector matrix, infos)."""
+    import torch
+    m = A.shape[0]
+    sizes = np.full(m, N, dtype=np.int32)
+    offs = np.arange(m + 1, dtype=np.int64) * N * N
+    o = jx.opts_default(precision=jx.PREC_FP64 if precision is None else precision, max_sweeps=max_sweeps)
+    ws = torch.empty(jx.batched_workspace(sizes, True, o), dtype=torch.uint8, device="cuda")
+    q0 = None if Q0 is None else Q0.transpose(1, 2).contiguous().reshape(-1)
+    W, Q, infos = jx.jacobi_eig_batched(sizes, offs, A.reshape(-1), Q0=q0, opts=o, work=ws)
+    return W.view(m, N), Q.view(m, N, N).transpose(1, 2), infos
+
+
+def _greedy_columns(W, top=384):
+    """For each matrix of the batch W (m x n x n): the column paired with row i,
+    taking the largest remaining |W_ij| first (m x n int).  The `top` largest
+    entries of every matrix are sorted once and walked in step for the whole
+    batch; matrices left incomplete rerun the plain loop."""
+    m = W.shape[0]
+    A = np.abs(W).reshape(m, -1)
+    ar = np.arange(m)
+    c = np.full((m, N), -1, dtype=np.int64)
+    rowfree = np.ones((m, N), dtype=bool)
+    colfree = np.ones((m, N), dtype=bool)
+    k = min(top, N * N - 1)
+    idx = np.argpartition(-A, k, axis=1)[:, :k]
+    idx = np.take_along_axis(idx, np.argsort(-np.take_along_axis(A, idx, axis=1), axis=1, kind="stable"), axis=1)
+    for p in range(k):
+        i, j = idx[:, p] // N, idx[:, p] % N
+        ok = rowfree[ar, i] & colfree[ar, j]
+        a, ii, jj = ar[ok], i[ok], j[ok]
+        c[a, ii] = jj
+        rowfree[a, ii] = False
+        colfree[a, jj] = False
+    rest = np.nonzero(rowfree.any(axis=1))[0]
+    if len(rest):
+        B = A[rest].reshape(len(rest), N, N).copy()
+        r = len(rest)
+        cc = np.full((r, N), -1, dtype=np.int64)
+        br = np.arange(r)
+        for _ in range(N):
+            flat = B.reshape(r, -1).argmax(axis=1)
+            i, j = flat // N, flat % N
+            cc[br, i] = j
+            B[br, i, :] = -1.0
+            B[br, :, j] = -1.0
+        c[rest] = cc
+    return c
+
+
+def _targets_chunk(Qref, Qc):
+    """canonical_targets for one chunk (see there)."""
+    I = np.eye(N)
+    Qc = np.asarray(Qc, dtype=np.float64)
+    mc = Qc.shape[0]
+    Wm = (Qref.T @ Qc.transpose(1, 0, 2).reshape(N, -1)).reshape(N, mc, N).transpose(1, 0, 2)
+    cols = _greedy_columns(Wm)
+    Wm = np.take_along_axis(Wm, cols[:, None, :], axis=2)
+    d = np.diagonal(Wm, axis1=1, axis2=2)
+    Wm = Wm * np.where(d < 0.0, -1.0, 1.0)[:, None, :]
+    neg = np.linalg.det(Wm) < 0.0
+    if np.any(neg):
+        j = np.argmin(np.abs(np.diagonal(Wm, axis1=1, axis2=2)), axis=1)
+        idx = np.nonzero(neg)[0]
+        Wm[idx, :, j[idx]] *= -1.0
+    # S (W + I) = W - I  <=>  (W + I)^T S^T = (W - I)^T
+    lhs, rhs = np.swapaxes(Wm + I, 1, 2), np.swapaxes(Wm - I, 1, 2)
+    try:
+        St = np.linalg.solve(lhs, rhs)
+    except np.linalg.LinAlgError:  # some W + I singular: those samples are dropped
+        St = np.full_like(lhs, np.nan)
+        for q in range(mc):
+            try:
+                St[q] = np.linalg.solve(lhs[q], rhs[q])
+            except np.linalg.LinAlgError:
+                pass
+    S = np.swapaxes(St, 1, 2)
+    S = 0.5 * (S - np.swapaxes(S, 1, 2))
+    ok = np.all(np.isfinite(S), axis=(1, 2)) & (np.max(np.abs(S), axis=(1, 2)) <= 10.0)
+    return np.where(ok[:, None], S[:, IU[0], IU[1]], 0.0).astype(np.float32), ok
+
+
+def canonical_targets(Qref, Q, chunk=1024, threads=None):
+    """Generator coordinates of the solutions: W = Qref^T Q with its columns
+    matched to Qref's columns (largest remaining overlap first), column signs
+    with diag(W) >= 0, the column of smallest |W_jj| flipped when det W < 0,
+    S = (W - I)(W + I)^{-1} made exactly skew.  Matching by overlap instead of
+    eigenvalue order keeps W near I when eigenvalues cross.  Returns
+    (coords m x 2016 float32, kept mask: finite and max |S_ij| <= 10).
+    Chunks run on a thread pool (numpy releases the GIL in its kernels)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    Qref = np.asarray(Qref, dtype=np.float64)
+    m = Q.shape[0]
+    out = np.zeros((m, NC), dtype=np.float32)
+    keep = np.zeros(m, dtype=bool)
+    starts = list(range(0, m, chunk))
+    threads = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        for a, (c, k) in zip(starts, ex.map(lambda a: _targets_chunk(Qref, Q[a:a + chunk]), starts)):
+            out[a:a + chunk], keep[a:a + chunk] = c, k
+    return out, keep
+
+
+# ---------------------------------------------------------------------------
+# Network
+# ---------------------------------------------------------------------------
+class Net:
+    """FP32 master parameters, BF16 copy, Adam moments (device)."""
+
+    def __init__(self, seed=0):
+        import torch
+        assert int(jx.lib().jws_param_count()) == NPARAM
+        rng = np.random.default_rng(seed)
+        p = np.zeros(NPARAM, dtype=np.float32)
+        for off, fan_in, rows, cols in ((OFF_W1, NIN, NIN, HID), (OFF_W2, HID, HID, HID), (OFF_W3, HID, HID, NC)):
+            lim = np.sqrt(6.0 / fan_in)   # He-uniform
+            ld = cols
+            w = rng.uniform(-lim, lim, size=(rows, cols)).astype(np.float32)
+            p[off:off + rows * ld] = w.reshape(-1)
+        self.master = torch.from_numpy(p).cuda()
+        self.bf16 = torch.empty(NPARAM, dtype=torch.int16, device="cuda")
+        self.grad = torch.zeros(NPARAM, dtype=torch.float32, device="cuda")
+        self.m = torch.zeros(NPARAM, dtype=torch.float32, device="cuda")
+        self.v = torch.zeros(NPARAM, dtype=torch.float32, device="cuda")
+        self.step = 0
+        self.mean = None
+        self.std = None
+        _chk(jx.lib().jws_to_bf16(NPARAM, _p(self.master), _p(self.bf16), _s()), "jws_to_bf16")
+        self._acts = {}
+
+    def acts(self, B):
+        import torch
+        if B not in self._acts:
+            self._acts[B] = torch.empty(int(jx.lib().jws_acts_bytes(B)) // 2, dtype=torch.int16, device="cuda")
+        return self._acts[B]
+
+    def bias_ptr(self):
+        return self.master.data_ptr() + 4 * OFF_B1
+
+    def forward(self, theta, out=None):
+        import torch
+        B = theta.shape[0]
+        out = torch.empty(B, NC, dtype=torch.float32, device="cuda") if out is None else out
+        _chk(jx.lib().jws_mlp_forward(B, _p(theta), _p(self.bf16), self.bias_ptr(), _p(out), _p(self.acts(B)), _s()),
+             "jws_mlp_forward")
+        return out
+
+    def backward(self, theta, dY):
+        B = theta.shape[0]
+        _chk(jx.lib().jws_mlp_backward(B, _p(self.acts(B)), _p(dY), _p(self.bf16), _p(self.grad),
+                                       self.grad.data_ptr() + 4 * OFF_B1, _s()), "jws_mlp_backward")
+
+    def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        _chk(jx.lib().jws_adam_step(NPARAM, _p(self.master), _p(self.bf16), _p(self.grad), _p(self.m), _p(self.v),
+                                    lr, b1, b2, eps, self.step, _s()), "jws_adam_step")
+
+    def mse(self, Y, T, dY=None, loss=None):
+        import torch
+        loss = torch.empty(1, dtype=torch.float64, device="cuda") if loss is None else loss
+        _chk(jx.lib().jws_mse(Y.shape[0], _p(Y), _p(T), _p(dY), _p(loss), _s()), "jws_mse")
+        return loss
+
+
+def train(net, theta, target, val_theta, val_target, epochs=40, batch=1024, lr=1e-3, patience=5, seed=1, log=None):
+    """Adam with cosine-decayed learning rate on the MSE of standardised
+    targets; early stop when the validation loss has not improved for
+    `patience` epochs (the best parameters are kept)."""
+    import torch
+    m = theta.shape[0]
+    steps_per_epoch = max(m // batch, 1)
+    total = epochs * steps_per_epoch
+    rng = np.random.default_rng(seed)
+    dY = torch.empty(batch, NC, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    best, best_state, bad, hist = np.inf, None, 0, []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(m)).cuda()
+        for s in range(steps_per_epoch):
+            idx = perm[s * batch:(s + 1) * batch]
+            th, tg = theta.index_select(0, idx), target.index_select(0, idx)
+            Y = net.forward(th)
+            net.mse(Y, tg, dY=dY, loss=loss)
+            net.backward(th, dY)
+            k = ep * steps_per_epoch + s
+            net.adam(lr * 0.5 * (1.0 + np.cos(np.pi * k / total)))
+        vl = float(net.mse(net.forward(val_theta), val_target).item())
+        tl = float(loss.item())
+        hist.append((ep, tl, vl))
+        if log:
+            log(f"epoch {ep}: train {tl:.4e} val {vl:.4e}")
+        if not np.isfinite(best) or vl < best - 1e-6 * abs(best):
+            best, bad = vl, 0
+            best_state = (net.master.clone(), net.bf16.clone())
+        else:
+            bad += 1
+            if bad >= patience:
+                break
+    torch.cuda.synchronize()
+    if best_state is not None:
+        net.master.copy_(best_state[0])
+        net.bf16.copy_(best_state[1])
+    return {"epochs": len(hist), "best_val": best, "history": hist, "seconds": time.perf_counter() - t0}
+
+
+def propose(net, fam, theta):
+    """Q0 (m x n x n, Q0[k] the matrix) for theta (m x 8 float32 CUDA)."""
+    import torch
+    m = theta.shape[0]
+    Y = net.forward(theta)
+    S = torch.empty(m, N, N, dtype=torch.float64, device="cuda")
+    _chk(jx.lib().jws_skew_from_coords(m, N, _p(Y), _p(net.mean), _p(net.std), _p(S), _s()), "jws_skew_from_coords")
+    Q0cm = torch.empty(m, N, N, dtype=torch.float64, device="cuda")
+    _chk(jx.lib().jws_cayley_batched(m, N, _p(S), _p(fam.Qref_cm), _p(Q0cm), _s()), "jws_cayley_batched")
+    return Q0cm.transpose(1, 2)   # column-major storage -> matrices
+
+
+def generate(fam, count, seed, chunk=32768, log=None):
+    """Thetas (count x 8, N(0, 0.1^2)), standardisable targets and the kept mask."""
+    th = inputs.warmstart_thetas(count, seed)
+    coords = np.zeros((count, NC), dtype=np.float32)
+    keep = np.zeros(count, dtype=bool)
+    Qref = fam.Qref.cpu().numpy()
+    for a in range(0, count, chunk):
+        A = fam.matrices(th[a:a + chunk])
+        _, Q, infos = solve(A)
+        if any(i["status"] != 0 for i in infos):
+            raise RuntimeError("training solve did not converge")
+        c, k = canonical_targets(Qref, Q.cpu().numpy())
+        coords[a:a + chunk], keep[a:a + chunk] = c, k
+        if log:
+            log(f"generated {min(a + chunk, count)}/{count}")
+    return th.astype(np.float32), coords, keep
+
+
+def evaluate(net, fam, test_theta, reps=3):
+    """Cold vs warm batched FP64 solves of the test batch: sweeps, fallback
+    rate and solves/s (warm includes the network and the Cayley map)."""
+    import torch
+    A = fam.matrices(test_theta)
+    th = torch.from_numpy(np.ascontiguousarray(test_theta, dtype=np.float32)).cuda()
+    m = A.shape[0]
+
+    def timed(fn):
+        best = np.inf
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return r, best
+
+    (_, _, ic), tc = timed(lambda: solve(A))
+    (_, _, iw), tw = timed(lambda: solve(A, Q0=propose(net, fam, th)))
+    sc = np.array([i["sweeps"] for i in ic])
+    sw = np.array([i["sweeps"] for i in iw])
+    fb = np.array([i["fallback_used"] for i in iw])
+    return {
+        "matrices": m,
+        "cold_sweeps_mean": float(sc.mean()), "warm_sweeps_mean": float(sw.mean()),
+        "sweeps_saved_mean": float((sc - sw).mean()),
+        "sweeps_saved_hist": {int(k): int(v) for k, v in zip(*np.unique(sc - sw, return_counts=True))},
+        "fallback_rate": float(fb.mean()),
+        "cold_solves_per_s": m / tc, "warm_solves_per_s": m / tw, "speedup": tc / tw,
+        "status_ok": bool(all(i["status"] == 0 for i in ic + iw)),
+    }
+
+
+def run(train_count=1 << 18, epochs=40, val_count=4096, test_count=4096, seed=5, log=print):
+    import torch
+    fam = Family(seed)
+    t0 = time.perf_counter()
+    th, coords, keep = generate(fam, train_count, 50, log=log)
+    gen_s = time.perf_counter() - t0
+    vth, vco, vkeep = generate(fam, val_count, 51)
+    mean = coords[keep].mean(axis=0)
+    std = coords[keep].std(axis=0) + 1e-6
+    net = Net(seed=0)
+    net.mean = torch.from_numpy(mean).cuda()
+    net.std = torch.from_numpy(std).cuda()
+    T = torch.from_numpy((coords[keep] - mean) / std).cuda()
+    X = torch.from_numpy(th[keep]).cuda()
+    VT = torch.from_numpy((vco[vkeep] - mean) / std).cuda()
+    VX = torch.from_numpy(vth[vkeep]).cuda()
+    tr = train(net, X, T, VX, VT, epochs=epochs, log=log)
+    test_theta = inputs.warmstart_thetas(test_count, 52)
+    ev = evaluate(net, fam, test_theta)
+    return {"train_samples": int(train_count), "dropped_fraction": float(1.0 - keep.mean()),
+            "generation_seconds": gen_s, "training": {k: v for k, v in tr.items() if k != "history"},
+            "val_history": tr["history"], "test": ev}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=1 << 18)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    res = run(a.train, a.epochs, log=lambda s: print(s, flush=True))
+    txt = json.dumps(res, indent=1)
+    print(txt)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,6 +97,16 @@ def test_skew_coordinates_round_trip():
     assert S[0, 1] == c[0] and S[0, 63] == c[62] and S[1, 2] == c[63] and S[62, 63] == c[-1]
 
 
+def test_greedy_match_on_permutation_and_brute_force():
+    rng = np.random.default_rng(6)
+    P = np.eye(5)[:, rng.permutation(5)] * rng.choice([-1.0, 1.0], 5)
+    c = M.greedy_match(P + 0.01 * rng.standard_normal((5, 5)))
+    assert np.all(np.abs(P[np.arange(5), c]) == 1.0)
+    # on a diagonally dominant matrix the greedy choice is the identity
+    D = np.eye(6) * 3 + rng.random((6, 6))
+    assert M.greedy_match(D) == list(range(6))
+
+
 def test_canonical_generator_inverts_cayley():
     # Q = Qref cay(S) with a small S: the canonical target gives S back, and
     # sign flips / column order of Q do not change it
@@ -110,4 +120,6 @@ def test_canonical_generator_inverts_cayley():
     flips = np.where(rng.random(n) < 0.5, -1.0, 1.0)
     S2, _ = M.canonical_generator(Qref, Q * flips)
     assert np.max(np.abs(S2 - S)) < 1e-12
+    S3, _ = M.canonical_generator(Qref, (Q * flips)[:, rng.permutation(n)])
+    assert np.max(np.abs(S3 - S)) < 1e-12
     assert np.linalg.det(W) > 0 and np.all(np.diag(W) >= 0)
