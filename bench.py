@@ -1,17 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark: blocked two-sided Jacobi eigensolver, n = 4096, b = 64, graded
+"""Benchmark of the blocked Jacobi eigensolver on one MI355X.
+
+Main line (the headline workload): blocked two-sided Jacobi eigendecomposition,
+n = 4096, b = 64 (64 block columns, 32 block pairs per parallel step), graded
 spectrum lambda_i = +-10^(-8 i / n) (Haar Q, seed 2), FP64, to
-Xi(A) <= 1e-14 ||A||_F, with eigenvectors and orthogonality refinement.
+Xi(A) <= 1e-14 ||A||_F, with eigenvectors and orthogonality refinement.  One
+step = one full solve (jacobi_eig) on inputs already resident in HBM.
 
-One step = one full solve (jacobi_eig) on inputs already resident in HBM.
-Prints one JSON line.  Also reported:
-  * roofline: the dominant kernel's algorithmic flops (or bytes) per launch
-    over its average launch time, measured with HIP events recorded by the
-    library on the launch stream during the timed steps;
-  * cpu_baseline: the CPU oracle (scalar FP64 Jacobi, round-robin, all host
-    cores) timed on a bounded sample of the same matrix and scaled to s/solve.
+Reported beside it on the same JSON line:
+  * roofline: the dominant kernel's algorithmic flops per launch over its
+    average launch time, timed with HIP events the library records on the
+    launch stream during the timed steps; `traffic` from the committed
+    rocprofv3 counter summary when it was taken on the current kernel source;
+  * cpu_baseline: the CPU oracle (scalar FP64 round-robin Jacobi, all host
+    cores) on a bounded sample of the same matrix, scaled to s/solve;
+  * extras: the batched workload (10,000 matrices, n ~ U{16..256}, FP32
+    stored, to 1e-12 residuals) in solves/s against per-matrix plain FP64
+    calls, the FP32 precision ladder on the headline matrix, and the one-sided
+    SVD of 16384 x 2048 (sigma log-uniform in [1e-6, 1]).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extras]
+    python bench.py --copy-probe MiB     # plain copy kernel of known size (counter scaling)
 """
 import argparse
 import ctypes
@@ -30,48 +39,159 @@ METRIC = "block-Jacobi eig n=4096 s/solve & %MFMA peak; batched solves/s vs plai
 N = 4096
 BLOCK = 64
 SEED = 2
-PEAK = {"fp64_mfma_tflops": 78.6, "fp64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
-KINDS = {0: "k_subproblem", 1: "k_update_a", 2: "k_update_q", 3: "k_gemm_f64"}
+PEAK = {"fp64_tflops": 78.6, "hbm_gbs": 8000.0}
+KINDS = {0: "k_subproblem2", 1: "k_update_a", 2: "k_update_q", 3: "k_gemm_f64"}
+SOURCES = {"k_subproblem2": ["k_subproblem.hip", "jx_sweep.hpp"], "k_update_a": ["k_update.hip"],
+           "k_update_q": ["k_update.hip"], "k_gemm_f64": ["k_gemm.hip"]}
 
 
 def kernel_source_hash(name):
-    src = {"k_update_a": "k_update.hip", "k_update_q": "k_update.hip", "k_subproblem": "k_subproblem.hip",
-           "k_gemm_f64": "k_gemm.hip"}[name]
-    with open(os.path.join(ROOT, "paper_2608_28952_amd", "csrc", src), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for src in SOURCES[name]:
+        with open(os.path.join(ROOT, "paper_2608_28952_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{name}_n4096_traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/<kernel>_n4096_b64_traffic.md, lines `key: value`), if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{name}_n4096_b64_traffic.md")
     if not os.path.exists(path):
         return None
+    kv = {}
     with open(path) as f:
-        t = json.load(f)
-    if t.get("source_sha256_16") != kernel_source_hash(name):
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip().lstrip("-* ").strip("`")] = v.strip().strip("`")
+    if kv.get("source_sha256_16") != kernel_source_hash(name):
         return None
-    return t.get("hbm_bytes_per_launch")
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
-def cpu_baseline(A, gpu_sweeps, budget_rotations=None):
-    """Oracle timed on a bounded sample: the first rounds of the first sweep of
-    the scalar round-robin oracle on the same n = 4096 matrix, all host cores.
-    Scaled to s/solve: (time per rotation) x n(n-1)/2 rotations per sweep x
-    the sweep count of the GPU solve on the same matrix."""
+def cpu_baseline(A, gpu_sweeps, target_s=15.0):
+    """The oracle (scalar round-robin Jacobi, FP64, all host cores) on the same
+    matrix: rounds of sweep 1 until about target_s seconds, scaled to s/solve
+    as (time per rotation) x n(n-1)/2 rotations per sweep x the GPU's sweep
+    count."""
     from oracle import oracle as O
     cores = os.cpu_count() or 1
     n = A.shape[0]
-    rot = budget_rotations or 64 * (n // 2)  # 64 rounds of n/2 rotations
     t0 = time.perf_counter()
-    r = O.eig(A, order=1, nthreads=cores, max_rotations=rot, max_sweeps=1)
+    r = O.eig(A, order=1, nthreads=cores, max_rotations=n // 2, max_sweeps=1)
+    dt = time.perf_counter() - t0
+    rounds = int(min(n - 1, max(1, target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    r = O.eig(A, order=1, nthreads=cores, max_rotations=rounds * (n // 2), max_sweeps=1)
     dt = time.perf_counter() - t0
     per_rot = dt / max(r.rotations, 1)
-    per_sweep = per_rot * n * (n - 1) / 2
-    return {"value": per_sweep * gpu_sweeps, "unit": "s/solve", "cores": cores, "kind": "oracle",
-            "sample": (f"{r.rotations} rotations ({r.rotations // (n // 2)} round-robin rounds) of sweep 1 "
-                       f"on the same n={n} matrix in {dt:.1f} s, scaled by n(n-1)/2 rotations/sweep x "
-                       f"{gpu_sweeps} sweeps (the GPU's sweep count)")}
+    return {"value": per_rot * n * (n - 1) / 2 * gpu_sweeps, "unit": "s/solve", "cores": cores, "kind": "oracle",
+            "seconds_measured": dt,
+            "sample": (f"{r.rotations} rotations ({r.rotations // (n // 2)} round-robin rounds of sweep 1) on the "
+                       f"same n={n} matrix in {dt:.1f} s, scaled by n(n-1)/2 rotations per sweep x {gpu_sweeps} "
+                       f"sweeps (the GPU solve's sweep count)")}
+
+
+def copy_probe(mib, reps=20):
+    """A plain device copy of `mib` MiB, `reps` times (reads and writes mib MiB
+    each): the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "reps": reps, "bytes_read_per_launch": n * 8,
+                      "bytes_written_per_launch": n * 8}), flush=True)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def extras(jx):
+    import torch
+    from paper_2608_28952_amd import inputs
+    out = {}
+    log("extras: batched workload")
+    # batched workload against per-matrix plain FP64 calls
+    sizes, offs, packed = inputs.batched_case(10000, 4)
+    o = jx.opts_default(precision=jx.PREC_MIXED_FP32)
+    dA = torch.from_numpy(packed).cuda()
+    ws = torch.empty(jx.batched_workspace(sizes, False, o), dtype=torch.uint8, device="cuda")
+    W = torch.empty(int(sizes.sum()), dtype=torch.float64, device="cuda")
+    Q = torch.empty(int(offs[-1]), dtype=torch.float64, device="cuda")
+    times = []
+    for _ in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, infos = jx.jacobi_eig_batched(sizes, offs, dA, opts=o, work=ws, out=(W, Q))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ok = all(i["status"] == 0 for i in infos)
+    tb = float(np.median(times[1:]))
+    idx = np.random.default_rng(0).choice(len(sizes), 40, replace=False)
+    tp = 0.0
+    for k in idx:
+        n = int(sizes[k])
+        A = torch.from_numpy(np.ascontiguousarray(packed[offs[k]:offs[k + 1]].astype(np.float64)
+                                                  .reshape((n, n), order="F"))).cuda()
+        jx.jacobi_eig(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        jx.jacobi_eig(A)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t0
+    plain = len(idx) / tp
+    out["batched"] = {"workload": "10,000 symmetric matrices, n ~ U{16..256}, lambda ~ N(0,1), FP32 stored, seed 4; "
+                                  "FP32 phase + FP64 refinement to off(A) <= 1e-14 ||A||_F, one cached hipGraph launch",
+                      "solves_per_s": len(sizes) / tb, "ms_per_batch": tb * 1e3, "all_converged": ok,
+                      "max_off_rel": max(i["off_rel"] for i in infos),
+                      "fp32_sweeps_mean": float(np.mean([i["sweeps_by_prec"][1] for i in infos])),
+                      "fp64_sweeps_mean": float(np.mean([i["sweeps_by_prec"][2] for i in infos])),
+                      "plain_fp64_per_matrix_solves_per_s": plain,
+                      "plain_sample": "40 matrices of the batch, one jacobi_eig call each (FP64)",
+                      "speedup_vs_plain": (len(sizes) / tb) / plain}
+    del dA, ws, W, Q
+    log("extras: FP32 ladder n=4096")
+    # FP32 ladder on the headline matrix
+    A_np, lam = inputs.eig_graded(N, SEED)
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+    om = jx.opts_default(block=BLOCK, precision=jx.PREC_MIXED_FP32)
+    work = torch.empty(jx.jacobi_eig_workspace(N, om), dtype=torch.uint8, device="cuda")
+    jx.jacobi_eig(A, opts=om, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wm, Qm, info = jx.jacobi_eig(A, opts=om, work=work)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    out["mixed_fp32_eig_n4096"] = {"s_per_solve": tm, "sweeps_by_prec": info["sweeps_by_prec"],
+                                   "max_abs_eig_err_vs_construction":
+                                       float(np.max(np.abs(Wm.cpu().numpy() - np.sort(lam))))}
+    del A, work
+    log("extras: SVD 16384 x 2048")
+    # one-sided SVD, FP64 and FP32 ladder
+    G_np, sigma = inputs.svd_case(16384, 2048, 3)
+    G = torch.from_numpy(np.ascontiguousarray(G_np)).cuda()
+    ref = np.sort(sigma)[::-1]
+    for name, prec in (("svd_16384x2048_fp64", jx.PREC_FP64), ("svd_16384x2048_mixed_fp32", jx.PREC_MIXED_FP32)):
+        os_ = jx.opts_default(precision=prec)
+        jx.jacobi_svd(G, opts=os_)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S, U, V, info = jx.jacobi_svd(G, opts=os_)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        Sn = S.cpu().numpy()
+        out[name] = {"s_per_solve": ts, "sweeps_by_prec": info["sweeps_by_prec"],
+                     "max_rel_sigma_err_vs_construction": float(np.max(np.abs(Sn - ref) / ref))}
+    return out
 
 
 def main():
@@ -80,11 +200,16 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not a benchmark", file=sys.stderr)
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding is described in DESIGN.md, not benchmarked", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
     from paper_2608_28952_amd import inputs
@@ -96,6 +221,7 @@ def main():
     work = torch.empty(jx.jacobi_eig_workspace(N, o), dtype=torch.uint8, device="cuda")
     L = jx.lib()
 
+    log(f"warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         jx.jacobi_eig(A, opts=o, work=work)
     torch.cuda.synchronize()
@@ -122,20 +248,22 @@ def main():
 
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
-    avg_s = d["ms"] / 1e3 / max(d["launches"], 1)
-    if dom in ("k_update_a", "k_update_q", "k_gemm_f64"):
-        ach = d["flops"] / max(d["launches"], 1) / avg_s / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64_mfma_tflops"], "unit": "TFLOP/s",
-                "frac": ach / PEAK["fp64_mfma_tflops"]}
-    else:
-        ach = d["flops"] / max(d["launches"], 1) / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK["fp64_vector_tflops"], "unit": "TFLOP/s",
-                "frac": ach / PEAK["fp64_vector_tflops"]}
-    roof["kernel"] = dom
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["launches"] = d["launches"]
-    roof["traffic"] = traffic_for(dom)
-    kernel_share = {k: round(v["ms"] / max(sum(x["ms"] for x in prof.values()), 1e-9), 4) for k, v in prof.items()}
+    launches = max(d["launches"], 1)
+    avg_s = d["ms"] / 1e3 / launches
+    ach = d["flops"] / launches / avg_s / 1e12
+    bound = "alu" if dom == "k_subproblem2" else "mfma"
+    roof = {"bound": bound, "achieved": ach, "peak": PEAK["fp64_tflops"], "unit": "TFLOP/s",
+            "frac": ach / PEAK["fp64_tflops"], "traffic": None,
+            "kernel": dom, "avg_launch_us": avg_s * 1e6, "launches": d["launches"],
+            "algorithmic_flops_per_launch": d["flops"] / launches}
+    t = traffic_for(dom)
+    if t is not None:
+        roof["traffic"] = t
+    others = {k: {"avg_launch_us": v["ms"] * 1e3 / max(v["launches"], 1), "launches": v["launches"],
+                  "achieved_tflops": (v["flops"] / max(v["ms"], 1e-12) / 1e9) if v["ms"] > 0 else 0.0}
+              for k, v in prof.items()}
+    total_ms = sum(x["ms"] for x in prof.values())
+    share = {k: round(v["ms"] / max(total_ms, 1e-9), 4) for k, v in prof.items()}
 
     out = {
         "metric": METRIC,
@@ -150,14 +278,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "blocked two-sided Jacobi eig, n=4096, b=64, graded spectrum +-10^(-8i/n), "
-                               "Haar Q seed 2, tol 1e-14, eigenvectors + refinement",
+        "config": {"workload": "blocked two-sided Jacobi eig, n=4096, b=64 (32 block pairs per parallel step), "
+                               "graded spectrum +-10^(-8i/n), Haar Q seed 2, FP64, off(A) <= 1e-14 ||A||_F, "
+                               "eigenvectors + orthogonality refinement",
                    "n": N, "block": BLOCK, "sweeps": sweeps, "max_abs_eig_err_vs_construction": err,
-                   "kernel_time_share": kernel_share},
+                   "kernel_time_share": share, "kernels": others},
         "roofline": roof,
     }
+    log(f"{sec:.3f} s/solve, {sweeps} sweeps")
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(A_np, sweeps)
+    if not args.no_extras:
+        del A, work
+        torch.cuda.empty_cache()
+        out["extras"] = extras(jx)
     print(json.dumps(out), flush=True)
 
 

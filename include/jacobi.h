@@ -300,8 +300,11 @@ enum jacobi_prof_kind {
 /*
  * on != 0: from now on every launch of the kernels above records a HIP event
  * pair on its launch stream plus its algorithmic work (flops and HBM bytes
- * the method needs for that launch; rotation tiles whose both sides were
- * skipped count zero).  Clears earlier records.  Synchronises the device.
+ * the method needs for that launch; skipped pairs and rotation tiles whose
+ * both sides were skipped count zero; a rotated 2b x 2b subproblem counts one
+ * scalar round-robin sweep: (2b - 1) rounds of b(b - 1)/2 pair-block updates
+ * at 24 flops plus 2b x b rotated pairs of V at 6 flops).  Clears earlier
+ * records.  Synchronises the device.
  * Not thread-safe against concurrent solver calls.  Returns 0 or 3.
  */
 int jacobi_profile_enable(int on);

@@ -229,8 +229,10 @@ struct EigState {
                 JX_HIP(hipStreamWaitEvent(s, ev_q[buf], 0));
                 q_pending[buf] = false;
             }
+            // flags of this round land in the profiler's flag log at `slot`
+            const int slot_next = (h_flaglog && flog_count < flog_cap) ? flog_base + flog_count * p.H : -1;
             {
-                ProfScope ps(PROF_SUBPROBLEM, s, k1_flops, k1_bytes);
+                ProfScope ps(PROF_SUBPROBLEM, s, k1_flops / p.H, k1_bytes / p.H, slot_next, p.H, m2);
                 launch_subproblem(a, s);
             }
             int slot = -1;

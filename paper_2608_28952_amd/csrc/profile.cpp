@@ -129,8 +129,17 @@ extern "C" int jacobi_profile_query(int kind, int *launches, double *total_ms, d
             if (r.flag_slot >= 0 && r.flag_slot + r.npairs <= (int)g_flag_log.size()) {
                 double f = 0.0, b = 0.0;
                 const int *fl_ = g_flag_log.data() + r.flag_slot;
-                if (kind == PROF_UPDATE_A) tile_work(fl_, r.npairs, r.m2, f, b);
-                else qupd_work(fl_, r.npairs, r.m2, r.flops, f, b);  // r.flops holds the row count
+                if (kind == PROF_UPDATE_A) {
+                    tile_work(fl_, r.npairs, r.m2, f, b);
+                } else if (kind == PROF_SUBPROBLEM) {  // r.flops / r.bytes: per rotated pair
+                    for (int q = 0; q < r.npairs; ++q)
+                        if (!fl_[q]) {
+                            f += r.flops;
+                            b += r.bytes;
+                        }
+                } else {
+                    qupd_work(fl_, r.npairs, r.m2, r.flops, f, b);  // r.flops holds the row count
+                }
                 fl += f;
                 by += b;
             } else {
