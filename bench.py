@@ -259,6 +259,12 @@ def main():
     t = traffic_for(dom)
     if t is not None:
         roof["traffic"] = t
+    # whole-solve rate: Alg. 2's rotation-apply work per sweep, 12 n^2 b (N - 1)
+    # flops (both block rows and block columns of A, and Q), over the solve time
+    nb = N // BLOCK
+    f_sweep = 12.0 * N * N * BLOCK * (nb - 1)
+    solve_rate = {"flops_per_sweep": f_sweep, "tflops": f_sweep * sweeps / sec / 1e12,
+                  "frac_of_fp64_peak": f_sweep * sweeps / sec / 1e12 / PEAK["fp64_tflops"]}
     others = {k: {"avg_launch_us": v["ms"] * 1e3 / max(v["launches"], 1), "launches": v["launches"],
                   "achieved_tflops": (v["flops"] / max(v["ms"], 1e-12) / 1e9) if v["ms"] > 0 else 0.0}
               for k, v in prof.items()}
@@ -282,7 +288,7 @@ def main():
                                "graded spectrum +-10^(-8i/n), Haar Q seed 2, FP64, off(A) <= 1e-14 ||A||_F, "
                                "eigenvectors + orthogonality refinement",
                    "n": N, "block": BLOCK, "sweeps": sweeps, "max_abs_eig_err_vs_construction": err,
-                   "kernel_time_share": share, "kernels": others},
+                   "kernel_time_share": share, "kernels": others, "solve_rotation_apply_rate": solve_rate},
         "roofline": roof,
     }
     log(f"{sec:.3f} s/solve, {sweeps} sweeps")
