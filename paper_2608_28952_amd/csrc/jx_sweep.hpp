@@ -18,12 +18,15 @@
 //     1 <- 2 <- 4 <- ... <- m2-2 <- m2-1 <- m2-3 <- ... <- 3 <- 1 (0 stays), so
 //     that every index pair meets once per sweep; two values per thread cross
 //     to the neighbouring lane.  After m2 - 1 rounds positions equal indices.
-//   * Rotation parameters (c, s, t, a_pq per pair): LDS, two rounds.  The
-//     pivot a_pq of a round becomes zero and is not written: in the next round
-//     it lies in a known pair-block, which reads it as zero.  The pair-blocks
-//     that compute the next round's pivots also update the two diagonal
-//     entries of that pair and write the next round's parameters, so a round
-//     needs one barrier.
+//   * Rotation parameters (c, s and the diagonal shift t a_pq per pair): LDS,
+//     two rounds.  The pivot a_pq of a round becomes zero and is not written:
+//     in the next round it lies in a known pair-block, which reads it as zero.
+//     The pair-blocks that compute the next round's pivots also update the two
+//     diagonal entries of that pair and write the next round's parameters, so
+//     a round needs one barrier.
+//   * A round is bound by VALU issue (every lane of a wave executes every
+//     instruction): the next round's parameters are computed only in the
+//     waves that hold producers (a wave-uniform branch).
 #pragma once
 
 #include "jx_common.hpp"
@@ -119,44 +122,61 @@ __device__ __forceinline__ double rsq_nr(double x) {
     return fma(0.5 * y, r, y);
 }
 
-// Rotation (c, s, t) that zeroes a_pq.  With d = a_qq - a_pp, e = 2 a_pq,
-// theta = d / e and r = sqrt(d^2 + e^2), the smaller root of t^2 + 2 theta t = 1
-// is t = sgn(theta) / (|theta| + sqrt(1 + theta^2)) = sgn(theta) |e| / (|d| + r)
-// (sgn(0) = +1), c = 1 / sqrt(1 + t^2), s = t c.  The second form needs one
-// reciprocal and two reciprocal square roots; where d^2 + e^2 leaves the
-// normal range the first form is used (for huge |theta|, t = 1 / (2 theta)).
+// Rotation (c, s, t) that zeroes a_pq, without branches.  With d = a_qq - a_pp,
+// e = 2 a_pq, theta = d / e and r = sqrt(d^2 + e^2), the smaller root of
+// t^2 + 2 theta t = 1 is t = sgn(theta) / (|theta| + sqrt(1 + theta^2)) =
+// sgn(theta) |e| / (|d| + r) (sgn(0) = +1), c = 1 / sqrt(1 + t^2), s = t c.
+// d and e are first scaled by one power of two (t depends only on their
+// ratio) so that the larger magnitude lies in [1/2, 1): d^2 + e^2 then lies in
+// [1/4, 2), with no overflow or harmful underflow at any input magnitude.  One
+// reciprocal and two reciprocal square roots.
 __device__ __forceinline__ void rot_cst(double app, double aqq, double apq, double &c, double &s, double &t) {
-    const double d = aqq - app, e = 2.0 * apq;
+    const double d0 = aqq - app, e0 = 2.0 * apq;
+    int k;
+    (void)frexp(fmax(fabs(d0), fabs(e0)), &k);
+    const double d = ldexp(d0, -k), e = ldexp(e0, -k);
     const double x = fma(d, d, e * e);
     const double r = x * rsq_nr(x);
     double tt = fabs(e) * rcp_nr(fabs(d) + r);
     tt = (d != 0.0 && ((d < 0.0) != (e < 0.0))) ? -tt : tt;
-    double cc = rsq_nr(fma(tt, tt, 1.0));
-    if (!(x > 1e-280 && x < 1e280)) {  // rare: extreme magnitudes
-        tt = 0.0;
-        cc = 1.0;
-        if (apq != 0.0) {
-            const double th = d / e;
-            const double ath = fabs(th);
-            tt = ath > 1e150 ? 0.5 / ath : 1.0 / (ath + sqrt(1.0 + th * th));
-            if (th < 0.0) tt = -tt;
-            cc = 1.0 / sqrt(1.0 + tt * tt);
-        }
-    }
-    if (apq == 0.0) { tt = 0.0; cc = 1.0; }
-    c = cc;
-    s = tt * cc;
-    t = tt;
+    const double cc = rsq_nr(fma(tt, tt, 1.0));
+    const bool none = apq == 0.0;
+    c = none ? 1.0 : cc;
+    s = none ? 0.0 : tt * cc;
+    t = none ? 0.0 : tt;
 }
 
-// Rotation parameters of pair k (c, s, t, a_pq) into the parameter arrays.
+// Rotation parameters of pair k into the parameter arrays: c, s and the
+// diagonal shift t a_pq (a_pp -= t a_pq, a_qq += t a_pq).
 __device__ __forceinline__ void rot_params(double app, double aqq, double apq, double *prm, int k, int H) {
     double c, s, t;
     rot_cst(app, aqq, apq, c, s, t);
     prm[k] = c;
     prm[H + k] = s;
-    prm[2 * H + k] = t;
-    prm[3 * H + k] = apq;
+    prm[2 * H + k] = t * apq;
+}
+
+// Value of the next / previous lane within groups of G consecutive lanes (the
+// group's last / first lane gets an unspecified value).  G = 2, 4: DPP quad
+// permutes, which stay in the VALU (no LDS round trip); otherwise shuffles.
+template <int CTRL>
+__device__ __forceinline__ double dpp_quad_t(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int G>
+__device__ __forceinline__ double lane_next(double v) {
+    if constexpr (G == 2) return dpp_quad_t<(1 | 1 << 2 | 3 << 4 | 3 << 6)>(v);  // quad_perm [1,1,3,3]
+    else if constexpr (G == 4) return dpp_quad_t<(1 | 2 << 2 | 3 << 4 | 3 << 6)>(v);  // [1,2,3,3]
+    else return __shfl_down(v, 1, G);
+}
+template <int G>
+__device__ __forceinline__ double lane_prev(double v) {
+    if constexpr (G == 2) return dpp_quad_t<(0 | 0 << 2 | 2 << 4 | 2 << 6)>(v);  // quad_perm [0,0,2,2]
+    else if constexpr (G == 4) return dpp_quad_t<(0 | 0 << 2 | 1 << 4 | 2 << 6)>(v);  // [0,0,1,2]
+    else return __shfl_up(v, 1, G);
 }
 
 // ---------------------------------------------------------------------------
@@ -233,6 +253,9 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
         icode[ii] = (st + 1) | ((kn + 1) << 3) | (pv << 10) | (mp << 12) | (mq << 14);
     }
 
+    // The producer items (distance <= 2, the first item of threads < 2H) fill
+    // whole waves: a wave-uniform branch keeps the parameter work out of the others.
+    const bool prod_wave = __builtin_amdgcn_readfirstlane(tid) < 2 * H;
     const double eps = 2.220446049250313e-16;
     const int cap = conv ? 30 : nsw;
     int gr = 0;  // rounds done (parameter buffer parity)
@@ -250,86 +273,109 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
         for (int t = 0; t < R; ++t, ++gr) {
             const double *pc = prm0 + (gr & 1) * 4 * H;  // this round
             double *pn = prm0 + ((gr + 1) & 1) * 4 * H;  // next round
+            // ---- every load of the round first: the compiler keeps LDS loads
+            //      behind earlier stores that might alias, so loads issued after
+            //      a store would cost one LDS round trip each
+            double cs[MAXI][4], xv[MAXI][4];
+            int ia[MAXI][4];
 #pragma unroll
             for (int ii = 0; ii < MAXI; ++ii) {
-                const bool valid = ii * NT + tid < NOFF;
                 const int k1 = ikk[ii] & 255, k2 = ikk[ii] >> 8;
-                const int code = icode[ii];
                 const int sp1 = isl[ii][0], sq1 = isl[ii][1], sp2 = isl[ii][2], sq2 = isl[ii][3];
-                const double c1 = pc[k1], s1 = pc[H + k1], c2 = pc[k2], s2 = pc[H + k2];
-                const int i11 = min(sp1, sp2) * LD + max(sp1, sp2);
-                const int i12 = min(sp1, sq2) * LD + max(sp1, sq2);
-                const int i21 = min(sq1, sp2) * LD + max(sq1, sp2);
-                const int i22 = min(sq1, sq2) * LD + max(sq1, sq2);
-                double x11 = As[i11], x12 = As[i12], x21 = As[i21], x22 = As[i22];
-                // producer operands (first item only; diagonal entries are
-                // written by their producer alone, never by an item)
-                const int kn = ((code >> 3) & 127) - 1;
-                const int pv = (code >> 10) & 3, mp = (code >> 12) & 3, mq = (code >> 14) & 3;
-                const int spn = mp == 0 ? sp1 : (mp == 1 ? sq1 : (mp == 2 ? sp2 : sq2));
-                const int sqn = mq == 0 ? sp1 : (mq == 1 ? sq1 : (mq == 2 ? sp2 : sq2));
-                const int pp = mp < 2 ? k1 : k2, pq_ = mq < 2 ? k1 : k2;
-                double dpo = 0.0, dqo = 0.0, tp = 0.0, tq = 0.0;
-                if (ii == 0) {
-                    dpo = As[spn * (LD + 1)];
-                    dqo = As[sqn * (LD + 1)];
-                    tp = pc[2 * H + pp] * pc[3 * H + pp];
-                    tq = pc[2 * H + pq_] * pc[3 * H + pq_];
-                }
-                if (ii == 0 && t > 0) {  // previous pivots: first item only (d <= 2)
-                    const int st = (code & 7) - 1;
-                    x11 = st == 0 ? 0.0 : x11;
-                    x12 = st == 1 ? 0.0 : x12;
-                    x21 = st == 2 ? 0.0 : x21;
-                    x22 = st == 3 ? 0.0 : x22;
-                }
-                // left: rows p1, q1; right: columns p2, q2
+                cs[ii][0] = pc[k1];
+                cs[ii][1] = pc[H + k1];
+                cs[ii][2] = pc[k2];
+                cs[ii][3] = pc[H + k2];
+                ia[ii][0] = min(sp1, sp2) * LD + max(sp1, sp2);
+                ia[ii][1] = min(sp1, sq2) * LD + max(sp1, sq2);
+                ia[ii][2] = min(sq1, sp2) * LD + max(sq1, sp2);
+                ia[ii][3] = min(sq1, sq2) * LD + max(sq1, sq2);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) xv[ii][m] = As[ia[ii][m]];
+            }
+            // producer operands (first item of the producer waves; diagonal
+            // entries are written by their producer alone, never by an item)
+            const int code = icode[0];
+            const int kn = ((code >> 3) & 127) - 1;
+            const int pv = (code >> 10) & 3, mp = (code >> 12) & 3, mq = (code >> 14) & 3;
+            int spn = 0, sqn = 0;
+            double dpo = 0.0, dqo = 0.0, tp = 0.0, tq = 0.0;
+            if (prod_wave) {
+                const int k1 = ikk[0] & 255, k2 = ikk[0] >> 8;
+                const int sp1 = isl[0][0], sq1 = isl[0][1], sp2 = isl[0][2], sq2 = isl[0][3];
+                // two-level selects on single bits stay selects
+                spn = (mp & 2) ? ((mp & 1) ? sq2 : sp2) : ((mp & 1) ? sq1 : sp1);
+                sqn = (mq & 2) ? ((mq & 1) ? sq2 : sp2) : ((mq & 1) ? sq1 : sp1);
+                dpo = As[spn * (LD + 1)];
+                dqo = As[sqn * (LD + 1)];
+                tp = pc[2 * H + (mp < 2 ? k1 : k2)];
+                tq = pc[2 * H + (mq < 2 ? k1 : k2)];
+                // the previous round's pivot lies in this block: read as zero
+                const int st0 = t > 0 ? (code & 7) - 1 : -1;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) xv[0][m] = st0 == m ? 0.0 : xv[0][m];
+            }
+            double vc[P / 2], vs[P / 2];  // this thread's position pairs
+#pragma unroll
+            for (int j = 0; j < P / 2; ++j) {
+                vc[j] = pc[(P / 2) * g + j];
+                vs[j] = pc[H + (P / 2) * g + j];
+            }
+
+            // ---- rotate the pair-blocks: left rows p1, q1; right columns p2, q2
+            double piv = 0.0;
+#pragma unroll
+            for (int ii = 0; ii < MAXI; ++ii) {
+                const double c1 = cs[ii][0], s1 = cs[ii][1], c2 = cs[ii][2], s2 = cs[ii][3];
+                const double x11 = xv[ii][0], x12 = xv[ii][1], x21 = xv[ii][2], x22 = xv[ii][3];
                 const double y11 = c1 * x11 - s1 * x21, y21 = s1 * x11 + c1 * x21;
                 const double y12 = c1 * x12 - s1 * x22, y22 = s1 * x12 + c1 * x22;
                 const double z11 = c2 * y11 - s2 * y12, z12 = s2 * y11 + c2 * y12;
                 const double z21 = c2 * y21 - s2 * y22, z22 = s2 * y21 + c2 * y22;
-                if (valid) {
-                    As[i11] = z11;
-                    As[i12] = z12;
-                    As[i21] = z21;
-                    As[i22] = z22;
+                if (ii * NT + tid < NOFF) {
+                    As[ia[ii][0]] = z11;
+                    As[ia[ii][1]] = z12;
+                    As[ia[ii][2]] = z21;
+                    As[ia[ii][3]] = z22;
                 }
-                if (ii == 0) {
-                    // diagonal of next round's pair kn after this round's
-                    // rotation (p-member a_pp - t a_pq, q-member a_qq + t a_pq),
-                    // then its parameters (computed by every lane, stored by producers)
-                    const double piv = pv == 0 ? z11 : (pv == 1 ? z12 : (pv == 2 ? z21 : z22));
-                    const double dp = dpo + ((mp & 1) ? tp : -tp);
-                    const double dq = dqo + ((mq & 1) ? tq : -tq);
-                    double cn, sn, tn;
-                    rot_cst(dp, dq, piv, cn, sn, tn);
-                    if (valid && kn >= 0) {
-                        As[spn * (LD + 1)] = dp;
-                        As[sqn * (LD + 1)] = dq;
-                        pn[kn] = cn;
-                        pn[H + kn] = sn;
-                        pn[2 * H + kn] = tn;
-                        pn[3 * H + kn] = piv;
-                    }
+                if (ii == 0) piv = (pv & 2) ? ((pv & 1) ? z22 : z21) : ((pv & 1) ? z12 : z11);
+            }
+
+            // ---- next round's parameters: diagonal of pair kn after this
+            //      round's rotation (p-member a_pp - t a_pq, q-member
+            //      a_qq + t a_pq), then (c, s, t a_pq); computed by the whole
+            //      wave, stored by the producers
+            if (prod_wave) {
+                const double dp = dpo + ((mp & 1) ? tp : -tp);
+                const double dq = dqo + ((mq & 1) ? tq : -tq);
+                double cn, sn, tn;
+                rot_cst(dp, dq, piv, cn, sn, tn);
+                if (kn >= 0) {
+                    As[spn * (LD + 1)] = dp;
+                    As[sqn * (LD + 1)] = dq;
+                    pn[kn] = cn;
+                    pn[H + kn] = sn;
+                    pn[2 * H + kn] = tn * piv;
                 }
+            }
+#pragma unroll
+            for (int ii = 0; ii < MAXI; ++ii)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int sl = isl[ii][m];
                     isl[ii][m] = sl == 0 ? 0 : (sl == R ? 1 : sl + 1);
                 }
-            }
-            // V <- V J on this thread's P/2 position pairs, then one ring step
+
+            // ---- V <- V J on this thread's P/2 position pairs, then one ring step
 #pragma unroll
             for (int j = 0; j < P / 2; ++j) {
-                const int k = (P / 2) * g + j;
-                const double cc = pc[k], ss = pc[H + k];
                 const double e = V[2 * j], o = V[2 * j + 1];
-                V[2 * j] = cc * e - ss * o;
-                V[2 * j + 1] = ss * e + cc * o;
+                V[2 * j] = vc[j] * e - vs[j] * o;
+                V[2 * j + 1] = vs[j] * e + vc[j] * o;
             }
             {
-                const double from_right = __shfl_down(V[0], 1, G);
-                const double from_left = __shfl_up(V[P - 1], 1, G);
+                const double from_right = lane_next<G>(V[0]);
+                const double from_left = lane_prev<G>(V[P - 1]);
                 const double e0 = V[0], e1 = V[2], olast = V[P - 1];
 #pragma unroll
                 for (int j = 0; j < P / 2 - 1; ++j) V[2 * j] = V[2 * j + 2];

@@ -237,14 +237,28 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
     }
     double off2 = 0.0, fro2 = 0.0;
     {
+        // the upper triangle of A_hat, column-major positions e = c M2 + r (a
+        // wave's 64 positions share a column half: one source block per
+        // wave), eight loads in flight per thread before their LDS stores
         const HatSource<M2, MODE> load(a, pr);
-        for (int e = tid; e < M2 * M2; e += NT) {
-            const int r = e % M2, c = e / M2;
-            if (r > c) continue;
-            const double v = load(r, c);
-            Ap[pk(r, c)] = v;
-            if (r == c) fro2 += v * v;
-            else { off2 += 2.0 * v * v; fro2 += 2.0 * v * v; }
+#pragma unroll 1
+        for (int e0 = 0; e0 < M2 * M2; e0 += 8 * NT) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * NT + tid, r = e % M2, c = e / M2;
+                v[u] = r <= c ? load(r, c) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * NT + tid, r = e % M2, c = e / M2;
+                if (r <= c) {
+                    Ap[pk(r, c)] = v[u];
+                    const double w2 = v[u] * v[u];
+                    if (r == c) fro2 += w2;
+                    else { off2 += 2.0 * w2; fro2 += 2.0 * w2; }
+                }
+            }
         }
     }
     off2 = block_sum<NT>(off2, red);
@@ -252,182 +266,247 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
     auto get = [&](int r, int c) { return Ap[pkm(r, c)]; };
     if (skip_test<M2, NT, MODE>(a, pr, off2, red, get)) return;
 
-    // Vt = I: tile tt, lane (g, x), component v holds Vt(16 tt + g + 4 v, 16 wv + x)
-    d4 vt[NB];
-#pragma unroll
-    for (int tt = 0; tt < NB; ++tt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) vt[tt][v] = (16 * tt + g + 4 * v == 16 * wv + x) ? 1.0 : 0.0;
-
+    // Number of inner sweeps: both roles evaluate this identically (the same
+    // workgroup barriers, the same decision).
     const double eps = 2.220446049250313e-16;
     const bool conv = a.inner_sweeps <= 0;
     const int cap = conv ? 30 : a.inner_sweeps;
-    for (int swp = 0; swp < cap; ++swp) {
-        if (conv && swp > 0) {
-            double o = 0.0;
-            for (int e = tid; e < M2 * M2; e += NT) {
-                const int rr = e % M2, cc = e / M2;
-                if (rr < cc) { const double v = Ap[pk(rr, cc)]; o += 2.0 * v * v; }
-            }
-            o = block_sum<NT>(o, red);
-            if (sqrt(o) <= eps * sqrt(fro2)) break;
+    auto more = [&](int swp) -> bool {
+        if (swp >= cap) return false;
+        if (!conv || swp == 0) return true;
+        double o = 0.0;
+        for (int e = tid; e < M2 * M2; e += NT) {
+            const int rr = e % M2, cc = e / M2;
+            if (rr < cc) { const double v = Ap[pk(rr, cc)]; o += 2.0 * v * v; }
         }
-        for (int t = 0; t < NB - 1; ++t) {
-            // ---- phase 1: waves k, k+4 diagonalise (one sweep) the 32 x 32
-            //      problem of block pair k (waves k and k+4 run on different
-            //      SIMDs, and so do the four waves holding the rotation
-            //      producers); local index l < 16 is row l of block ba,
-            //      l >= 16 row l - 16 of block bb
-            {
-                const int k = wv & 3, lt = ((wv >> 2) << 6) | lane;
-                double *S = Ap + AP + k * SW;  // slots
-                double *prm = S + 32 * 32;     // parameters
-                double *W = S + WOFF;          // rotation, row-major stride 33
+        o = block_sum<NT>(o, red);
+        return !(sqrt(o) <= eps * sqrt(fro2));
+    };
+
+    if (wv < 4) {
+        // ================= solver role: wave k owns pair problem k =================
+        const int k = wv;
+        double *S = Ap + AP + k * SW;  // slots
+        double *prm = S + 32 * 32;     // parameters
+        double *W = S + WOFF;          // rotation, row-major stride 33
+        const double *Wl = Ap + AP + WOFF + g * 33 + x;  // W reads: lane base + constant
+        // This lane's entries of the 528-entry upper triangle (diagonal
+        // included) of a 32 x 32 pair problem: the triangle is read as a 16 x 33
+        // rectangle (rows a and 31 - a together hold 33 entries); entry i is
+        // e = lane + 64 i.  lr: local (row, col) packed; si: slot-array index.
+        constexpr int NG = (528 + 63) / 64;
+        int lr[NG], si[NG];
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int e = min(lane + 64 * i, 527), ra = e / 33, cb = e - 33 * ra;
+            const int r = cb < 32 - ra ? ra : 31 - ra, c = cb < 32 - ra ? ra + cb : cb - 1;
+            const int u = slot_of(r, 32), w = slot_of(c, 32);
+            lr[i] = r | (c << 8);
+            si[i] = min(u, w) * 32 + max(u, w);
+        }
+        for (int swp = 0; more(swp); ++swp) {
+            for (int t = 0; t < NB - 1; ++t) {
+                // ---- phase 1: one sweep on the 32 x 32 problem of block pair k;
+                //      local index l < 16 is row l of block ba, l >= 16 row
+                //      l - 16 of block bb
                 const int ba = index_at(2 * k, t, NB), bb = index_at(2 * k + 1, t, NB);
-                for (int e = lt; e < 32 * 32; e += 128) {
-                    const int r = e & 31, c = e >> 5;
-                    if (r > c) continue;
-                    const int gr = r < BS ? BS * ba + r : BS * bb + (r - BS);
-                    const int gc = c < BS ? BS * ba + c : BS * bb + (c - BS);
-                    const int u = slot_of(r, 32), w = slot_of(c, 32);
-                    S[min(u, w) * 32 + max(u, w)] = Ap[pkm(gr, gc)];
-                }
-                __syncthreads();
-                double Vl[8];
-                scalar_sweeps<32, 128, false>(S, prm, nullptr, lt, 1, false, 0.0, Vl);
-                // W(r, 8 h + xx) = Vl[xx], r = lt / 4, h = lt mod 4; D back into A_hat
-                const int r = lt >> 2, h = lt & 3;
+                auto glob = [&](int l) { return l < BS ? BS * ba + l : BS * bb + (l - BS); };
+                int ai[NG];  // A_hat (packed) index of each entry
 #pragma unroll
-                for (int xx = 0; xx < 8; ++xx) W[r * 33 + 8 * h + xx] = Vl[xx];
-                for (int e = lt; e < 32 * 32; e += 128) {
-                    const int rr = e & 31, cc = e >> 5;
-                    if (rr > cc) continue;
-                    const int gr = rr < BS ? BS * ba + rr : BS * bb + (rr - BS);
-                    const int gc = cc < BS ? BS * ba + cc : BS * bb + (cc - BS);
-                    const int u = slot_of(rr, 32), w = slot_of(cc, 32);
-                    Ap[pkm(gr, gc)] = S[min(u, w) * 32 + max(u, w)];
+                for (int i = 0; i < NG; ++i) ai[i] = pkm(glob(lr[i] & 255), glob(lr[i] >> 8));
+                {
+                    double v[NG];
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) v[i] = Ap[ai[i]];
+#pragma unroll
+                    for (int i = 0; i < NG; ++i)
+                        if (lane + 64 * i < 528) S[si[i]] = v[i];
                 }
-            }
-            __syncthreads();
+                wave_lds_sync();
+                double Vl[16];
+                scalar_sweeps<32, 64, true>(S, prm, nullptr, lane, 1, false, 0.0, Vl);
+                __syncthreads();  // X: the V role has read the previous W
+                // W(r, 16 h + xx) = Vl[xx], r = lane / 2, h = lane mod 2; D back into A_hat
+                {
+                    const int r = lane >> 1, h = lane & 1;
+#pragma unroll
+                    for (int xx = 0; xx < 16; ++xx) W[r * 33 + 16 * h + xx] = Vl[xx];
+                }
+                {
+                    double v[NG];
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) v[i] = S[si[i]];
+#pragma unroll
+                    for (int i = 0; i < NG; ++i)
+                        if (lane + 64 * i < 528) Ap[ai[i]] = v[i];
+                }
+                __syncthreads();  // Y: all four W and diagonal blocks in place
 
-            // ---- phase 2a: waves 0..5, tile (p, q), p < q:
-            //      A_hat(p, q) <- W_p^T A_hat(p, q) W_q
-            if (wv < 6) {
-                const int p = wv < 3 ? 0 : (wv < 5 ? 1 : 2);
-                const int q = wv < 3 ? wv + 1 : (wv < 5 ? wv - 1 : 3);
-                const double *Wp = Ap + AP + p * SW + WOFF;
-                const double *Wq = Ap + AP + q * SW + WOFF;
-                const int pa = index_at(2 * p, t, NB), pb = index_at(2 * p + 1, t, NB);
-                const int qa = index_at(2 * q, t, NB), qb = index_at(2 * q + 1, t, NB);
-                auto gp = [&](int l) { return l < BS ? BS * pa + l : BS * pb + (l - BS); };
-                auto gq = [&](int l) { return l < BS ? BS * qa + l : BS * qb + (l - BS); };
-                // T = X W_q, X(i, k) = A_hat(gp(i), gq(k)); T[i][j] lane (g, x)
-                // component v = T(16 i + g + 4 v, 16 j + x)
-                d4 T[2][2];
+                // ---- phase 2: A_hat(p, q) <- W_p^T A_hat(p, q) W_q for the six
+                //      tiles p < q, as twelve column halves j (three per wave);
+                //      computed into registers, written after a barrier (a
+                //      half reads the whole tile)
+                d4 O[3][2];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int hh = 0; hh < 3; ++hh) {
+                    const int h = k + 4 * hh, u = h >> 1, j = h & 1;
+                    const int p = u < 3 ? 0 : (u < 5 ? 1 : 2);
+                    const int q = u < 3 ? u + 1 : (u < 5 ? u - 1 : 3);
+                    const double *Wp = Wl + p * SW;  // W_p(kk, i) = Wp[(kk - g) * 33 + i - x]
+                    const double *Wq = Wl + q * SW;
+                    const int pa = index_at(2 * p, t, NB), pb = index_at(2 * p + 1, t, NB);
+                    const int qa = index_at(2 * q, t, NB), qb = index_at(2 * q + 1, t, NB);
+                    auto gp = [&](int l) { return l < BS ? BS * pa + l : BS * pb + (l - BS); };
+                    auto gq = [&](int l) { return l < BS ? BS * qa + l : BS * qb + (l - BS); };
+                    // T = X W_q (column half j), X(i, kk) = A_hat(gp(i), gq(kk));
+                    // T[i] lane (g, x) component v = T(16 i + g + 4 v, 16 j + x)
+                    d4 T[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) T[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+                    for (int k0 = 0; k0 < 32; k0 += 4) {
+                        const int kk = k0 + g;
+                        const double bq = Wq[k0 * 33 + 16 * j];
+                        const double a0 = Ap[pkm(gp(x), gq(kk))], a1 = Ap[pkm(gp(16 + x), gq(kk))];
+                        T[0] = mfma_f64(a0, bq, T[0]);
+                        T[1] = mfma_f64(a1, bq, T[1]);
+                    }
+                    // O = W_p^T T; step (ti, s) contracts over row 16 ti + g + 4 s of T
+                    O[hh][0] = d4{0.0, 0.0, 0.0, 0.0};
+                    O[hh][1] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int k0 = 0; k0 < 32; k0 += 4) {
-                    const int k = k0 + g;
-                    const double b0 = Wq[k * 33 + x], b1 = Wq[k * 33 + 16 + x];
-                    const double a0 = Ap[pkm(gp(x), gq(k))], a1 = Ap[pkm(gp(16 + x), gq(k))];
-                    T[0][0] = mfma_f64(a0, b0, T[0][0]);
-                    T[0][1] = mfma_f64(a0, b1, T[0][1]);
-                    T[1][0] = mfma_f64(a1, b0, T[1][0]);
-                    T[1][1] = mfma_f64(a1, b1, T[1][1]);
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4) {
+                            const int kk = 16 * ti + 4 * s4;  // + g (in Wl)
+                            const double a0 = Wp[kk * 33], a1 = Wp[kk * 33 + 16];
+                            O[hh][0] = mfma_f64(a0, T[ti][s4], O[hh][0]);
+                            O[hh][1] = mfma_f64(a1, T[ti][s4], O[hh][1]);
+                        }
                 }
-                // out = W_p^T T; step (ti, s) contracts over row 16 ti + g + 4 s of T
-                d4 O[2][2];
+                __syncthreads();  // every read of the six tiles is done
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int hh = 0; hh < 3; ++hh) {
+                    const int h = k + 4 * hh, u = h >> 1, j = h & 1;
+                    const int p = u < 3 ? 0 : (u < 5 ? 1 : 2);
+                    const int q = u < 3 ? u + 1 : (u < 5 ? u - 1 : 3);
+                    const int pa = index_at(2 * p, t, NB), pb = index_at(2 * p + 1, t, NB);
+                    const int qa = index_at(2 * q, t, NB), qb = index_at(2 * q + 1, t, NB);
+                    auto gp = [&](int l) { return l < BS ? BS * pa + l : BS * pb + (l - BS); };
+                    auto gq = [&](int l) { return l < BS ? BS * qa + l : BS * qb + (l - BS); };
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) O[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+                    for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int k = 16 * ti + g + 4 * s;
-                        const double a0 = Wp[k * 33 + x], a1 = Wp[k * 33 + 16 + x];
-                        O[0][0] = mfma_f64(a0, T[ti][0][s], O[0][0]);
-                        O[0][1] = mfma_f64(a0, T[ti][1][s], O[0][1]);
-                        O[1][0] = mfma_f64(a1, T[ti][0][s], O[1][0]);
-                        O[1][1] = mfma_f64(a1, T[ti][1][s], O[1][1]);
-                    }
-                // every read of this tile fed T, so it can be overwritten in place
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) Ap[pkm(gp(16 * i + g + 4 * v), gq(16 * j + x))] = O[i][j][v];
-            }
-
-            // ---- phase 2b: all waves, Vt rows of block pair k <- W_k^T (those rows)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const double *Wk = Ap + AP + k * SW + WOFF;
-                d4 n0 = d4{0.0, 0.0, 0.0, 0.0}, n1 = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int rr = 16 * ti + g + 4 * s;
-                        const double a0 = Wk[rr * 33 + x], a1 = Wk[rr * 33 + 16 + x];
-                        const double bv = vt[2 * k + ti][s];
-                        n0 = mfma_f64(a0, bv, n0);
-                        n1 = mfma_f64(a1, bv, n1);
-                    }
-                vt[2 * k] = n0;
-                vt[2 * k + 1] = n1;
-            }
-            __syncthreads();
-            // ---- tiles follow the block ring: 1 <- 2 <- 4 <- 6 <- 7 <- 5 <- 3 <- 1
-            {
-                const d4 o1 = vt[1];
-                vt[1] = vt[2];
-                vt[2] = vt[4];
-                vt[4] = vt[6];
-                vt[6] = vt[7];
-                vt[7] = vt[5];
-                vt[5] = vt[3];
-                vt[3] = o1;
+                        for (int v = 0; v < 4; ++v) Ap[pkm(gp(16 * i + g + 4 * v), gq(16 * j + x))] = O[hh][i][v];
+                }
+                __syncthreads();  // Z: A_hat complete for the next round
             }
         }
-    }
-
-    // ---- results: V_hat(16 wv + x, 16 tt + g + 4 v) = vt[tt][v]
-    if (MODE == SUB_PLAIN) {
-        double *vo = a.vout + (size_t)pr * M2 * M2;
+    } else {
+        // ================= V role: Vt = V_hat^T in registers =================
+        // wave 4 + c owns column tiles 2c, 2c + 1 of Vt (rows of V_hat);
+        // vt[tt][j] lane (g, x) component v = Vt(16 tt + g + 4 v, 16 (2c + j) + x).
+        // It applies round t's rotations while the solver role runs round t + 1.
+        const int c = wv - 4;
+        d4 vt[NB][2];
 #pragma unroll
         for (int tt = 0; tt < NB; ++tt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) vo[(size_t)(16 * tt + g + 4 * v) * M2 + 16 * wv + x] = vt[tt][v];
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) vt[tt][j][v] = (16 * tt + g + 4 * v == 16 * (2 * c + j) + x) ? 1.0 : 0.0;
+        // Vt rows of block pair k <- W_k^T (those rows), then the tiles follow
+        // the block ring: 1 <- 2 <- 4 <- 6 <- 7 <- 5 <- 3 <- 1.  Every W read is
+        // one lane base plus a constant (no per-address registers).
+        const double *Wl = Ap + AP + WOFF + g * 33 + x;
+        auto apply = [&]() {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double *Wk = Wl + k * SW;
+                d4 n0[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+                d4 n1[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int rr = 16 * ti + 4 * s4;  // + g (in Wl)
+                        const double a0 = Wk[rr * 33], a1 = Wk[rr * 33 + 16];
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            n0[j] = mfma_f64(a0, vt[2 * k + ti][j][s4], n0[j]);
+                            n1[j] = mfma_f64(a1, vt[2 * k + ti][j][s4], n1[j]);
+                        }
+                    }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    vt[2 * k][j] = n0[j];
+                    vt[2 * k + 1][j] = n1[j];
+                }
+                // keep the next pair's W loads from being hoisted over this
+                // one (Vt already holds half the register file)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const d4 o1 = vt[1][j];
+                vt[1][j] = vt[2][j];
+                vt[2][j] = vt[4][j];
+                vt[4][j] = vt[6][j];
+                vt[6][j] = vt[7][j];
+                vt[7][j] = vt[5][j];
+                vt[5][j] = vt[3][j];
+                vt[3][j] = o1;
+            }
+        };
+        // The same barriers and sweep decisions as the solver role; apply()
+        // appears once (two inlined copies cost the register allocator its Vt).
+        bool pend = false, run = more(0);
+        for (int swp = 0, t = 0;;) {
+            if (pend) apply();  // the previous round's W
+            if (!run) break;
+            __syncthreads();  // X
+            __syncthreads();  // Y
+            __syncthreads();  // tile reads done
+            __syncthreads();  // Z
+            pend = true;
+            if (++t == NB - 1) {
+                t = 0;
+                run = more(++swp);
+            }
+        }
+
+        // ---- results: V_hat(16 (2c + j) + x, 16 tt + g + 4 v) = vt[tt][j][v].
+        //      Each layout is a lane base plus (tt, j, v) constants; one tile row
+        //      at a time keeps the store addresses out of the Vt registers.
+        auto put = [&](auto *base, int stt, int sj, int sv) {
+#pragma unroll
+            for (int tt = 0; tt < NB; ++tt) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) base[tt * stt + j * sj + v * sv] = vt[tt][j][v];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        };
+        const size_t vofs = (size_t)pr * M2 * M2;
+        if (MODE == SUB_PLAIN) {  // V_hat(r, col) at col * M2 + r
+            put(a.vout + vofs + g * M2 + 32 * c + x, 16 * M2, 16, 4 * M2);
+        } else if (a.vout32) {  // vperm32(16 (2c + j) + x, 16 tt + g + 4 v)
+            put(a.vout32 + vofs + (8 * c + (x & 3)) * 512 + (x >> 2) * 16 + g, 64, 2048, 4);
+        } else {  // vperm(16 (2c + j) + x, 16 tt + g + 4 v)
+            put(a.vout + vofs + (8 * c + (x >> 2)) * 512 + (x & 3) * 16 + g, 64, 2048, 4);
+        }
+    }
+
+    // ---- D_hat (A_hat is final after the last barrier of the solver role)
+    if (MODE == SUB_PLAIN) {
         double *dd = a.dout + (size_t)pr * M2 * M2;
         for (int e = tid; e < M2 * M2; e += NT) dd[e] = Ap[pkm(e % M2, e / M2)];
-    } else {
-        if (a.vout32) {
-            float *vo = a.vout32 + (size_t)pr * M2 * M2;
-#pragma unroll
-            for (int tt = 0; tt < NB; ++tt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) vo[vperm32(16 * wv + x, 16 * tt + g + 4 * v, M2)] = (float)vt[tt][v];
-        } else {
-            double *vo = a.vout + (size_t)pr * M2 * M2;
-#pragma unroll
-            for (int tt = 0; tt < NB; ++tt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) vo[vperm(16 * wv + x, 16 * tt + g + 4 * v, M2)] = vt[tt][v];
-        }
-        if (MODE == SUB_EIG) {  // A([I,J],[I,J]) <- D_hat
-            const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
-            const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
-                         oij = ublk(I, J) * (size_t)(B * B);
-            for (int e = tid; e < M2 * M2; e += NT) {
-                const int rr = e % M2, cc = e / M2;
-                store_dhat<M2>(a, oii, ojj, oij, rr, cc, Ap[pkm(rr, cc)]);
-            }
+    } else if (MODE == SUB_EIG) {  // A([I,J],[I,J]) <- D_hat
+        const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
+        const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
+                     oij = ublk(I, J) * (size_t)(B * B);
+        for (int e = tid; e < M2 * M2; e += NT) {
+            const int rr = e % M2, cc = e / M2;
+            store_dhat<M2>(a, oii, ojj, oij, rr, cc, Ap[pkm(rr, cc)]);
         }
     }
 }
@@ -466,7 +545,11 @@ static void launch_sub_m(const SubArgs &a, hipStream_t s) {
     switch (a.m2) {
         case 32: launch_sub_t<32, MODE>(a, s); break;
         case 64: launch_sub_t<64, MODE>(a, s); break;
+#ifdef JX_K1_ONE_LEVEL
+        case 128: launch_sub_t<128, MODE>(a, s); break;
+#else
         case 128: launch_sub2_t<MODE>(a, s); break;
+#endif
         default: set_error("subproblem order must be 32, 64 or 128"); throw HipFail{hipErrorInvalidValue};
     }
 }
