@@ -38,34 +38,34 @@ namespace jx {
 // ---------------------------------------------------------------------------
 
 // Ring of positions 1 .. m2-1 in the order their content moves.
-__device__ __forceinline__ int ring_at(int i, int m2) {
+__host__ __device__ constexpr __forceinline__ int ring_at(int i, int m2) {
     if (i == 0) return 1;
     if (i < m2 / 2) return 2 * i;
     return 2 * m2 - 1 - 2 * i;
 }
-__device__ __forceinline__ int ring_index(int x, int m2) {
+__host__ __device__ constexpr __forceinline__ int ring_index(int x, int m2) {
     if (x == 1) return 0;
     if ((x & 1) == 0) return x >> 1;
     return (2 * m2 - 1 - x) >> 1;
 }
 // LDS slot of index x (its place along the ring; 0 stays 0).
-__device__ __forceinline__ int slot_of(int x, int m2) { return x == 0 ? 0 : 1 + ring_index(x, m2); }
+__host__ __device__ constexpr __forceinline__ int slot_of(int x, int m2) { return x == 0 ? 0 : 1 + ring_index(x, m2); }
 // Slots of the members of pair k in round t of a sweep (t < m2 - 1):
 // position 2k holds slot 1 + (k + t) mod (m2-1) (position 0: slot 0),
 // position 2k+1 holds slot 1 + (t - k) mod (m2-1).
-__device__ __forceinline__ int slot_p(int k, int t, int m2) {
+__host__ __device__ constexpr __forceinline__ int slot_p(int k, int t, int m2) {
     if (k == 0) return 0;
     int i = k + t;
     if (i >= m2 - 1) i -= m2 - 1;
     return 1 + i;
 }
-__device__ __forceinline__ int slot_q(int k, int t, int m2) {
+__host__ __device__ constexpr __forceinline__ int slot_q(int k, int t, int m2) {
     int i = (k == 0) ? t : t - k;
     if (i < 0) i += m2 - 1;
     return 1 + i;
 }
 // Index found at position x in round t.
-__device__ __forceinline__ int index_at(int x, int t, int m2) {
+__host__ __device__ constexpr __forceinline__ int index_at(int x, int t, int m2) {
     if (x == 0) return 0;
     int i = ring_index(x, m2) + t;
     if (i >= m2 - 1) i -= m2 - 1;
@@ -179,6 +179,88 @@ __device__ __forceinline__ double lane_prev(double v) {
     else return __shfl_up(v, 1, G);
 }
 
+// Item it of a sweep (a pair-block between pairs k1 and k2, or padding when
+// it >= H (H - 1) / 2): pairs packed k1 | k2 << 8, the four slots in round 0
+// and the code of its stale and next-round pivot roles (see scalar_sweeps).
+__host__ __device__ constexpr void sweep_item(int it, int M2, int &ikk, int *isl, int &icode) {
+    const int H = M2 / 2, NOFF = H * (H - 1) / 2;
+    int k1 = 0, d = 1;
+    if (it < H * (H / 2 - 1)) { d = it / H + 1; k1 = it - (d - 1) * H; }
+    else { d = H / 2; k1 = it - H * (H / 2 - 1); }
+    int k2 = k1 + d;
+    if (k2 >= H) k2 -= H;
+    const bool valid = it < NOFF;
+    if (!valid) { k1 = 0; k2 = 1; }
+    ikk = k1 | (k2 << 8);
+    isl[0] = slot_p(k1, 0, M2);
+    isl[1] = slot_q(k1, 0, M2);
+    isl[2] = slot_p(k2, 0, M2);
+    isl[3] = slot_q(k2, 0, M2);
+    const int lo = k1 < k2 ? k1 : k2, hi = k1 < k2 ? k2 : k1;
+    const bool fw = (k1 == lo);
+    // the previous round's pivot of pair k lies at (p of k-1, q of k+1) for
+    // 2 <= k <= H-2; pair 0: (p0, q1); pair 1: (q0, q2); pair H-1:
+    // (p(H-2), p(H-1))
+    int st = -1;
+    if (hi - lo == 2 && lo >= 1) st = fw ? 1 : 2;
+    else if (lo == 0 && hi == 2) st = 3;
+    else if (lo == 0 && hi == 1) st = fw ? 1 : 2;
+    else if (lo == H - 2 && hi == H - 1) st = 0;
+    // the next round's pivot of pair lo + 1 is (q_lo, p_hi); of pair 0,
+    // (p0, p1); of pair H-1, (q(H-2), q(H-1))
+    int kn = -1, pv = 0, mp = 0, mq = 0;
+    if (hi - lo == 2) {
+        kn = lo + 1; pv = fw ? 2 : 1; mp = fw ? 2 : 0; mq = fw ? 1 : 3;
+    } else if (lo == 0 && hi == 1) {
+        kn = 0; pv = 0; mp = fw ? 0 : 2; mq = fw ? 2 : 0;
+    } else if (lo == H - 2 && hi == H - 1) {
+        kn = H - 1; pv = 3; mp = fw ? 3 : 1; mq = fw ? 1 : 3;
+    }
+    if (!valid) { st = -1; kn = -1; }
+    icode = (st + 1) | ((kn + 1) << 3) | (pv << 10) | (mp << 12) | (mq << 14);
+}
+
+// Next slot along the ring (slot 0 stays).
+__host__ __device__ constexpr __forceinline__ int slot_next(int sl, int R) { return sl == 0 ? 0 : (sl == R ? 1 : sl + 1); }
+
+// LDS addresses of a whole sweep, per round and thread, for one wave per
+// problem: the four entries of each item (upper-triangle index min * m2 + max
+// of its slots) and the producer's two diagonal entries, as 16-bit halves.
+// Computed at compile time; a round then reads its addresses with one vector
+// load (prefetched a round ahead) instead of advancing slots and recomputing
+// addresses in the VALU.
+template <int M2, int NT>
+struct SweepTable {
+    static constexpr int H = M2 / 2, R = M2 - 1, NOFF = H * (H - 1) / 2, MAXI = (NOFF + NT - 1) / NT;
+    static_assert(MAXI == 2, "layout: two items per thread");
+    unsigned int item[R][NT][4];  // item ii entry m: half (2 ii + m / 2), bits 16 (m & 1)
+    unsigned int prod[R][NT];     // diagonal of the next-round pair's p and q member
+};
+template <int M2, int NT>
+constexpr SweepTable<M2, NT> make_sweep_table() {
+    using T = SweepTable<M2, NT>;
+    T tb{};
+    for (int tid = 0; tid < NT; ++tid) {
+        int ikk[T::MAXI] = {}, isl[T::MAXI][4] = {}, icode[T::MAXI] = {};
+        for (int ii = 0; ii < T::MAXI; ++ii) sweep_item(tid + ii * NT, M2, ikk[ii], isl[ii], icode[ii]);
+        const int mp = (icode[0] >> 12) & 3, mq = (icode[0] >> 14) & 3;
+        for (int t = 0; t < T::R; ++t) {
+            for (int ii = 0; ii < T::MAXI; ++ii) {
+                const int a = isl[ii][0], b = isl[ii][1], c = isl[ii][2], d = isl[ii][3];
+                const int e[4] = {(a < c ? a : c) * M2 + (a < c ? c : a), (a < d ? a : d) * M2 + (a < d ? d : a),
+                                  (b < c ? b : c) * M2 + (b < c ? c : b), (b < d ? b : d) * M2 + (b < d ? d : b)};
+                tb.item[t][tid][2 * ii] = (unsigned)e[0] | ((unsigned)e[1] << 16);
+                tb.item[t][tid][2 * ii + 1] = (unsigned)e[2] | ((unsigned)e[3] << 16);
+            }
+            const int spn = isl[0][mp], sqn = isl[0][mq];
+            tb.prod[t][tid] = (unsigned)(spn * (M2 + 1)) | ((unsigned)(sqn * (M2 + 1)) << 16);
+            for (int ii = 0; ii < T::MAXI; ++ii)
+                for (int m = 0; m < 4; ++m) isl[ii][m] = slot_next(isl[ii][m], T::R);
+        }
+    }
+    return tb;
+}
+
 // ---------------------------------------------------------------------------
 // Round-robin scalar Jacobi on an m2 x m2 matrix held in LDS (slot order)
 // ---------------------------------------------------------------------------
@@ -188,9 +270,9 @@ __device__ __forceinline__ double lane_prev(double v) {
 // off <= eps sqrt(fro2).  V receives this thread's part of the accumulated
 // rotation (row r = tid / G, columns P g .. P g + P - 1, g = tid mod G,
 // G = m2 / P); position space equals index space at the end of a sweep.
-template <int M2, int NT, bool WAVE>
+template <int M2, int NT, bool WAVE, bool TBL = false>
 __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, int nsw, bool conv, double fro2,
-                              double *V) {
+                              double *V, const SweepTable<M2, NT> *tbl = nullptr) {
     constexpr int H = M2 / 2, P = M2 * M2 / NT, G = M2 / P, LD = M2, R = M2 - 1;
     constexpr int NOFF = H * (H - 1) / 2;  // pair-blocks between different pairs
     static_assert(P >= 4 && P % 2 == 0 && M2 % P == 0, "whole position pairs per thread");
@@ -215,50 +297,25 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
     static_assert(2 * H <= NT, "pivot pair-blocks must be first items");
     int ikk[MAXI], isl[MAXI][4], icode[MAXI];
 #pragma unroll
-    for (int ii = 0; ii < MAXI; ++ii) {
-        const int it = tid + ii * NT;
-        int k1 = 0, d = 1;
-        if (it < H * (H / 2 - 1)) { d = it / H + 1; k1 = it - (d - 1) * H; }
-        else { d = H / 2; k1 = it - H * (H / 2 - 1); }
-        int k2 = k1 + d;
-        if (k2 >= H) k2 -= H;
-        const bool valid = it < NOFF;
-        if (!valid) { k1 = 0; k2 = 1; }
-        ikk[ii] = k1 | (k2 << 8);
-        isl[ii][0] = slot_p(k1, 0, M2);
-        isl[ii][1] = slot_q(k1, 0, M2);
-        isl[ii][2] = slot_p(k2, 0, M2);
-        isl[ii][3] = slot_q(k2, 0, M2);
-        const int lo = min(k1, k2), hi = max(k1, k2);
-        const bool fw = (k1 == lo);
-        // the previous round's pivot of pair k lies at (p of k-1, q of k+1) for
-        // 2 <= k <= H-2; pair 0: (p0, q1); pair 1: (q0, q2); pair H-1:
-        // (p(H-2), p(H-1))
-        int st = -1;
-        if (hi - lo == 2 && lo >= 1) st = fw ? 1 : 2;
-        else if (lo == 0 && hi == 2) st = 3;
-        else if (lo == 0 && hi == 1) st = fw ? 1 : 2;
-        else if (lo == H - 2 && hi == H - 1) st = 0;
-        // the next round's pivot of pair lo + 1 is (q_lo, p_hi); of pair 0,
-        // (p0, p1); of pair H-1, (q(H-2), q(H-1))
-        int kn = -1, pv = 0, mp = 0, mq = 0;
-        if (hi - lo == 2) {
-            kn = lo + 1; pv = fw ? 2 : 1; mp = fw ? 2 : 0; mq = fw ? 1 : 3;
-        } else if (lo == 0 && hi == 1) {
-            kn = 0; pv = 0; mp = fw ? 0 : 2; mq = fw ? 2 : 0;
-        } else if (lo == H - 2 && hi == H - 1) {
-            kn = H - 1; pv = 3; mp = fw ? 3 : 1; mq = fw ? 1 : 3;
-        }
-        if (!valid) { st = -1; kn = -1; }
-        icode[ii] = (st + 1) | ((kn + 1) << 3) | (pv << 10) | (mp << 12) | (mq << 14);
-    }
+    for (int ii = 0; ii < MAXI; ++ii) sweep_item(tid + ii * NT, M2, ikk[ii], isl[ii], icode[ii]);
 
     // The producer items (distance <= 2, the first item of threads < 2H) fill
     // whole waves: a wave-uniform branch keeps the parameter work out of the others.
-    const bool prod_wave = __builtin_amdgcn_readfirstlane(tid) < 2 * H;
+    const bool prod_wave = WAVE || __builtin_amdgcn_readfirstlane(tid) < 2 * H;
+    // One wave per problem: the round is kept free of branches (lanes without
+    // a store target write a never-read lower-triangle entry of their own), so
+    // the scheduler can fill the parameter chain's latency with the rest of
+    // the round.
+    const int dum = (M2 - 1 - (tid & 63) / H) * LD + (tid & 63) % H;
     const double eps = 2.220446049250313e-16;
     const int cap = conv ? 30 : nsw;
     int gr = 0;  // rounds done (parameter buffer parity)
+    uint4 cur = {0, 0, 0, 0};  // table: this round's item addresses and producer diagonal
+    unsigned int curp = 0;
+    if constexpr (TBL) {
+        cur = *reinterpret_cast<const uint4 *>(tbl->item[0][tid]);
+        curp = tbl->prod[0][tid];
+    }
     for (int swp = 0; swp < cap; ++swp) {
         if (conv && swp > 0) {
             double o = 0.0;
@@ -278,18 +335,37 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
             //      a store would cost one LDS round trip each
             double cs[MAXI][4], xv[MAXI][4];
             int ia[MAXI][4];
+            int dpa = 0, dqa = 0;  // producer's diagonal entries
+            if constexpr (TBL) {   // this round's addresses; fetch the next round's
+                const uint4 ta = cur;
+                dpa = (int)(curp & 0xffff);
+                dqa = (int)(curp >> 16);
+                const int tn = t + 1 < R ? t + 1 : 0;
+                cur = *reinterpret_cast<const uint4 *>(tbl->item[tn][tid]);
+                curp = tbl->prod[tn][tid];
+                const unsigned int w[4] = {ta.x, ta.y, ta.z, ta.w};
+#pragma unroll
+                for (int ii = 0; ii < MAXI; ++ii)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const unsigned int h = w[2 * ii + m / 2];
+                        ia[ii][m] = (int)((m & 1) ? (h >> 16) : (h & 0xffff));
+                    }
+            }
 #pragma unroll
             for (int ii = 0; ii < MAXI; ++ii) {
                 const int k1 = ikk[ii] & 255, k2 = ikk[ii] >> 8;
-                const int sp1 = isl[ii][0], sq1 = isl[ii][1], sp2 = isl[ii][2], sq2 = isl[ii][3];
                 cs[ii][0] = pc[k1];
                 cs[ii][1] = pc[H + k1];
                 cs[ii][2] = pc[k2];
                 cs[ii][3] = pc[H + k2];
-                ia[ii][0] = min(sp1, sp2) * LD + max(sp1, sp2);
-                ia[ii][1] = min(sp1, sq2) * LD + max(sp1, sq2);
-                ia[ii][2] = min(sq1, sp2) * LD + max(sq1, sp2);
-                ia[ii][3] = min(sq1, sq2) * LD + max(sq1, sq2);
+                if constexpr (!TBL) {
+                    const int sp1 = isl[ii][0], sq1 = isl[ii][1], sp2 = isl[ii][2], sq2 = isl[ii][3];
+                    ia[ii][0] = min(sp1, sp2) * LD + max(sp1, sp2);
+                    ia[ii][1] = min(sp1, sq2) * LD + max(sp1, sq2);
+                    ia[ii][2] = min(sq1, sp2) * LD + max(sq1, sp2);
+                    ia[ii][3] = min(sq1, sq2) * LD + max(sq1, sq2);
+                }
 #pragma unroll
                 for (int m = 0; m < 4; ++m) xv[ii][m] = As[ia[ii][m]];
             }
@@ -298,16 +374,17 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
             const int code = icode[0];
             const int kn = ((code >> 3) & 127) - 1;
             const int pv = (code >> 10) & 3, mp = (code >> 12) & 3, mq = (code >> 14) & 3;
-            int spn = 0, sqn = 0;
             double dpo = 0.0, dqo = 0.0, tp = 0.0, tq = 0.0;
             if (prod_wave) {
                 const int k1 = ikk[0] & 255, k2 = ikk[0] >> 8;
-                const int sp1 = isl[0][0], sq1 = isl[0][1], sp2 = isl[0][2], sq2 = isl[0][3];
-                // two-level selects on single bits stay selects
-                spn = (mp & 2) ? ((mp & 1) ? sq2 : sp2) : ((mp & 1) ? sq1 : sp1);
-                sqn = (mq & 2) ? ((mq & 1) ? sq2 : sp2) : ((mq & 1) ? sq1 : sp1);
-                dpo = As[spn * (LD + 1)];
-                dqo = As[sqn * (LD + 1)];
+                if constexpr (!TBL) {
+                    const int sp1 = isl[0][0], sq1 = isl[0][1], sp2 = isl[0][2], sq2 = isl[0][3];
+                    // two-level selects on single bits stay selects
+                    dpa = ((mp & 2) ? ((mp & 1) ? sq2 : sp2) : ((mp & 1) ? sq1 : sp1)) * (LD + 1);
+                    dqa = ((mq & 2) ? ((mq & 1) ? sq2 : sp2) : ((mq & 1) ? sq1 : sp1)) * (LD + 1);
+                }
+                dpo = As[dpa];
+                dqo = As[dqa];
                 tp = pc[2 * H + (mp < 2 ? k1 : k2)];
                 tq = pc[2 * H + (mq < 2 ? k1 : k2)];
                 // the previous round's pivot lies in this block: read as zero
@@ -332,7 +409,13 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                 const double y12 = c1 * x12 - s1 * x22, y22 = s1 * x12 + c1 * x22;
                 const double z11 = c2 * y11 - s2 * y12, z12 = s2 * y11 + c2 * y12;
                 const double z21 = c2 * y21 - s2 * y22, z22 = s2 * y21 + c2 * y22;
-                if (ii * NT + tid < NOFF) {
+                if constexpr (WAVE) {
+                    const bool ok = ii * NT + tid < NOFF;
+                    As[ok ? ia[ii][0] : dum] = z11;
+                    As[ok ? ia[ii][1] : dum] = z12;
+                    As[ok ? ia[ii][2] : dum] = z21;
+                    As[ok ? ia[ii][3] : dum] = z22;
+                } else if (ii * NT + tid < NOFF) {
                     As[ia[ii][0]] = z11;
                     As[ia[ii][1]] = z12;
                     As[ia[ii][2]] = z21;
@@ -350,21 +433,28 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                 const double dq = dqo + ((mq & 1) ? tq : -tq);
                 double cn, sn, tn;
                 rot_cst(dp, dq, piv, cn, sn, tn);
-                if (kn >= 0) {
-                    As[spn * (LD + 1)] = dp;
-                    As[sqn * (LD + 1)] = dq;
+                if constexpr (WAVE) {
+                    const bool ok = kn >= 0;
+                    As[ok ? dpa : dum] = dp;
+                    As[ok ? dqa : dum] = dq;
+                    double *const pd = ok ? pn + kn : As + dum;
+                    pd[0] = cn;
+                    pd[ok ? H : 0] = sn;
+                    pd[ok ? 2 * H : 0] = tn * piv;
+                } else if (kn >= 0) {
+                    As[dpa] = dp;
+                    As[dqa] = dq;
                     pn[kn] = cn;
                     pn[H + kn] = sn;
                     pn[2 * H + kn] = tn * piv;
                 }
             }
+            if constexpr (!TBL) {
 #pragma unroll
-            for (int ii = 0; ii < MAXI; ++ii)
+                for (int ii = 0; ii < MAXI; ++ii)
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int sl = isl[ii][m];
-                    isl[ii][m] = sl == 0 ? 0 : (sl == R ? 1 : sl + 1);
-                }
+                    for (int m = 0; m < 4; ++m) isl[ii][m] = slot_next(isl[ii][m], R);
+            }
 
             // ---- V <- V J on this thread's P/2 position pairs, then one ring step
 #pragma unroll

@@ -220,6 +220,9 @@ __device__ __forceinline__ int pk(int i, int j) {  // i <= j
 __device__ __forceinline__ int pkm(int i, int j) { return i <= j ? pk(i, j) : pk(j, i); }
 }  // namespace tl
 
+// Addresses of the 32 x 32 pair problems' sweeps (compile-time table).
+__device__ const SweepTable<32, 64> kSweep32 = make_sweep_table<32, 64>();
+
 template <int MODE>
 __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
     using namespace tl;
@@ -324,7 +327,7 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
                 }
                 wave_lds_sync();
                 double Vl[16];
-                scalar_sweeps<32, 64, true>(S, prm, nullptr, lane, 1, false, 0.0, Vl);
+                scalar_sweeps<32, 64, true, true>(S, prm, nullptr, lane, 1, false, 0.0, Vl, &kSweep32);
                 __syncthreads();  // X: the V role has read the previous W
                 // W(r, 16 h + xx) = Vl[xx], r = lane / 2, h = lane mod 2; D back into A_hat
                 {
