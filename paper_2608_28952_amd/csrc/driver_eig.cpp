@@ -256,8 +256,10 @@ struct EigState {
                 }
                 {
                     ProfScope ps(PROF_UPDATE_Q, qs, (double)p.npad, 0.0, slot, p.H, m2);
-                    if (f32) launch_update_q32(p.b, p.H, pr, Q32, p.npad, p.npad, Vbuf32(r), Fbuf(r), qs);
-                    else launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs);
+                    // beside the next round's subproblems: leave them their CUs
+                    const int reserve = sq ? p.H : 0;
+                    if (f32) launch_update_q32(p.b, p.H, pr, Q32, p.npad, p.npad, Vbuf32(r), Fbuf(r), qs, reserve);
+                    else launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs, reserve);
                 }
                 if (sq) {
                     JX_HIP(hipEventRecord(ev_q[buf], sq));

@@ -131,6 +131,7 @@ struct SubArgs {
     int *rot_count;         // optional: +1 per pair that is rotated (not skipped)
     float *ablk32;          // SUB_EIG with FP32 storage of A (instead of ablk)
     float *vout32;          // V_hat written in FP32, vperm32 order (instead of vout)
+    int spin_limit;         // bound of the in-kernel hand-off waits (0: the default)
 };
 void launch_subproblem(const SubArgs &a, hipStream_t s);
 
@@ -184,14 +185,15 @@ void launch_scale_scatter(int m, int n, const double *G, int ldg, const double *
                           double *U, int ldu, hipStream_t s);
 
 // One-sided update Q(:, [I,J]) <- Q(:, [I,J]) V_p for every pair p and every
-// 128-row chunk of Q (n_rows multiple of 128).
+// 128-row chunk of Q (n_rows multiple of 128).  reserve > 0: run on at most
+// (CUs - reserve) CUs, leaving `reserve` CUs free for a kernel running beside it.
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
-                     const double *vhat, const int *flags, hipStream_t s);
+                     const double *vhat, const int *flags, hipStream_t s, int reserve = 0);
 // FP32 versions (FP32 storage, FP32 MFMA with FP32 accumulation, V_hat in vperm32 order).
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
                        const int *tiles, int ntiles, hipStream_t s);
 void launch_update_q32(int b, int npairs, const int *pairs, float *Q, int ldq, int n_rows, const float *vhat,
-                       const int *flags, hipStream_t s);
+                       const int *flags, hipStream_t s, int reserve = 0);
 
 // Layout conversion and reductions.
 void launch_pack_sym(int n, int npad, int b, const double *A, int lda, char uplo, double *ablk,

@@ -261,6 +261,39 @@ constexpr SweepTable<M2, NT> make_sweep_table() {
     return tb;
 }
 
+// Hand-off of a sweep's rotations to another wave of the workgroup, which
+// accumulates V while the sweep runs on.  The (c, s) of global round n sit in
+// ring slot n mod VR_DEPTH; sdone counts the rounds whose parameters are in
+// the ring, vdone the rounds the follower has applied.  Both counters only
+// grow.  Waits are bounded (VR_SPIN polls, thousands of times the longest
+// legitimate wait): a wait that runs out gives up rather than hang and sets
+// *fail, and the kernel then poisons its output with NaN (reported as a
+// non-finite iterate) instead of returning wrong numbers.
+constexpr int VR_DEPTH = 8;
+constexpr int VR_SPIN = 1 << 16;
+struct VRing {
+    double *ring;  // VR_DEPTH x (c[H], s[H])
+    int *sdone;
+    int *vdone;
+    int base;      // global round number of this sweep's round 0
+    int *fail;     // set when a wait runs out
+    int spin;      // polls per wait
+};
+__device__ __forceinline__ int lds_load_acquire(int *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store_release(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Wait until *p >= v (at most `spin` polls; *fail = 1 when they run out).
+__device__ __forceinline__ void lds_wait_geq(int *p, int v, int *fail, int spin) {
+    for (int it = 0; it < spin; ++it) {
+        if (lds_load_acquire(p) >= v) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_store_release(fail, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Round-robin scalar Jacobi on an m2 x m2 matrix held in LDS (slot order)
 // ---------------------------------------------------------------------------
@@ -270,22 +303,34 @@ constexpr SweepTable<M2, NT> make_sweep_table() {
 // off <= eps sqrt(fro2).  V receives this thread's part of the accumulated
 // rotation (row r = tid / G, columns P g .. P g + P - 1, g = tid mod G,
 // G = m2 / P); position space equals index space at the end of a sweep.
-template <int M2, int NT, bool WAVE, bool TBL = false>
+template <int M2, int NT, bool WAVE, bool TBL = false, bool VOUT = false>
 __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, int nsw, bool conv, double fro2,
-                              double *V, const SweepTable<M2, NT> *tbl = nullptr) {
+                              double *V, const SweepTable<M2, NT> *tbl = nullptr, VRing vr = VRing{}) {
+    // VOUT: V is not accumulated here; every round's (c, s) goes to the ring
+    // for a follower wave (follow_sweep) instead.
+    static_assert(!VOUT || (WAVE && TBL), "hand-off: one wave per problem, table addressing");
     constexpr int H = M2 / 2, P = M2 * M2 / NT, G = M2 / P, LD = M2, R = M2 - 1;
     constexpr int NOFF = H * (H - 1) / 2;  // pair-blocks between different pairs
     static_assert(P >= 4 && P % 2 == 0 && M2 % P == 0, "whole position pairs per thread");
     const int r = tid / G, g = tid - (tid / G) * G;
+    if constexpr (!VOUT) {
 #pragma unroll
-    for (int x = 0; x < P; ++x) V[x] = (r == P * g + x) ? 1.0 : 0.0;
+        for (int x = 0; x < P; ++x) V[x] = (r == P * g + x) ? 1.0 : 0.0;
+    }
 
     // parameters of the first round
     if (tid < H) {
         const int up = slot_p(tid, 0, M2), uq = slot_q(tid, 0, M2);
         rot_params(As[up * (LD + 1)], As[uq * (LD + 1)], As[min(up, uq) * LD + max(up, uq)], prm0, tid, H);
+        if constexpr (VOUT) {
+            double *rb = vr.ring + (vr.base & (VR_DEPTH - 1)) * 2 * H;
+            lds_wait_geq(vr.vdone, vr.base + 1 - VR_DEPTH, vr.fail, vr.spin);
+            rb[tid] = prm0[tid];
+            rb[H + tid] = prm0[H + tid];
+        }
     }
     group_sync<WAVE>();
+    if constexpr (VOUT) lds_store_release(vr.sdone, vr.base + 1);
 
     // This thread's pair-blocks (fixed for all rounds); their slots advance by
     // one per round along 1 .. m2-1 (slot 0 stays), kept in registers.  Entry
@@ -395,8 +440,8 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
             double vc[P / 2], vs[P / 2];  // this thread's position pairs
 #pragma unroll
             for (int j = 0; j < P / 2; ++j) {
-                vc[j] = pc[(P / 2) * g + j];
-                vs[j] = pc[H + (P / 2) * g + j];
+                vc[j] = VOUT ? 0.0 : pc[(P / 2) * g + j];
+                vs[j] = VOUT ? 0.0 : pc[H + (P / 2) * g + j];
             }
 
             // ---- rotate the pair-blocks: left rows p1, q1; right columns p2, q2
@@ -441,6 +486,13 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                     pd[0] = cn;
                     pd[ok ? H : 0] = sn;
                     pd[ok ? 2 * H : 0] = tn * piv;
+                    if constexpr (VOUT) {  // next round's slot, once the follower is done with it
+                        const int nr = vr.base + t + 1;
+                        double *const rd = ok ? vr.ring + (nr & (VR_DEPTH - 1)) * 2 * H + kn : As + dum;
+                        lds_wait_geq(vr.vdone, nr + 1 - VR_DEPTH, vr.fail, vr.spin);
+                        rd[0] = cn;
+                        rd[ok ? H : 0] = sn;
+                    }
                 } else if (kn >= 0) {
                     As[dpa] = dp;
                     As[dqa] = dq;
@@ -457,13 +509,13 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
             }
 
             // ---- V <- V J on this thread's P/2 position pairs, then one ring step
+            if constexpr (!VOUT) {
 #pragma unroll
-            for (int j = 0; j < P / 2; ++j) {
-                const double e = V[2 * j], o = V[2 * j + 1];
-                V[2 * j] = vc[j] * e - vs[j] * o;
-                V[2 * j + 1] = vs[j] * e + vc[j] * o;
-            }
-            {
+                for (int j = 0; j < P / 2; ++j) {
+                    const double e = V[2 * j], o = V[2 * j + 1];
+                    V[2 * j] = vc[j] * e - vs[j] * o;
+                    V[2 * j + 1] = vs[j] * e + vc[j] * o;
+                }
                 const double from_right = lane_next<G>(V[0]);
                 const double from_left = lane_prev<G>(V[P - 1]);
                 const double e0 = V[0], e1 = V[2], olast = V[P - 1];
@@ -476,6 +528,9 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                 if (g == 0) V[0] = e0;
             }
             group_sync<WAVE>();
+            // rounds <= t + 1 are in the ring; the last round's "next" parameters
+            // are not (the next sweep writes its round 0 itself)
+            if constexpr (VOUT) lds_store_release(vr.sdone, vr.base + min(t + 2, R));
         }
         // end of sweep: clear the last round's pivots (the diagonal is current)
         if (tid < H) {
@@ -483,6 +538,47 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
             As[min(up, uq) * LD + max(up, uq)] = 0.0;
         }
         group_sync<WAVE>();
+    }
+}
+
+// The follower of a sweep run with VOUT: applies each round's rotations to
+// V (same layout and ring steps as scalar_sweeps with one wave, P = m2^2 / 64
+// positions of one row per thread) as soon as the ring holds them.  V starts
+// as the identity; after the m2 - 1 rounds positions equal indices.
+template <int M2>
+__device__ void follow_sweep(const VRing &vr, int lane, double *V) {
+    constexpr int NT = 64, H = M2 / 2, P = M2 * M2 / NT, G = M2 / P, R = M2 - 1;
+    const int r = lane / G, g = lane - (lane / G) * G;
+#pragma unroll
+    for (int x = 0; x < P; ++x) V[x] = (r == P * g + x) ? 1.0 : 0.0;
+    for (int t = 0; t < R; ++t) {
+        const int n = vr.base + t;
+        lds_wait_geq(vr.sdone, n + 1, vr.fail, vr.spin);
+        const double *rb = vr.ring + (n & (VR_DEPTH - 1)) * 2 * H + (P / 2) * g;
+        double vc[P / 2], vs[P / 2];
+#pragma unroll
+        for (int j = 0; j < P / 2; ++j) {
+            vc[j] = rb[j];
+            vs[j] = rb[H + j];
+        }
+#pragma unroll
+        for (int j = 0; j < P / 2; ++j) {
+            const double e = V[2 * j], o = V[2 * j + 1];
+            V[2 * j] = vc[j] * e - vs[j] * o;
+            V[2 * j + 1] = vs[j] * e + vc[j] * o;
+        }
+        // this round's slot is read (the values are in registers): free it
+        lds_store_release(vr.vdone, n + 1);
+        const double from_right = lane_next<G>(V[0]);
+        const double from_left = lane_prev<G>(V[P - 1]);
+        const double e0 = V[0], e1 = V[2], olast = V[P - 1];
+#pragma unroll
+        for (int j = 0; j < P / 2 - 1; ++j) V[2 * j] = V[2 * j + 2];
+        V[P - 2] = (g < G - 1) ? from_right : olast;
+#pragma unroll
+        for (int j = P / 2 - 1; j > 0; --j) V[2 * j + 1] = V[2 * j - 1];
+        V[1] = (g > 0) ? from_left : e1;
+        if (g == 0) V[0] = e0;
     }
 }
 

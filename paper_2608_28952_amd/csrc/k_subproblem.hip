@@ -21,6 +21,8 @@
 // jx_sweep.hpp.
 #include "jx_common.hpp"
 #include "jx_sweep.hpp"
+#include <algorithm>
+#include <cstdlib>
 
 namespace jx {
 
@@ -213,7 +215,8 @@ constexpr int M2 = 128, NB = 8, BS = 16, NT = 512;
 constexpr int AP = M2 * (M2 + 1) / 2;           // packed upper triangle
 constexpr int SW = 32 * 32 + 8 * 16 + 32 * 33;  // per pair problem: slots, parameters, W
 constexpr int WOFF = 32 * 32 + 8 * 16;          // offset of W in a solver region
-constexpr size_t LDS_BYTES = sizeof(double) * ((size_t)AP + 4 * SW + 16);
+constexpr int RING = VR_DEPTH * 32;                // per pair problem: rotations handed to the V role
+constexpr size_t LDS_BYTES = sizeof(double) * ((size_t)AP + 4 * SW + 16 + 4 * RING) + 9 * sizeof(int);
 __device__ __forceinline__ int pk(int i, int j) {  // i <= j
     return i * (2 * M2 - 1 - i) / 2 + j;
 }
@@ -230,9 +233,13 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
     extern __shared__ double smem[];
     double *Ap = smem;
     double *red = Ap + AP + 4 * SW;
+    double *rings = red + 16;                                // 4 x RING
+    int *ctr = reinterpret_cast<int *>(rings + 4 * RING);  // sdone[4], vdone[4], fail
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int pr = blockIdx.x;
+    if (tid < 9) ctr[tid] = 0;  // ordered before use by the prologue's barriers
+    const int spin = a.spin_limit > 0 ? a.spin_limit : VR_SPIN;
 
     if (MODE != SUB_PLAIN && a.force_skip && a.force_skip[pr]) {  // placeholder pair
         if (tid == 0 && a.flags) a.flags[pr] = 1;
@@ -291,8 +298,8 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
         const int k = wv;
         double *S = Ap + AP + k * SW;  // slots
         double *prm = S + 32 * 32;     // parameters
-        double *W = S + WOFF;          // rotation, row-major stride 33
         const double *Wl = Ap + AP + WOFF + g * 33 + x;  // W reads: lane base + constant
+        int rnd = 0;  // global round number of the next sweep's round 0
         // This lane's entries of the 528-entry upper triangle (diagonal
         // included) of a 32 x 32 pair problem: the triangle is read as a 16 x 33
         // rectangle (rows a and 31 - a together hold 33 entries); entry i is
@@ -326,15 +333,10 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
                         if (lane + 64 * i < 528) S[si[i]] = v[i];
                 }
                 wave_lds_sync();
-                double Vl[16];
-                scalar_sweeps<32, 64, true, true>(S, prm, nullptr, lane, 1, false, 0.0, Vl, &kSweep32);
-                __syncthreads();  // X: the V role has read the previous W
-                // W(r, 16 h + xx) = Vl[xx], r = lane / 2, h = lane mod 2; D back into A_hat
-                {
-                    const int r = lane >> 1, h = lane & 1;
-#pragma unroll
-                    for (int xx = 0; xx < 16; ++xx) W[r * 33 + 16 * h + xx] = Vl[xx];
-                }
+                const VRing vr{rings + k * RING, ctr + k, ctr + 4 + k, rnd, ctr + 8, spin};
+                scalar_sweeps<32, 64, true, true, true>(S, prm, nullptr, lane, 1, false, 0.0, nullptr, &kSweep32, vr);
+                rnd += 31;
+                __syncthreads();  // X: W of this round written by the V role; D back into A_hat
                 {
                     double v[NG];
 #pragma unroll
@@ -462,9 +464,23 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
         // The same barriers and sweep decisions as the solver role; apply()
         // appears once (two inlined copies cost the register allocator its Vt).
         bool pend = false, run = more(0);
+        int rnd = 0;
         for (int swp = 0, t = 0;;) {
             if (pend) apply();  // the previous round's W
             if (!run) break;
+            {
+                // this round's rotations of pair problem c, as the solver role
+                // produces them; then W_c(r, 16 h + xx) = Vl[xx], r = lane / 2,
+                // h = lane mod 2
+                const VRing vr{rings + c * RING, ctr + c, ctr + 4 + c, rnd, ctr + 8, spin};
+                double Vl[16];
+                follow_sweep<32>(vr, lane, Vl);
+                rnd += 31;
+                double *W = Ap + AP + c * SW + WOFF;
+                const int r = lane >> 1, h = lane & 1;
+#pragma unroll
+                for (int xx = 0; xx < 16; ++xx) W[r * 33 + 16 * h + xx] = Vl[xx];
+            }
             __syncthreads();  // X
             __syncthreads();  // Y
             __syncthreads();  // tile reads done
@@ -479,13 +495,15 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
         // ---- results: V_hat(16 (2c + j) + x, 16 tt + g + 4 v) = vt[tt][j][v].
         //      Each layout is a lane base plus (tt, j, v) constants; one tile row
         //      at a time keeps the store addresses out of the Vt registers.
+        // (NaN if a hand-off wait ran out; every wait is behind the last barrier)
+        const double bad = ctr[8] ? __builtin_nan("") : 0.0;
         auto put = [&](auto *base, int stt, int sj, int sv) {
 #pragma unroll
             for (int tt = 0; tt < NB; ++tt) {
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) base[tt * stt + j * sj + v * sv] = vt[tt][j][v];
+                    for (int v = 0; v < 4; ++v) base[tt * stt + j * sj + v * sv] = vt[tt][j][v] + bad;
                 __builtin_amdgcn_sched_barrier(0);
             }
         };
@@ -499,7 +517,13 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
         }
     }
 
-    // ---- D_hat (A_hat is final after the last barrier of the solver role)
+    // ---- D_hat (A_hat is final after the last barrier of the solver role);
+    //      NaN if a hand-off wait ran out (the caller sees a non-finite iterate)
+    __syncthreads();
+    if (ctr[8]) {
+        for (int e = tid; e < AP; e += NT) Ap[e] = __builtin_nan("");
+        __syncthreads();
+    }
     if (MODE == SUB_PLAIN) {
         double *dd = a.dout + (size_t)pr * M2 * M2;
         for (int e = tid; e < M2 * M2; e += NT) dd[e] = Ap[pkm(e % M2, e / M2)];
@@ -531,8 +555,20 @@ static void launch_sub_t(const SubArgs &a, hipStream_t s) {
     JX_LAUNCHED();
 }
 
+// JACOBI_HANDOFF_SPIN (environment): bound of the hand-off waits, for tests
+// of the failure path (a tiny bound makes them run out).
+static int handoff_spin() {
+    static const int v = [] {
+        const char *e = std::getenv("JACOBI_HANDOFF_SPIN");
+        return e ? std::max(0, std::atoi(e)) : 0;
+    }();
+    return v;
+}
+
 template <int MODE>
-static void launch_sub2_t(const SubArgs &a, hipStream_t s) {
+static void launch_sub2_t(const SubArgs &a0, hipStream_t s) {
+    SubArgs a = a0;
+    if (a.spin_limit <= 0) a.spin_limit = handoff_spin();
     static bool attr_set = false;
     if (!attr_set) {
         JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_subproblem2<MODE>),

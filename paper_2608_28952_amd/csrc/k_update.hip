@@ -215,26 +215,25 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
 
 // Q(r0 .. r0+127, [I,J]) <- Q(r0 .. r0+127, [I,J]) V_p, computed as
 // out^T = V_p^T X^T so that lanes hold consecutive rows of the column-major Q.
-// Waves in a 2 x 2 layout: wave (wi, wj) owns out columns b wi .. b wi + b-1
-// (of the 2b pair columns) and Q rows r0 + 64 wj .. r0 + 64 wj + 63.
+// 256 threads (t = 0 .. 255) in a 2 x 2 wave layout: wave (wi, wj) owns out
+// columns b wi .. b wi + b-1 (of the 2b pair columns) and Q rows
+// r0 + 64 wj .. r0 + 64 wj + 63.  `active` false: no work, but the barrier
+// before the in-place store is still taken (the caller's barrier count).
 template <int B, class T>
-__global__ void __launch_bounds__(256, 2)
-k_update_q(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
-           const T *__restrict__ vhat, const int *__restrict__ flags) {
+__device__ __forceinline__ void uq_item(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
+                                        const T *__restrict__ vhat, int p, int rb, int t, bool active) {
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int M2 = 2 * B;
     constexpr int HALF = M2 / 2;     // out columns per wave
     constexpr int IT = HALF / 16;    // 16-tiles of out columns per wave
     constexpr int JT = 4;            // 16-tiles of rows per wave (64 rows)
-    const int p = blockIdx.y;
-    if (flags[p]) return;
-    const int I = pairs[2 * p], J = pairs[2 * p + 1];
+    const int I = active ? pairs[2 * p] : 0, J = active ? pairs[2 * p + 1] : 0;
     const T *vp = vhat + (size_t)p * M2 * M2;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lane = t & 63, w = t >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int wi = w & 1, wj = w >> 1;
-    const size_t r0 = (size_t)blockIdx.x * 128 + 64 * wj;
+    const size_t r0 = (size_t)rb * 128 + 64 * wj;
 
     acc_t acc[IT][JT];
 #pragma unroll
@@ -244,47 +243,81 @@ k_update_q(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
 
     auto colof = [&](int k) { return k < B ? I * B + k : J * B + (k - B); };
 
-    T an[IT], bn[JT];
-    {
-        const int k = MT::kstep(0, g);
-        const T *qc = Q + (size_t)colof(k) * ldq + r0;
-#pragma unroll
-        for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
-#pragma unroll
-        for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
-    }
-#pragma unroll 4
-    for (int st = 0; st < M2 / 4; ++st) {
-        T a_[IT], b_[JT];
-#pragma unroll
-        for (int i = 0; i < IT; ++i) a_[i] = an[i];
-#pragma unroll
-        for (int j = 0; j < JT; ++j) b_[j] = bn[j];
-        if (st + 1 < M2 / 4) {
-            const int k = 16 * ((st + 1) >> 2) + MT::kstep((st + 1) & 3, g);
+    if (active) {
+        T an[IT], bn[JT];
+        {
+            const int k = MT::kstep(0, g);
             const T *qc = Q + (size_t)colof(k) * ldq + r0;
 #pragma unroll
             for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
 #pragma unroll
             for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
         }
+#pragma unroll 4
+        for (int st = 0; st < M2 / 4; ++st) {
+            T a_[IT], b_[JT];
 #pragma unroll
-        for (int i = 0; i < IT; ++i)
+            for (int i = 0; i < IT; ++i) a_[i] = an[i];
 #pragma unroll
-            for (int j = 0; j < JT; ++j) acc[i][j] = MT::mma(a_[i], b_[j], acc[i][j]);
+            for (int j = 0; j < JT; ++j) b_[j] = bn[j];
+            if (st + 1 < M2 / 4) {
+                const int k = 16 * ((st + 1) >> 2) + MT::kstep((st + 1) & 3, g);
+                const T *qc = Q + (size_t)colof(k) * ldq + r0;
+#pragma unroll
+                for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
+#pragma unroll
+                for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
+            }
+#pragma unroll
+            for (int i = 0; i < IT; ++i)
+#pragma unroll
+                for (int j = 0; j < JT; ++j) acc[i][j] = MT::mma(a_[i], b_[j], acc[i][j]);
+        }
     }
     // the two waves sharing these rows read every pair column: wait for both
     // before the in-place store
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < IT; ++i)
+        for (int i = 0; i < IT; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            T *qc = Q + (size_t)colof(HALF * wi + 16 * i + MT::rrow(g, v)) * ldq + r0;
+            for (int v = 0; v < 4; ++v) {
+                T *qc = Q + (size_t)colof(HALF * wi + 16 * i + MT::rrow(g, v)) * ldq + r0;
 #pragma unroll
-            for (int j = 0; j < JT; ++j) qc[16 * j + x] = acc[i][j][v];
-        }
+                for (int j = 0; j < JT; ++j) qc[16 * j + x] = acc[i][j][v];
+            }
+    }
 }
+
+// One 128-row block of one pair per workgroup: grid (n_rows / 128, npairs).
+template <int B, class T>
+__global__ void __launch_bounds__(256, 2)
+k_update_q(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
+           const T *__restrict__ vhat, const int *__restrict__ flags) {
+    const int p = blockIdx.y;
+    if (flags[p]) return;
+    uq_item<B, T>(pairs, Q, ldq, vhat, p, blockIdx.x, threadIdx.x, true);
+}
+
+// The same work on a bounded set of CUs: 512 threads (two 256-thread halves,
+// each one row block of one pair at a time) and a dynamic LDS request larger
+// than half a CU's, so each workgroup holds a CU of its own and a grid of
+// CUs - reserve workgroups leaves `reserve` CUs free for the subproblem kernel
+// that runs beside it.  Item i = 2 (k gridDim + blockIdx) + half, row block
+// i mod nrb of pair i / nrb; every half takes every barrier.
+template <int B, class T>
+__global__ void __launch_bounds__(512, 1)
+k_update_q_bounded(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
+                   const T *__restrict__ vhat, const int *__restrict__ flags, int nrb, int nwork) {
+    const int half = threadIdx.x >> 8, t = threadIdx.x & 255;
+    for (int i0 = 2 * blockIdx.x; i0 < nwork; i0 += 2 * gridDim.x) {
+        const int i = i0 + half;
+        const int p = i / nrb, rb = i - p * nrb;
+        const bool active = i < nwork && !flags[i < nwork ? p : 0];
+        uq_item<B, T>(pairs, Q, ldq, vhat, active ? p : 0, active ? rb : 0, t, active);
+    }
+}
+constexpr size_t UQ_BOUNDED_LDS = 81 * 1024;  // > half of the 160 KB LDS: one workgroup per CU
 
 template <int B, class T>
 void launch_ua_t(int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
@@ -311,14 +344,49 @@ void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, cons
     else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
 }
 
+// CUs of the current device (cached per device).
+int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    JX_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        hipDeviceProp_t pr;
+        JX_HIP(hipGetDeviceProperties(&pr, dev));
+        cus[dev] = pr.multiProcessorCount;
+    }
+    return cus[dev];
+}
+
+template <int B, class T>
+void launch_uq_bounded(int npairs, const int *pairs, T *Q, int ldq, int n_rows, const T *vhat, const int *flags,
+                       int reserve, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_q_bounded<B, T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)UQ_BOUNDED_LDS));
+        attr = true;
+    }
+    const int nrb = n_rows / 128, nwork = nrb * npairs;
+    const int grid = std::max(1, std::min(device_cus() - reserve, (nwork + 1) / 2));
+    hipLaunchKernelGGL((k_update_q_bounded<B, T>), dim3(grid), dim3(512), UQ_BOUNDED_LDS, s, pairs, Q, ldq, vhat,
+                       flags, nrb, nwork);
+    JX_LAUNCHED();
+}
+
 template <class T>
 void launch_uq(int b, int npairs, const int *pairs, T *Q, int ldq, int n_rows, const T *vhat, const int *flags,
-               hipStream_t s) {
+               int reserve, hipStream_t s) {
     if (npairs <= 0 || n_rows <= 0) return;
+    if (b != 64 && b != 32) { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
+    if (reserve > 0) {
+        if (b == 64) launch_uq_bounded<64, T>(npairs, pairs, Q, ldq, n_rows, vhat, flags, reserve, s);
+        else launch_uq_bounded<32, T>(npairs, pairs, Q, ldq, n_rows, vhat, flags, reserve, s);
+        return;
+    }
     dim3 grid(n_rows / 128, npairs);
     if (b == 64) hipLaunchKernelGGL((k_update_q<64, T>), grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
-    else if (b == 32) hipLaunchKernelGGL((k_update_q<32, T>), grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
-    else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
+    else hipLaunchKernelGGL((k_update_q<32, T>), grid, dim3(256), 0, s, pairs, Q, ldq, vhat, flags);
     JX_LAUNCHED();
 }
 
@@ -333,12 +401,12 @@ void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const f
     launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
 }
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
-                     const double *vhat, const int *flags, hipStream_t s) {
-    launch_uq<double>(b, npairs, pairs, Q, ldq, n_rows, vhat, flags, s);
+                     const double *vhat, const int *flags, hipStream_t s, int reserve) {
+    launch_uq<double>(b, npairs, pairs, Q, ldq, n_rows, vhat, flags, reserve, s);
 }
 void launch_update_q32(int b, int npairs, const int *pairs, float *Q, int ldq, int n_rows, const float *vhat,
-                       const int *flags, hipStream_t s) {
-    launch_uq<float>(b, npairs, pairs, Q, ldq, n_rows, vhat, flags, s);
+                       const int *flags, hipStream_t s, int reserve) {
+    launch_uq<float>(b, npairs, pairs, Q, ldq, n_rows, vhat, flags, reserve, s);
 }
 
 }  // namespace jx

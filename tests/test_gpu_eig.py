@@ -337,3 +337,29 @@ def test_eig_n4096_graded_mixed_fp32(jx):
     cols = np.random.default_rng(0).choice(n, 48, replace=False)
     res, orth = O.check_eig_sampled(A, W, Q, cols)
     assert res <= 1e-12 / np.sqrt(48) * 10 and orth <= 1e-13, (res, orth)
+
+
+def test_handoff_wait_bound_reports_nonfinite(tmp_path):
+    """At 2b = 128 the subproblem kernel hands each round's rotations from the
+    sweeping wave to the wave that accumulates V, through waits that are
+    bounded.  A wait whose bound runs out poisons the kernel's output with NaN,
+    so the solve reports a non-finite iterate (status 2) instead of returning
+    wrong numbers.  A bound of one poll (JACOBI_HANDOFF_SPIN=1, read once per
+    process, hence the child process) forces that path; every kernel still
+    exits normally."""
+    import os
+    import subprocess
+    import sys
+    script = tmp_path / "bound.py"
+    script.write_text(
+        "import sys\n"
+        f"sys.path.insert(0, {os.path.dirname(os.path.dirname(os.path.abspath(__file__)))!r})\n"
+        "import numpy as np, torch\n"
+        "from paper_2608_28952_amd import inputs, jacobi as jx\n"
+        "A, _ = inputs.eig_uniform(256, 5)\n"
+        "W, Q, info = jx.jacobi_eig(torch.from_numpy(A).cuda(), opts=jx.opts_default(block=64), check=False)\n"
+        "print('status', info['status'], flush=True)\n")
+    env = dict(os.environ, JACOBI_HANDOFF_SPIN="1")
+    r = subprocess.run([sys.executable, str(script)], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "status 2" in r.stdout, r.stdout
