@@ -65,14 +65,18 @@ int ora_antidiag_list(int P, int *pairs, int *sizes)
     if (P < 2) return 0;
     for (int K = 0; K < P; ++K) {
         int cnt = 0;
-        for (int I = 1; I <= P - 1; ++I)
-            for (int J = I + 1; J <= P; ++J)
-                if ((I + J) % P == K % P) {
-                    pairs[2 * total] = I - 1;
-                    pairs[2 * total + 1] = J - 1;
-                    ++total;
-                    ++cnt;
-                }
+        /* for each I the one J in 1 .. P with I + J = K mod P; kept if J > I
+         * (the pairs of the group in increasing I) */
+        for (int I = 1; I <= P - 1; ++I) {
+            int J = ((K - I) % P + P) % P;
+            if (J == 0) J = P;
+            if (J > I) {
+                pairs[2 * total] = I - 1;
+                pairs[2 * total + 1] = J - 1;
+                ++total;
+                ++cnt;
+            }
+        }
         sizes[K] = cnt;
     }
     return total;
@@ -98,14 +102,16 @@ int ora_rr_list(int N, int *pairs, int *sizes)
     int M = N - 1, total = 0;
     for (int K = 0; K < M; ++K) {
         int cnt = 0;
-        for (int I = 1; I <= M - 1; ++I)
-            for (int J = I + 1; J <= M; ++J)
-                if ((I + J) % M == K % M) {
-                    pairs[2 * total] = I - 1;
-                    pairs[2 * total + 1] = J - 1;
-                    ++total;
-                    ++cnt;
-                }
+        for (int I = 1; I <= M - 1; ++I) {  /* the one J in 1 .. M with I + J = K mod M */
+            int J = ((K - I) % M + M) % M;
+            if (J == 0) J = M;
+            if (J > I) {
+                pairs[2 * total] = I - 1;
+                pairs[2 * total + 1] = J - 1;
+                ++total;
+                ++cnt;
+            }
+        }
         for (int I = 1; I <= M; ++I)
             if ((2 * I) % M == K % M) {
                 pairs[2 * total] = I - 1;

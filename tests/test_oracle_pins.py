@@ -112,6 +112,21 @@ def test_round_robin_covers_each_pair_once(N):
     assert len(R) == (N - 1 if N % 2 == 0 else N)
 
 
+@pytest.mark.parametrize("N", list(range(2, 41)))
+def test_schedules_equal_the_scan_of_their_definition(N):
+    """The group of Alg. 3 (pairs with I + J = K mod P, in increasing I) and the
+    even-N round-robin built on it, against a plain scan over all pairs."""
+    def scan(P):
+        return [[(I - 1, J - 1) for I in range(1, P) for J in range(I + 1, P + 1) if (I + J) % P == K % P]
+                for K in range(P)]
+    assert O.antidiag_list(N) == scan(N)
+    if N % 2 == 0:
+        M = N - 1
+        want = [g + [(I - 1, N - 1) for I in range(1, M + 1) if (2 * I) % M == K % M] if M > 0 else []
+                for K, g in enumerate(scan(M) if M > 1 else [[]])]
+        assert O.rr_list(N) == want
+
+
 def test_round_robin_n64_shape():
     R = O.rr_list(64)
     assert len(R) == 63 and all(len(r) == 32 for r in R)
