@@ -144,7 +144,7 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     p.off_flags = wb.add(sizeof(int) * 2 * p.H);
     p.off_pairs = wb.add(sizeof(int) * 2 * (size_t)p.R * p.H);
     p.off_force = wb.add(sizeof(int) * (size_t)p.R * p.H);
-    p.off_tiles = wb.add(sizeof(int) * (size_t)p.H * (p.H - 1));
+    p.off_tiles = wb.add(sizeof(int) * (size_t)p.R * p.H * (p.H - 1));  // per round, critical tiles first
     p.off_partial = wb.add(sizeof(double) * 2 * nb);
     p.off_scal = wb.add(sizeof(double) * 8);
     p.off_w = wb.add(sizeof(double) * npad);
@@ -180,6 +180,11 @@ struct EigState {
     hipEvent_t ev_v[2] = {nullptr, nullptr};   // V_hat(r) ready (on s)
     hipEvent_t ev_q[2] = {nullptr, nullptr};   // Q update of the round using buffer i done (on sq)
     bool q_pending[2] = {false, false};
+    // per round: the first ncrit[r] tiles of its list hold the blocks the next
+    // round's subproblems read; the rest run on sq beside those subproblems
+    std::vector<int> ncrit;
+    hipEvent_t ev_rest = nullptr;  // rest tiles of the last round done (on sq)
+    bool rest_pending = false;
     // profiling: skip flags of every round copied to pinned host memory
     int *h_flaglog = nullptr;
     int flog_cap = 0, flog_count = 0, flog_base = 0;
@@ -242,18 +247,35 @@ struct EigState {
                 slot = flog_base + flog_count * p.H;
                 ++flog_count;
             }
+            // Tile updates.  The critical tiles (those holding the blocks that
+            // round r + 1's subproblems read) run here, on s; the rest run on
+            // sq on at most CUs - H CUs, beside round r + 1's subproblems,
+            // and must be done before round r + 1's tiles.  Without sq every
+            // tile runs here.
+            const int *tl = tiles + (size_t)2 * r * ntiles;
+            const int nc = sq ? ncrit[r] : ntiles;
+            if (rest_pending) {
+                JX_HIP(hipStreamWaitEvent(s, ev_rest, 0));
+                rest_pending = false;
+            }
             {
-                ProfScope ps(PROF_UPDATE_A, s, 0.0, 0.0, slot, p.H, m2);
-                if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tiles, ntiles, s);
-                else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tiles, ntiles, s);
+                ProfScope ps(PROF_UPDATE_A, s, (double)nc / ntiles, 0.0, slot, p.H, m2);
+                if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s);
+                else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s);
+            }
+            if (sq) {
+                JX_HIP(hipEventRecord(ev_v[buf], s));
+                JX_HIP(hipStreamWaitEvent(sq, ev_v[buf], 0));
+                if (nc < ntiles) {
+                    ProfScope ps(PROF_UPDATE_A, sq, (double)(ntiles - nc) / ntiles, 0.0, slot, p.H, m2);
+                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl + 2 * nc, ntiles - nc, sq, p.H);
+                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl + 2 * nc, ntiles - nc, sq, p.H);
+                }
+                JX_HIP(hipEventRecord(ev_rest, sq));
+                rest_pending = true;
             }
             if (p.need_q) {
-                hipStream_t qs = s;
-                if (sq) {
-                    JX_HIP(hipEventRecord(ev_v[buf], s));
-                    JX_HIP(hipStreamWaitEvent(sq, ev_v[buf], 0));
-                    qs = sq;
-                }
+                hipStream_t qs = sq ? sq : s;
                 {
                     ProfScope ps(PROF_UPDATE_Q, qs, (double)p.npad, 0.0, slot, p.H, m2);
                     // beside the next round's subproblems: leave them their CUs
@@ -261,13 +283,17 @@ struct EigState {
                     if (f32) launch_update_q32(p.b, p.H, pr, Q32, p.npad, p.npad, Vbuf32(r), Fbuf(r), qs, reserve);
                     else launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs, reserve);
                 }
-                if (sq) {
-                    JX_HIP(hipEventRecord(ev_q[buf], sq));
-                    q_pending[buf] = true;
-                }
+            }
+            if (sq) {  // V_hat / flag buffer `buf` free once sq is past this round
+                JX_HIP(hipEventRecord(ev_q[buf], sq));
+                q_pending[buf] = true;
             }
         }
-        // Q complete before anyone reads it (the refinement, the output)
+        // A and Q complete before anyone reads them (norms, refinement, output)
+        if (rest_pending) {
+            JX_HIP(hipStreamWaitEvent(s, ev_rest, 0));
+            rest_pending = false;
+        }
         for (int i = 0; i < 2; ++i)
             if (sq && q_pending[i]) {
                 JX_HIP(hipStreamWaitEvent(s, ev_q[i], 0));
@@ -276,12 +302,12 @@ struct EigState {
     }
 
     void make_streams() {
-        if (!p.need_q) return;
         JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
         for (int i = 0; i < 2; ++i) {
             JX_HIP(hipEventCreateWithFlags(&ev_v[i], hipEventDisableTiming));
             JX_HIP(hipEventCreateWithFlags(&ev_q[i], hipEventDisableTiming));
         }
+        JX_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
     }
     ~EigState() {
         if (sq) (void)hipStreamSynchronize(sq);
@@ -289,6 +315,7 @@ struct EigState {
             if (ev_v[i]) (void)hipEventDestroy(ev_v[i]);
             if (ev_q[i]) (void)hipEventDestroy(ev_q[i]);
         }
+        if (ev_rest) (void)hipEventDestroy(ev_rest);
         if (sq) (void)hipStreamDestroy(sq);
     }
 };
@@ -354,9 +381,35 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     std::vector<int> hp, hf;
     padded_rounds(p.N, o.ordering, hp, hf);
     st.any_force = std::any_of(hf.begin(), hf.end(), [](int v) { return v != 0; }) ? 1 : 0;
+    // tile lists: per round, the critical tiles first (tile (p, q) of round r
+    // holds block (I', J') of a pair of round r + 1 (cyclically) when I' is in
+    // pair p and J' in pair q), then the others in (p, q) order
     std::vector<int> ht;
-    for (int a = 0; a < p.H; ++a)
-        for (int b = a + 1; b < p.H; ++b) { ht.push_back(a); ht.push_back(b); }
+    st.ncrit.assign(p.R, 0);
+    {
+        std::vector<int> pos(p.N, 0);
+        std::vector<char> crit((size_t)p.H * p.H);
+        for (int r = 0; r < p.R; ++r) {
+            for (int k = 0; k < p.H; ++k) {
+                pos[hp[2 * ((size_t)r * p.H + k)]] = k;
+                pos[hp[2 * ((size_t)r * p.H + k) + 1]] = k;
+            }
+            std::fill(crit.begin(), crit.end(), 0);
+            const int rn = (r + 1) % p.R;
+            for (int k = 0; k < p.H; ++k) {
+                const int a = pos[hp[2 * ((size_t)rn * p.H + k)]], b = pos[hp[2 * ((size_t)rn * p.H + k) + 1]];
+                const int lo = std::min(a, b), hi = std::max(a, b);
+                if (lo == hi || crit[(size_t)lo * p.H + hi]) continue;
+                crit[(size_t)lo * p.H + hi] = 1;
+                ht.push_back(lo);
+                ht.push_back(hi);
+                ++st.ncrit[r];
+            }
+            for (int a = 0; a < p.H; ++a)
+                for (int b = a + 1; b < p.H; ++b)
+                    if (!crit[(size_t)a * p.H + b]) { ht.push_back(a); ht.push_back(b); }
+        }
+    }
     JX_HIP(hipMemcpyAsync(st.pairs, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, s));
     JX_HIP(hipMemcpyAsync(st.force, hf.data(), sizeof(int) * hf.size(), hipMemcpyHostToDevice, s));
     if (!ht.empty())

@@ -46,9 +46,8 @@ struct UaCfg {
 // that this thread stages.  Rows 0..B-1 come from block row Rr[0], rows
 // B..2B-1 from Rr[1]; the chunk lies in block column Cc.
 template <int B, class T>
-__device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int Cc, int c0, T *reg) {
+__device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int Cc, int c0, T *reg, int tid) {
     using U = UaCfg<B>;
-    const int tid = threadIdx.x;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int R = h ? Rr[1] : Rr[0];
@@ -71,9 +70,8 @@ __device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int 
 }
 
 template <int B, class T>
-__device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, const T *reg) {
+__device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, const T *reg, int tid) {
     using U = UaCfg<B>;
-    const int tid = threadIdx.x;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int R = h ? Rr[1] : Rr[0];
@@ -88,26 +86,23 @@ __device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, cons
     }
 }
 
+// Tile (p, q) by 256 threads t = 0 .. 255 with `lds` (U::LDS_BYTES) of their
+// own.  active false (no tile, or both rotations skipped): no work, but every
+// barrier is still taken, so two halves of one workgroup stay in step.
 template <int B, class T>
-__global__ void __launch_bounds__(256, 2)
-k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
-           const int *__restrict__ flags, const int *__restrict__ tiles) {
+__device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__restrict__ ablk,
+                                        const T *__restrict__ vhat, int p, int q, bool idp, bool idq, int tid,
+                                        T *lds, bool active) {
     using U = UaCfg<B>;
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int M2 = U::M2, RT = U::RT, CT = U::CT, WW = U::WW;
-    extern __shared__ double lds_raw[];
-    T *lds = reinterpret_cast<T *>(lds_raw);
-
-    const int p = tiles[2 * blockIdx.x], q = tiles[2 * blockIdx.x + 1];
-    const bool idp = flags[p] != 0, idq = flags[q] != 0;
-    if (idp && idq) return;
-    const int Rr[2] = {pairs[2 * p], pairs[2 * p + 1]};
-    const int Cq[2] = {pairs[2 * q], pairs[2 * q + 1]};
+    const int Rr[2] = {active ? pairs[2 * p] : 0, active ? pairs[2 * p + 1] : 1};
+    const int Cq[2] = {active ? pairs[2 * q] : 0, active ? pairs[2 * q + 1] : 1};
     const T *vp = vhat + (size_t)p * M2 * M2;
     const T *vq = vhat + (size_t)q * M2 * M2;
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int wc0 = w * WW;
 
@@ -119,19 +114,21 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
 
     // ---------------- GEMM 1: T(:, wc0 .. wc0+WW-1) = X V_q ----------------
     T reg[U::PER];
-    fetch_chunk<B, T>(ablk, Rr, Cq[0], 0, reg);
-    stage_chunk<B, T>(lds, Rr, Cq[0], reg);
+    if (active) {
+        fetch_chunk<B, T>(ablk, Rr, Cq[0], 0, reg, tid);
+        stage_chunk<B, T>(lds, Rr, Cq[0], reg, tid);
+    }
     __syncthreads();
     for (int ch = 0; ch < U::NCH; ++ch) {
         T *xs = lds + (size_t)(ch & 1) * KC * U::XLD;
-        if (ch + 1 < U::NCH) {
+        if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            fetch_chunk<B, T>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg);
+            fetch_chunk<B, T>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg, tid);
         }
         // (V_q = I is applied as an exact identity operand: products with 1.0
         // and sums of exact zeros reproduce X bit for bit)
 #pragma unroll 1
-        for (int st = 0; st < KC / 4; ++st) {
+        for (int st = 0; st < (active ? KC / 4 : 0); ++st) {
             const int kl = MT::kstep(st, g);
             const int kg = ch * KC + kl;
             T bf[CT];
@@ -147,9 +144,9 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
                 for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = MT::mma(af, bf[ct], acc[rt][ct]);
             }
         }
-        if (ch + 1 < U::NCH) {
+        if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            stage_chunk<B, T>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg);
+            stage_chunk<B, T>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg, tid);
         }
         __syncthreads();
     }
@@ -162,7 +159,7 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
     for (int h = 0; h < 2; ++h) {
         T *os = lds;
 #pragma unroll 1
-        for (int ot = 0; ot < RT / 2; ++ot) {
+        for (int ot = 0; ot < (active ? RT / 2 : 0); ++ot) {
             acc_t o[CT];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) o[ct] = acc_t{0, 0, 0, 0};
@@ -195,7 +192,8 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int Cc = cb ? Cq[1] : Cq[0];
-            if (R < Cc) {
+            if (!active) {
+            } else if (R < Cc) {
                 T *dst = ablk + ublk(R, Cc) * (size_t)(B * B);
                 for (int e = tid; e < B * B; e += 256) {
                     const int rl = e % B, cl = e / B;
@@ -210,6 +208,39 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
             }
         }
         __syncthreads();
+    }
+}
+
+// One tile per workgroup: tile i = (tiles[2 i], tiles[2 i + 1]).
+template <int B, class T>
+__global__ void __launch_bounds__(256, 2)
+k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
+           const int *__restrict__ flags, const int *__restrict__ tiles) {
+    extern __shared__ double lds_raw[];
+    const int p = tiles[2 * blockIdx.x], q = tiles[2 * blockIdx.x + 1];
+    const bool idp = flags[p] != 0, idq = flags[q] != 0;
+    if (idp && idq) return;
+    ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, reinterpret_cast<T *>(lds_raw), true);
+}
+
+// The same tiles on a bounded set of CUs (as k_update_q_bounded): 512 threads,
+// two 256-thread halves with their own LDS, each one tile at a time (tile
+// 2 (k gridDim + blockIdx) + half); the LDS request keeps one workgroup per
+// CU, so a grid of CUs - reserve leaves `reserve` CUs free.
+template <int B, class T>
+__global__ void __launch_bounds__(512, 1)
+k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
+                   const int *__restrict__ flags, const int *__restrict__ tiles, int ntiles) {
+    using U = UaCfg<B>;
+    extern __shared__ double lds_raw[];
+    const int half = threadIdx.x >> 8, t = threadIdx.x & 255;
+    T *lds = reinterpret_cast<T *>(reinterpret_cast<char *>(lds_raw) + half * U::LDS_BYTES);
+    for (int i0 = 2 * blockIdx.x; i0 < ntiles; i0 += 2 * gridDim.x) {
+        const int i = i0 + half;
+        const int p = i < ntiles ? tiles[2 * i] : 0, q = i < ntiles ? tiles[2 * i + 1] : 1;
+        const bool idp = flags[p] != 0, idq = flags[q] != 0;
+        const bool active = i < ntiles && !(idp && idq);
+        ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, t, lds, active);
     }
 }
 
@@ -335,13 +366,38 @@ void launch_ua_t(int npairs, const int *pairs, T *ablk, const T *vhat, const int
     JX_LAUNCHED();
 }
 
+int device_cus();
+
+template <int B, class T>
+void launch_ua_bounded(const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles, int ntiles,
+                       int reserve, hipStream_t s) {
+    using U = UaCfg<B>;
+    // two halves' LDS, and more than half a CU's in any case: one workgroup per CU
+    const size_t lds = std::max<size_t>(2 * U::LDS_BYTES, 81 * 1024);
+    static bool attr = false;
+    if (!attr) {
+        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a_bounded<B, T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+    }
+    const int grid = std::max(1, std::min(device_cus() - reserve, (ntiles + 1) / 2));
+    hipLaunchKernelGGL((k_update_a_bounded<B, T>), dim3(grid), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
+                       ntiles);
+    JX_LAUNCHED();
+}
+
 template <class T>
 void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
-               int ntiles, hipStream_t s) {
+               int ntiles, int reserve, hipStream_t s) {
     if (ntiles <= 0) return;
+    if (b != 64 && b != 32) { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
+    if (reserve > 0) {
+        if (b == 64) launch_ua_bounded<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
+        else launch_ua_bounded<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
+        return;
+    }
     if (b == 64) launch_ua_t<64, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
-    else if (b == 32) launch_ua_t<32, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
-    else { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
+    else launch_ua_t<32, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
 }
 
 // CUs of the current device (cached per device).
@@ -393,12 +449,12 @@ void launch_uq(int b, int npairs, const int *pairs, T *Q, int ldq, int n_rows, c
 }  // namespace
 
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
-                     const int *flags, const int *tiles, int ntiles, hipStream_t s) {
-    launch_ua<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
+                     const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve) {
+    launch_ua<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
 }
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
-                       const int *tiles, int ntiles, hipStream_t s) {
-    launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
+                       const int *tiles, int ntiles, hipStream_t s, int reserve) {
+    launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
 }
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s, int reserve) {
