@@ -260,8 +260,9 @@ struct EigState {
             }
             {
                 ProfScope ps(PROF_UPDATE_A, s, (double)nc / ntiles, 0.0, slot, p.H, m2);
-                if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s);
-                else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s);
+                const int mode = sq ? UA_LATENCY : 0;
+                if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s, mode);
+                else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s, mode);
             }
             if (sq) {
                 JX_HIP(hipEventRecord(ev_v[buf], s));

@@ -172,6 +172,9 @@ size_t batched_lds_bytes(int bs, int m2); // dynamic LDS of the class kernel
 
 // Fused two-sided update of the off-diagonal pair tiles of one round:
 // A[p,q] <- V_p^T A[p,q] V_q for p < q (pair indices of the round).
+// reserve > 0: on at most (CUs - reserve) CUs; UA_LATENCY: one workgroup of
+// eight waves per tile (for few tiles that others wait for); 0: four waves.
+constexpr int UA_LATENCY = -1;
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
                      const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve = 0);
 // Gram blocks of the one-sided SVD: ahat[p] = G(:, [I,J])^T G(:, [I,J]) over the

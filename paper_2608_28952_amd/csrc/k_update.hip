@@ -27,16 +27,16 @@ namespace {
 
 constexpr int KC = 16;  // X chunk width (columns)
 
-template <int B>
+template <int B, int NTH = 256>
 struct UaCfg {
     static constexpr int M2 = 2 * B;      // tile order
     static constexpr int RT = M2 / 16;    // 16-row tiles
-    static constexpr int WW = M2 / 4;     // columns per wave
+    static constexpr int WW = M2 / (NTH / 64);  // columns per wave
     static constexpr int CT = WW / 16;    // 16-column tiles per wave
     static constexpr int XLD = M2 + 1;    // LDS stride of an X chunk [k][row]
     static constexpr int OLD = B + 1;     // LDS stride of an output half [col][row]
     static constexpr int NCH = M2 / KC;   // chunks
-    static constexpr int PER = 2 * B * KC / 256;  // X chunk values per thread
+    static constexpr int PER = 2 * B * KC / NTH;  // X chunk values per thread
     static constexpr size_t XS_DOUBLES = 2 * (size_t)KC * XLD;
     static constexpr size_t OS_DOUBLES = (size_t)M2 * OLD;
     static constexpr size_t LDS_BYTES = sizeof(double) * (XS_DOUBLES > OS_DOUBLES ? XS_DOUBLES : OS_DOUBLES);
@@ -45,15 +45,15 @@ struct UaCfg {
 // Fetch the PER values of X chunk `ch` (columns ch*KC .. +KC-1 of the tile)
 // that this thread stages.  Rows 0..B-1 come from block row Rr[0], rows
 // B..2B-1 from Rr[1]; the chunk lies in block column Cc.
-template <int B, class T>
+template <int B, class T, int NTH>
 __device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int Cc, int c0, T *reg, int tid) {
-    using U = UaCfg<B>;
+    using U = UaCfg<B, NTH>;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int R = h ? Rr[1] : Rr[0];
 #pragma unroll
         for (int m = 0; m < U::PER / 2; ++m) {
-            const int e = tid + 256 * m;  // 0 .. B*KC-1
+            const int e = tid + NTH * m;  // 0 .. B*KC-1
             T v;
             if (R < Cc) {
                 const T *src = ablk + ublk(R, Cc) * (size_t)(B * B);
@@ -69,15 +69,15 @@ __device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int 
     }
 }
 
-template <int B, class T>
+template <int B, class T, int NTH>
 __device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, const T *reg, int tid) {
-    using U = UaCfg<B>;
+    using U = UaCfg<B, NTH>;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int R = h ? Rr[1] : Rr[0];
 #pragma unroll
         for (int m = 0; m < U::PER / 2; ++m) {
-            const int e = tid + 256 * m;
+            const int e = tid + NTH * m;
             int rl, cl;
             if (R < Cc) { rl = e % B; cl = e / B; }
             else { cl = e % KC; rl = e / KC; }
@@ -86,14 +86,15 @@ __device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, cons
     }
 }
 
-// Tile (p, q) by 256 threads t = 0 .. 255 with `lds` (U::LDS_BYTES) of their
-// own.  active false (no tile, or both rotations skipped): no work, but every
+// Tile (p, q) by NTH threads t = 0 .. NTH-1 (NTH / 64 waves, each owning
+// 2b / (NTH / 64) columns of T) with `lds` (U::LDS_BYTES) of their own.
+// active false (no tile, or both rotations skipped): no work, but every
 // barrier is still taken, so two halves of one workgroup stay in step.
-template <int B, class T>
+template <int B, class T, int NTH = 256>
 __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__restrict__ ablk,
                                         const T *__restrict__ vhat, int p, int q, bool idp, bool idq, int tid,
                                         T *lds, bool active) {
-    using U = UaCfg<B>;
+    using U = UaCfg<B, NTH>;
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int M2 = U::M2, RT = U::RT, CT = U::CT, WW = U::WW;
@@ -115,15 +116,15 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
     // ---------------- GEMM 1: T(:, wc0 .. wc0+WW-1) = X V_q ----------------
     T reg[U::PER];
     if (active) {
-        fetch_chunk<B, T>(ablk, Rr, Cq[0], 0, reg, tid);
-        stage_chunk<B, T>(lds, Rr, Cq[0], reg, tid);
+        fetch_chunk<B, T, NTH>(ablk, Rr, Cq[0], 0, reg, tid);
+        stage_chunk<B, T, NTH>(lds, Rr, Cq[0], reg, tid);
     }
     __syncthreads();
     for (int ch = 0; ch < U::NCH; ++ch) {
         T *xs = lds + (size_t)(ch & 1) * KC * U::XLD;
         if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            fetch_chunk<B, T>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg, tid);
+            fetch_chunk<B, T, NTH>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg, tid);
         }
         // (V_q = I is applied as an exact identity operand: products with 1.0
         // and sums of exact zeros reproduce X bit for bit)
@@ -146,7 +147,7 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
         }
         if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            stage_chunk<B, T>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg, tid);
+            stage_chunk<B, T, NTH>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg, tid);
         }
         __syncthreads();
     }
@@ -195,13 +196,13 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
             if (!active) {
             } else if (R < Cc) {
                 T *dst = ablk + ublk(R, Cc) * (size_t)(B * B);
-                for (int e = tid; e < B * B; e += 256) {
+                for (int e = tid; e < B * B; e += NTH) {
                     const int rl = e % B, cl = e / B;
                     dst[e] = os[(cb * B + cl) * U::OLD + rl];
                 }
             } else {
                 T *dst = ablk + ublk(Cc, R) * (size_t)(B * B);
-                for (int e = tid; e < B * B; e += 256) {
+                for (int e = tid; e < B * B; e += NTH) {
                     const int cl = e % B, rl = e / B;  // stored (Cc, R): element (cl, rl)
                     dst[e] = os[(cb * B + cl) * U::OLD + rl];
                 }
@@ -221,6 +222,19 @@ k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restr
     const bool idp = flags[p] != 0, idq = flags[q] != 0;
     if (idp && idq) return;
     ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, reinterpret_cast<T *>(lds_raw), true);
+}
+
+// One tile per workgroup of eight waves: the tiles that the next round's
+// subproblems wait for, where latency matters more than throughput.
+template <int B, class T>
+__global__ void __launch_bounds__(512, 1)
+k_update_a8(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
+            const int *__restrict__ flags, const int *__restrict__ tiles) {
+    extern __shared__ double lds_raw[];
+    const int p = tiles[2 * blockIdx.x], q = tiles[2 * blockIdx.x + 1];
+    const bool idp = flags[p] != 0, idq = flags[q] != 0;
+    if (idp && idq) return;
+    ua_tile<B, T, 512>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, reinterpret_cast<T *>(lds_raw), true);
 }
 
 // The same tiles on a bounded set of CUs (as k_update_q_bounded): 512 threads,
@@ -394,6 +408,19 @@ void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, cons
     if (reserve > 0) {
         if (b == 64) launch_ua_bounded<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
         else launch_ua_bounded<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
+        return;
+    }
+    if (reserve == UA_LATENCY && b == 64) {  // eight waves per tile (b = 32 keeps four: 16 columns each)
+        using U = UaCfg<64, 512>;
+        static bool attr = false;
+        if (!attr) {
+            JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a8<64, T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::LDS_BYTES));
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_update_a8<64, T>), dim3(ntiles), dim3(512), U::LDS_BYTES, s, pairs, ablk, vhat, flags,
+                           tiles);
+        JX_LAUNCHED();
         return;
     }
     if (b == 64) launch_ua_t<64, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
