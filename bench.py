@@ -40,9 +40,12 @@ N = 4096
 BLOCK = 64
 SEED = 2
 PEAK = {"fp64_tflops": 78.6, "hbm_gbs": 8000.0}
-KINDS = {0: "k_subproblem2", 1: "k_update_a", 2: "k_update_q", 3: "k_gemm_f64"}
+KINDS = {0: "k_subproblem2", 1: "k_update_a", 2: "k_update_q", 3: "k_gemm_f64", 5: "k_update_a_bounded"}
 SOURCES = {"k_subproblem2": ["k_subproblem.hip", "jx_sweep.hpp"], "k_update_a": ["k_update.hip"],
-           "k_update_q": ["k_update.hip"], "k_gemm_f64": ["k_gemm.hip"]}
+           "k_update_q": ["k_update.hip"], "k_gemm_f64": ["k_gemm.hip"], "k_update_a_bounded": ["k_update.hip"]}
+# kernels on the second stream, beside the next round's subproblems (not on
+# the solve's critical path): not candidates for the dominant kernel
+SIDE = {"k_update_q", "k_update_a_bounded"}
 
 
 def kernel_source_hash(name):
@@ -261,7 +264,7 @@ def main():
     err = float(np.max(np.abs(W_np - np.sort(lam))))
     sweeps = infos[-1]["sweeps"]
 
-    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dom = max((k for k in prof if k not in SIDE), key=lambda k: prof[k]["ms"])
     d = prof[dom]
     launches = max(d["launches"], 1)
     avg_s = d["ms"] / 1e3 / launches

@@ -294,7 +294,9 @@ enum jacobi_prof_kind {
     JACOBI_PROF_UPDATE_A = 1,   /* fused pair-tile update V_p^T A[p,q] V_q       */
     JACOBI_PROF_UPDATE_Q = 2,   /* Q(:, [I,J]) V_hat                              */
     JACOBI_PROF_GEMM = 3,       /* refinement GEMMs                              */
-    JACOBI_PROF_GRAM = 4        /* Gram blocks of the one-sided SVD              */
+    JACOBI_PROF_GRAM = 4,       /* Gram blocks of the one-sided SVD              */
+    JACOBI_PROF_UPDATE_A_REST = 5 /* pair tiles no next-round subproblem waits for,
+                                     on the second stream beside the subproblems  */
 };
 
 /*

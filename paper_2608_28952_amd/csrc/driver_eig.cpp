@@ -268,7 +268,7 @@ struct EigState {
                 JX_HIP(hipEventRecord(ev_v[buf], s));
                 JX_HIP(hipStreamWaitEvent(sq, ev_v[buf], 0));
                 if (nc < ntiles) {
-                    ProfScope ps(PROF_UPDATE_A, sq, (double)(ntiles - nc) / ntiles, 0.0, slot, p.H, m2);
+                    ProfScope ps(PROF_UPDATE_A_REST, sq, (double)(ntiles - nc) / ntiles, 0.0, slot, p.H, m2);
                     if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl + 2 * nc, ntiles - nc, sq, p.H);
                     else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl + 2 * nc, ntiles - nc, sq, p.H);
                 }

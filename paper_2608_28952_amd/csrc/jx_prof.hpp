@@ -9,7 +9,14 @@
 
 namespace jx {
 
-enum ProfKind { PROF_SUBPROBLEM = 0, PROF_UPDATE_A = 1, PROF_UPDATE_Q = 2, PROF_GEMM = 3, PROF_GRAM = 4 };
+enum ProfKind {
+    PROF_SUBPROBLEM = 0,
+    PROF_UPDATE_A = 1,       // tile updates on the solve's stream (the critical tiles)
+    PROF_UPDATE_Q = 2,
+    PROF_GEMM = 3,
+    PROF_GRAM = 4,
+    PROF_UPDATE_A_REST = 5   // the other tiles, beside the next round's subproblems
+};
 
 bool prof_on();
 

@@ -129,7 +129,7 @@ extern "C" int jacobi_profile_query(int kind, int *launches, double *total_ms, d
             if (r.flag_slot >= 0 && r.flag_slot + r.npairs <= (int)g_flag_log.size()) {
                 double f = 0.0, b = 0.0;
                 const int *fl_ = g_flag_log.data() + r.flag_slot;
-                if (kind == PROF_UPDATE_A) {  // r.flops: the launch's share of the round's tiles
+                if (kind == PROF_UPDATE_A || kind == PROF_UPDATE_A_REST) {  // r.flops: share of the round's tiles
                     tile_work(fl_, r.npairs, r.m2, f, b);
                     const double share = r.flops > 0.0 ? r.flops : 1.0;
                     f *= share;
@@ -145,7 +145,7 @@ extern "C" int jacobi_profile_query(int kind, int *launches, double *total_ms, d
                 }
                 fl += f;
                 by += b;
-            } else if (kind != PROF_UPDATE_A) {
+            } else if (kind != PROF_UPDATE_A && kind != PROF_UPDATE_A_REST) {
                 fl += r.flops;
                 by += r.bytes;
             }
