@@ -115,34 +115,63 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
 
     // ---------------- GEMM 1: T(:, wc0 .. wc0+WW-1) = X V_q ----------------
     T reg[U::PER];
+    // V_q operand of k-step st, column tile ct (V_q = I is applied as an exact
+    // identity operand: products with 1.0 and sums of exact zeros reproduce X
+    // bit for bit)
+    auto vqk = [&](int ch, int st, int ct) {
+        const int kg = ch * KC + MT::kstep(st, g), col = wc0 + 16 * ct + x;
+        return idq ? (kg == col ? T(1) : T(0)) : vq[MT::vidx(kg, col, M2)];
+    };
+    // one column tile per wave: a chunk's V_q operands are fetched one chunk
+    // ahead, so that their global-memory latency hides behind the previous
+    // chunk (with two column tiles the registers are not there)
+    constexpr bool PF = CT == 1;
+    T bnext[KC / 4];
     if (active) {
         fetch_chunk<B, T, NTH>(ablk, Rr, Cq[0], 0, reg, tid);
+        if constexpr (PF) {
+#pragma unroll
+            for (int st = 0; st < KC / 4; ++st) bnext[st] = vqk(0, st, 0);
+        }
         stage_chunk<B, T, NTH>(lds, Rr, Cq[0], reg, tid);
     }
     __syncthreads();
     for (int ch = 0; ch < U::NCH; ++ch) {
         T *xs = lds + (size_t)(ch & 1) * KC * U::XLD;
+        T bcur[KC / 4];
+#pragma unroll
+        for (int st = 0; st < KC / 4; ++st) bcur[st] = bnext[st];
         if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
             fetch_chunk<B, T, NTH>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg, tid);
-        }
-        // (V_q = I is applied as an exact identity operand: products with 1.0
-        // and sums of exact zeros reproduce X bit for bit)
-#pragma unroll 1
-        for (int st = 0; st < (active ? KC / 4 : 0); ++st) {
-            const int kl = MT::kstep(st, g);
-            const int kg = ch * KC + kl;
-            T bf[CT];
+            if constexpr (PF) {
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                const int col = wc0 + 16 * ct + x;
-                bf[ct] = idq ? (kg == col ? T(1) : T(0)) : vq[MT::vidx(kg, col, M2)];
+                for (int st = 0; st < KC / 4; ++st) bnext[st] = vqk(ch + 1, st, 0);
             }
+        }
+        if constexpr (PF) {
+            if (active) {
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const T af = xs[kl * U::XLD + 16 * rt + x];
+                for (int st = 0; st < KC / 4; ++st) {
+                    const int kl = MT::kstep(st, g);
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = MT::mma(af, bf[ct], acc[rt][ct]);
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][0] = MT::mma(xs[kl * U::XLD + 16 * rt + x], bcur[st], acc[rt][0]);
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int st = 0; st < (active ? KC / 4 : 0); ++st) {
+                const int kl = MT::kstep(st, g);
+                T bf[CT];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) bf[ct] = vqk(ch, st, ct);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const T af = xs[kl * U::XLD + 16 * rt + x];
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = MT::mma(af, bf[ct], acc[rt][ct]);
+                }
             }
         }
         if (active && ch + 1 < U::NCH) {
@@ -167,20 +196,36 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
             // (V_p = I is applied as an exact identity operand, as for V_q)
             const int orow = h * B + 16 * ot + x;
             const T *vrow = vp + MT::vidx(0, orow, M2);
+            // V_p operand of step (rt, s): row 16 rt + rrow(g, s) of T sits in
+            // component s of lane group g; vidx(k, i) - vidx(0, i) depends on k only
+            auto vpk = [&](int rt, int s) {
+                const int k = 16 * rt + MT::rrow(g, s);
+                return idp ? (k == orow ? T(1) : T(0)) : vrow[MT::vidx(k, 0, M2) - MT::vidx(0, 0, M2)];
+            };
+            if constexpr (CT == 1) {
+                // one output column tile per wave: every V_p operand of the
+                // row tile is loaded at once (one global-memory latency, not RT)
+                T af[RT][4];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                T af[4];
+                for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {  // vidx(k, i) - vidx(0, i) depends on k only
-                    // row of T held in component s of lane group g
-                    const int k = 16 * rt + MT::rrow(g, s);
-                    af[s] = idp ? (k == orow ? T(1) : T(0)) : vrow[MT::vidx(k, 0, M2) - MT::vidx(0, 0, M2)];
+                    for (int s = 0; s < 4; ++s) af[rt][s] = vpk(rt, s);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) o[0] = MT::mma(af[rt][s], acc[rt][0][s], o[0]);
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    T af[4];
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) af[s] = vpk(rt, s);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+#pragma unroll
+                        for (int ct = 0; ct < CT; ++ct) o[ct] = MT::mma(af[s], acc[rt][ct][s], o[ct]);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) o[ct] = MT::mma(af[s], acc[rt][ct][s], o[ct]);
-                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
