@@ -145,6 +145,8 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     p.off_pairs = wb.add(sizeof(int) * 2 * (size_t)p.R * p.H);
     p.off_force = wb.add(sizeof(int) * (size_t)p.R * p.H);
     p.off_tiles = wb.add(sizeof(int) * (size_t)p.R * p.H * (p.H - 1));  // per round, critical tiles first
+    p.off_qmask = wb.add(sizeof(int) * (size_t)p.R * p.H);               // per critical tile: its next-round blocks
+    p.off_side = wb.add(sizeof(double) * 4 * (size_t)p.H * p.b * p.b);   // their originals (FP64 or FP32)
     p.off_partial = wb.add(sizeof(double) * 2 * nb);
     p.off_scal = wb.add(sizeof(double) * 8);
     p.off_w = wb.add(sizeof(double) * npad);
@@ -167,7 +169,8 @@ struct EigState {
     char *ws;
     hipStream_t s;
     double *ablk, *Q, *V, *partial, *scal;
-    int *flags, *pairs, *force, *tiles;
+    int *flags, *pairs, *force, *tiles, *qmask;
+    void *side;
     float *ablk32 = nullptr, *Q32 = nullptr, *V32 = nullptr;
     bool f32 = false;  // current phase works on the FP32 copies
     double *h_scal;  // pinned
@@ -181,7 +184,9 @@ struct EigState {
     hipEvent_t ev_q[2] = {nullptr, nullptr};   // Q update of the round using buffer i done (on sq)
     bool q_pending[2] = {false, false};
     // per round: the first ncrit[r] tiles of its list hold the blocks the next
-    // round's subproblems read; the rest run on sq beside those subproblems
+    // round's subproblems read (qmask: which of their four blocks); those
+    // blocks are done first, the rest of every tile on sq beside the next
+    // round's subproblems
     std::vector<int> ncrit;
     hipEvent_t ev_rest = nullptr;  // rest tiles of the last round done (on sq)
     bool rest_pending = false;
@@ -247,30 +252,32 @@ struct EigState {
                 slot = flog_base + flog_count * p.H;
                 ++flog_count;
             }
-            // Tile updates.  The critical tiles (those holding the blocks that
-            // round r + 1's subproblems read) run here, on s; the rest run on
-            // sq on at most CUs - H CUs, beside round r + 1's subproblems,
-            // and must be done before round r + 1's tiles.  Without sq every
-            // tile runs here.
+            // Tile updates.  The blocks that round r + 1's subproblems read
+            // (qm: some quadrants of the first nc tiles) are computed here, on
+            // s, their originals saved to `side`; the rest of every tile runs
+            // on sq on at most CUs - H CUs, beside round r + 1's subproblems,
+            // and must be done before round r + 1's tiles (which also reuse
+            // `side`).
             const int *tl = tiles + (size_t)2 * r * ntiles;
-            const int nc = sq ? ncrit[r] : ntiles;
+            const int *qm = qmask + (size_t)r * p.H;
+            const int nc = ncrit[r];
             if (rest_pending) {
                 JX_HIP(hipStreamWaitEvent(s, ev_rest, 0));
                 rest_pending = false;
             }
             {
-                ProfScope ps(PROF_UPDATE_A, s, (double)nc / ntiles, 0.0, slot, p.H, m2);
-                const int mode = sq ? UA_LATENCY : 0;
-                if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s, mode);
-                else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s, mode);
-            }
-            if (sq) {
+                {
+                    // one block of a tile: 3/8 of its products (b = 64), 3/4 (b = 32)
+                    ProfScope ps(PROF_UPDATE_A, s, (p.b == 64 ? 0.375 : 0.75) * nc / ntiles, 0.0, slot, p.H, m2);
+                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, side);
+                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, side);
+                }
                 JX_HIP(hipEventRecord(ev_v[buf], s));
                 JX_HIP(hipStreamWaitEvent(sq, ev_v[buf], 0));
-                if (nc < ntiles) {
-                    ProfScope ps(PROF_UPDATE_A_REST, sq, (double)(ntiles - nc) / ntiles, 0.0, slot, p.H, m2);
-                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl + 2 * nc, ntiles - nc, sq, p.H);
-                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl + 2 * nc, ntiles - nc, sq, p.H);
+                {
+                    ProfScope ps(PROF_UPDATE_A_REST, sq, 1.0, 0.0, slot, p.H, m2);
+                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
+                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
                 }
                 JX_HIP(hipEventRecord(ev_rest, sq));
                 rest_pending = true;
@@ -360,6 +367,8 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     st.pairs = reinterpret_cast<int *>(ws + p.off_pairs);
     st.force = reinterpret_cast<int *>(ws + p.off_force);
     st.tiles = reinterpret_cast<int *>(ws + p.off_tiles);
+    st.qmask = reinterpret_cast<int *>(ws + p.off_qmask);
+    st.side = ws + p.off_side;
     st.partial = reinterpret_cast<double *>(ws + p.off_partial);
     st.scal = reinterpret_cast<double *>(ws + p.off_scal);
     st.h_scal = pin.ptr;
@@ -384,37 +393,47 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     st.any_force = std::any_of(hf.begin(), hf.end(), [](int v) { return v != 0; }) ? 1 : 0;
     // tile lists: per round, the critical tiles first (tile (p, q) of round r
     // holds block (I', J') of a pair of round r + 1 (cyclically) when I' is in
-    // pair p and J' in pair q), then the others in (p, q) order
-    std::vector<int> ht;
+    // pair p and J' in pair q), then the others in (p, q) order.  qmask of a
+    // critical tile: bit 2 h + c for each such block, h its row block within
+    // pair p (0: the pair's first block) and c its column block within pair q.
+    std::vector<int> ht, hq((size_t)p.R * p.H, 0);
     st.ncrit.assign(p.R, 0);
     {
-        std::vector<int> pos(p.N, 0);
-        std::vector<char> crit((size_t)p.H * p.H);
+        std::vector<int> pos(p.N, 0), half(p.N, 0);
+        std::vector<int> crit((size_t)p.H * p.H);
         for (int r = 0; r < p.R; ++r) {
             for (int k = 0; k < p.H; ++k) {
                 pos[hp[2 * ((size_t)r * p.H + k)]] = k;
                 pos[hp[2 * ((size_t)r * p.H + k) + 1]] = k;
+                half[hp[2 * ((size_t)r * p.H + k)]] = 0;
+                half[hp[2 * ((size_t)r * p.H + k) + 1]] = 1;
             }
-            std::fill(crit.begin(), crit.end(), 0);
+            std::fill(crit.begin(), crit.end(), -1);
             const int rn = (r + 1) % p.R;
             for (int k = 0; k < p.H; ++k) {
-                const int a = pos[hp[2 * ((size_t)rn * p.H + k)]], b = pos[hp[2 * ((size_t)rn * p.H + k) + 1]];
+                const int I = hp[2 * ((size_t)rn * p.H + k)], J = hp[2 * ((size_t)rn * p.H + k) + 1];
+                const int a = pos[I], b = pos[J];
+                if (a == b) continue;  // a block of a round-r pair: written by the subproblem kernel
                 const int lo = std::min(a, b), hi = std::max(a, b);
-                if (lo == hi || crit[(size_t)lo * p.H + hi]) continue;
-                crit[(size_t)lo * p.H + hi] = 1;
-                ht.push_back(lo);
-                ht.push_back(hi);
-                ++st.ncrit[r];
+                const int h = a < b ? half[I] : half[J], c = a < b ? half[J] : half[I];
+                int &ci = crit[(size_t)lo * p.H + hi];
+                if (ci < 0) {
+                    ci = st.ncrit[r]++;
+                    ht.push_back(lo);
+                    ht.push_back(hi);
+                }
+                hq[(size_t)r * p.H + ci] |= 1 << (2 * h + c);
             }
             for (int a = 0; a < p.H; ++a)
                 for (int b = a + 1; b < p.H; ++b)
-                    if (!crit[(size_t)a * p.H + b]) { ht.push_back(a); ht.push_back(b); }
+                    if (crit[(size_t)a * p.H + b] < 0) { ht.push_back(a); ht.push_back(b); }
         }
     }
     JX_HIP(hipMemcpyAsync(st.pairs, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, s));
     JX_HIP(hipMemcpyAsync(st.force, hf.data(), sizeof(int) * hf.size(), hipMemcpyHostToDevice, s));
     if (!ht.empty())
         JX_HIP(hipMemcpyAsync(st.tiles, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
+    JX_HIP(hipMemcpyAsync(st.qmask, hq.data(), sizeof(int) * hq.size(), hipMemcpyHostToDevice, s));
 
     // A -> upper block storage; Q = I or Q0 (then A <- Q0^T A Q0)
     double *A0 = p.refine ? reinterpret_cast<double *>(ws + p.off_a0) : nullptr;
@@ -571,23 +590,36 @@ int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *
     const size_t o_f = wb.add(sizeof(int) * H);
     const size_t o_p = wb.add(sizeof(int) * 2 * H);
     const size_t o_t = wb.add(sizeof(int) * (size_t)H * (H - 1) + sizeof(int));
+    const size_t o_m = wb.add(sizeof(int) * (size_t)H * (H - 1) / 2 + sizeof(int));
+    const size_t o_s = wb.add(sizeof(double) * 4 * (size_t)b * b * (H * (H - 1) / 2 + 1));
     buf.alloc(wb.total());
     double *ablk = reinterpret_cast<double *>(buf.ptr + o_ab);
     double *V = reinterpret_cast<double *>(buf.ptr + o_v);
     int *flags = reinterpret_cast<int *>(buf.ptr + o_f);
     int *pairs = reinterpret_cast<int *>(buf.ptr + o_p);
     int *tiles = reinterpret_cast<int *>(buf.ptr + o_t);
-    std::vector<int> ht;
+    int *qmask = reinterpret_cast<int *>(buf.ptr + o_m);
+    void *side = buf.ptr + o_s;
+    // The sweep's two-phase tile update: the first half of the tiles take
+    // the part of critical tiles (masks cycling through one block of either
+    // column half and two opposite blocks), then the bounded kernel does the
+    // rest of those and every other tile whole.
+    std::vector<int> ht, hq;
     for (int a = 0; a < H; ++a)
         for (int c = a + 1; c < H; ++c) { ht.push_back(a); ht.push_back(c); }
+    const int ntiles = (int)ht.size() / 2, nq = (ntiles + 1) / 2;
+    const int pattern[6] = {1, 2, 4, 8, 9, 6};
+    for (int i = 0; i < nq; ++i) hq.push_back(pattern[i % 6]);
     (void)npairs;
     JX_HIP(hipMemcpyAsync(pairs, hPairs, sizeof(int) * 2 * H, hipMemcpyHostToDevice, s));
     if (!ht.empty()) JX_HIP(hipMemcpyAsync(tiles, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
+    if (!hq.empty()) JX_HIP(hipMemcpyAsync(qmask, hq.data(), sizeof(int) * hq.size(), hipMemcpyHostToDevice, s));
     JX_HIP(hipMemsetAsync(flags, 0, sizeof(int) * H, s));
     launch_pack_sym(n, n, b, dA, n, 'U', ablk, s);
     launch_vperm_from_colmajor(H, m2, dV, V, s);
     launch_write_pair_blocks(H, b, pairs, dD, ablk, s);
-    launch_update_a(b, H, pairs, ablk, V, flags, tiles, (int)ht.size() / 2, s);
+    launch_update_a(b, H, pairs, ablk, V, flags, tiles, nq, s, UA_QUAD, qmask, nq, side);
+    launch_update_a(b, H, pairs, ablk, V, flags, tiles, ntiles, s, 1, qmask, nq, side);
     if (dQ) launch_update_q(b, H, pairs, dQ, n, n, V, flags, s);
     launch_unpack_sym(n, b, ablk, dA, n, s);
     JX_HIP(hipStreamSynchronize(s));

@@ -172,11 +172,15 @@ size_t batched_lds_bytes(int bs, int m2); // dynamic LDS of the class kernel
 
 // Fused two-sided update of the off-diagonal pair tiles of one round:
 // A[p,q] <- V_p^T A[p,q] V_q for p < q (pair indices of the round).
-// reserve > 0: on at most (CUs - reserve) CUs; UA_LATENCY: one workgroup of
-// eight waves per tile (for few tiles that others wait for); 0: four waves.
-constexpr int UA_LATENCY = -1;
+// reserve > 0: on at most (CUs - reserve) CUs.  UA_QUAD: one workgroup per
+// tile, only the blocks qmask[i] of tile i (bit 2 h + c: row block h of pair
+// p, column block c of pair q), their originals saved to side (4 blocks per
+// tile).  A bounded launch with nq > 0 then does the rest of its first nq
+// tiles (same qmask and side) and the other tiles whole.
+constexpr int UA_QUAD = -2;
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
-                     const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve = 0);
+                     const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve = 0,
+                     const int *qmask = nullptr, int nq = 0, void *side = nullptr);
 // Gram blocks of the one-sided SVD: ahat[p] = G(:, [I,J])^T G(:, [I,J]) over the
 // first m_rows rows (nchunks equal row chunks, partial sums added in order).
 void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, int m_rows, int nchunks,
@@ -194,7 +198,8 @@ void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, in
                      const double *vhat, const int *flags, hipStream_t s, int reserve = 0);
 // FP32 versions (FP32 storage, FP32 MFMA with FP32 accumulation, V_hat in vperm32 order).
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
-                       const int *tiles, int ntiles, hipStream_t s, int reserve = 0);
+                       const int *tiles, int ntiles, hipStream_t s, int reserve = 0, const int *qmask = nullptr,
+                       int nq = 0, void *side = nullptr);
 void launch_update_q32(int b, int npairs, const int *pairs, float *Q, int ldq, int n_rows, const float *vhat,
                        const int *flags, hipStream_t s, int reserve = 0);
 

@@ -27,11 +27,13 @@ namespace {
 
 constexpr int KC = 16;  // X chunk width (columns)
 
-template <int B, int NTH = 256>
+// HALF: T is computed for one column half of the tile only (the columns of
+// one block), which is all that one output block needs.
+template <int B, int NTH = 256, bool HALF = false>
 struct UaCfg {
     static constexpr int M2 = 2 * B;      // tile order
     static constexpr int RT = M2 / 16;    // 16-row tiles
-    static constexpr int WW = M2 / (NTH / 64);  // columns per wave
+    static constexpr int WW = (HALF ? B : M2) / (NTH / 64);  // columns per wave
     static constexpr int CT = WW / 16;    // 16-column tiles per wave
     static constexpr int XLD = M2 + 1;    // LDS stride of an X chunk [k][row]
     static constexpr int OLD = B + 1;     // LDS stride of an output half [col][row]
@@ -40,29 +42,44 @@ struct UaCfg {
     static constexpr size_t XS_DOUBLES = 2 * (size_t)KC * XLD;
     static constexpr size_t OS_DOUBLES = (size_t)M2 * OLD;
     static constexpr size_t LDS_BYTES = sizeof(double) * (XS_DOUBLES > OS_DOUBLES ? XS_DOUBLES : OS_DOUBLES);
+    static_assert(WW % 16 == 0, "a wave owns whole 16-column tiles");
 };
 
-// Fetch the PER values of X chunk `ch` (columns ch*KC .. +KC-1 of the tile)
-// that this thread stages.  Rows 0..B-1 come from block row Rr[0], rows
-// B..2B-1 from Rr[1]; the chunk lies in block column Cc.
+// Which blocks of a tile are read from and written to where.  Quadrant
+// (h, c) = block (row block h of pair p, column block c of pair q) has bit
+// 2 h + c.  A tile's blocks that the next round's subproblems read (its
+// "critical" quadrants) are computed first and alone; the rest of the tile
+// later, from the saved originals of those blocks:
+//   wmask  quadrants written back (the others are computed or not, but left)
+//   rmask  quadrants whose input block comes from side + quad B^2, not ablk
+//   save   before a quadrant is written, its original goes to side + quad B^2
+// (side holds four blocks of B x B, each stored as its block is in ablk).
+template <class T>
+struct TileIO {
+    int wmask = 15, rmask = 0;
+    bool save = false;
+    T *side = nullptr;
+};
+
+// Fetch the PER values of X chunk `ch` (columns c0 .. c0+KC-1 of one block
+// column) that this thread stages.  Rows h B .. h B + B-1 come from the block
+// at src[h], stored column-major as block (row, column) when tr[h] is false
+// and as its mirror (column, row) when tr[h] is true.
 template <int B, class T, int NTH>
-__device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int Cc, int c0, T *reg, int tid) {
+__device__ __forceinline__ void fetch_chunk(const T *const src[2], const bool tr[2], int c0, T *reg, int tid) {
     using U = UaCfg<B, NTH>;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int R = h ? Rr[1] : Rr[0];
 #pragma unroll
         for (int m = 0; m < U::PER / 2; ++m) {
             const int e = tid + NTH * m;  // 0 .. B*KC-1
             T v;
-            if (R < Cc) {
-                const T *src = ablk + ublk(R, Cc) * (size_t)(B * B);
+            if (!tr[h]) {
                 const int rl = e % B, cl = e / B;
-                v = src[(c0 + cl) * B + rl];
+                v = src[h][(c0 + cl) * B + rl];
             } else {
-                const T *src = ablk + ublk(Cc, R) * (size_t)(B * B);
                 const int cl = e % KC, rl = e / KC;
-                v = src[rl * B + c0 + cl];
+                v = src[h][rl * B + c0 + cl];
             }
             reg[h * (U::PER / 2) + m] = v;
         }
@@ -70,16 +87,15 @@ __device__ __forceinline__ void fetch_chunk(const T *ablk, const int Rr[2], int 
 }
 
 template <int B, class T, int NTH>
-__device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, const T *reg, int tid) {
+__device__ __forceinline__ void stage_chunk(T *xs, const bool tr[2], const T *reg, int tid) {
     using U = UaCfg<B, NTH>;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int R = h ? Rr[1] : Rr[0];
 #pragma unroll
         for (int m = 0; m < U::PER / 2; ++m) {
             const int e = tid + NTH * m;
             int rl, cl;
-            if (R < Cc) { rl = e % B; cl = e / B; }
+            if (!tr[h]) { rl = e % B; cl = e / B; }
             else { cl = e % KC; rl = e / KC; }
             xs[cl * U::XLD + h * B + rl] = reg[h * (U::PER / 2) + m];
         }
@@ -87,14 +103,15 @@ __device__ __forceinline__ void stage_chunk(T *xs, const int Rr[2], int Cc, cons
 }
 
 // Tile (p, q) by NTH threads t = 0 .. NTH-1 (NTH / 64 waves, each owning
-// 2b / (NTH / 64) columns of T) with `lds` (U::LDS_BYTES) of their own.
+// WW columns of T) with `lds` (U::LDS_BYTES) of their own.  HALF: T only for
+// column half `cb` (then io.wmask names quadrants of that half only).
 // active false (no tile, or both rotations skipped): no work, but every
 // barrier is still taken, so two halves of one workgroup stay in step.
-template <int B, class T, int NTH = 256>
+template <int B, class T, int NTH = 256, bool HALF = false>
 __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__restrict__ ablk,
                                         const T *__restrict__ vhat, int p, int q, bool idp, bool idq, int tid,
-                                        T *lds, bool active) {
-    using U = UaCfg<B, NTH>;
+                                        T *lds, bool active, const TileIO<T> &io, int cb = 0) {
+    using U = UaCfg<B, NTH, HALF>;
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int M2 = U::M2, RT = U::RT, CT = U::CT, WW = U::WW;
@@ -105,7 +122,27 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
 
     const int lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
-    const int wc0 = w * WW;
+    const int wc0 = (HALF ? cb * B : 0) + w * WW;
+
+    // input block of quadrant (h, c): ablk, or its saved original
+    auto src_of = [&](int h, int c) -> const T * {
+        if ((io.rmask >> (2 * h + c)) & 1) return io.side + (size_t)(2 * h + c) * B * B;
+        const int R = Rr[h], C = Cq[c];
+        return ablk + ublk(R < C ? R : C, R < C ? C : R) * (size_t)(B * B);
+    };
+    // chunk k0's column block c: its two row blocks (pointers formed at each
+    // fetch, not kept: the bounded kernel has no registers to spare)
+    auto fetch = [&](int k0, T *reg) {
+        const int c = k0 / B;
+        const T *src[2] = {src_of(0, c), src_of(1, c)};
+        const bool tr[2] = {Rr[0] > Cq[c], Rr[1] > Cq[c]};
+        fetch_chunk<B, T, NTH>(src, tr, k0 % B, reg, tid);
+    };
+    auto stage = [&](int k0, T *xs, const T *reg) {
+        const int c = k0 / B;
+        const bool tr[2] = {Rr[0] > Cq[c], Rr[1] > Cq[c]};
+        stage_chunk<B, T, NTH>(xs, tr, reg, tid);
+    };
 
     acc_t acc[RT][CT];
 #pragma unroll
@@ -128,12 +165,12 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
     constexpr bool PF = CT == 1;
     T bnext[KC / 4];
     if (active) {
-        fetch_chunk<B, T, NTH>(ablk, Rr, Cq[0], 0, reg, tid);
+        fetch(0, reg);
         if constexpr (PF) {
 #pragma unroll
             for (int st = 0; st < KC / 4; ++st) bnext[st] = vqk(0, st, 0);
         }
-        stage_chunk<B, T, NTH>(lds, Rr, Cq[0], reg, tid);
+        stage(0, lds, reg);
     }
     __syncthreads();
     for (int ch = 0; ch < U::NCH; ++ch) {
@@ -143,7 +180,7 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
         for (int st = 0; st < KC / 4; ++st) bcur[st] = bnext[st];
         if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            fetch_chunk<B, T, NTH>(ablk, Rr, k0 < B ? Cq[0] : Cq[1], k0 % B, reg, tid);
+            fetch(k0, reg);
             if constexpr (PF) {
 #pragma unroll
                 for (int st = 0; st < KC / 4; ++st) bnext[st] = vqk(ch + 1, st, 0);
@@ -176,7 +213,7 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
         }
         if (active && ch + 1 < U::NCH) {
             const int k0 = (ch + 1) * KC;
-            stage_chunk<B, T, NTH>(lds + (size_t)((ch + 1) & 1) * KC * U::XLD, Rr, k0 < B ? Cq[0] : Cq[1], reg, tid);
+            stage(k0, lds + (size_t)((ch + 1) & 1) * KC * U::XLD, reg);
         }
         __syncthreads();
     }
@@ -188,8 +225,9 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         T *os = lds;
+        const bool hact = active && ((io.wmask >> (2 * h)) & 3) != 0;  // a block of this row half is written
 #pragma unroll 1
-        for (int ot = 0; ot < (active ? RT / 2 : 0); ++ot) {
+        for (int ot = 0; ot < (hact ? RT / 2 : 0); ++ot) {
             acc_t o[CT];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) o[ct] = acc_t{0, 0, 0, 0};
@@ -236,70 +274,96 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
         __syncthreads();
         const int R = h ? Rr[1] : Rr[0];
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            const int Cc = cb ? Cq[1] : Cq[0];
-            if (!active) {
-            } else if (R < Cc) {
-                T *dst = ablk + ublk(R, Cc) * (size_t)(B * B);
-                for (int e = tid; e < B * B; e += NTH) {
-                    const int rl = e % B, cl = e / B;
-                    dst[e] = os[(cb * B + cl) * U::OLD + rl];
-                }
-            } else {
-                T *dst = ablk + ublk(Cc, R) * (size_t)(B * B);
-                for (int e = tid; e < B * B; e += NTH) {
-                    const int cl = e % B, rl = e / B;  // stored (Cc, R): element (cl, rl)
-                    dst[e] = os[(cb * B + cl) * U::OLD + rl];
-                }
+        for (int c = 0; c < 2; ++c) {
+            const int Cc = c ? Cq[1] : Cq[0];
+            const int quad = 2 * h + c;
+            if (!hact || !((io.wmask >> quad) & 1)) continue;
+            T *dst = ablk + ublk(R < Cc ? R : Cc, R < Cc ? Cc : R) * (size_t)(B * B);
+            T *sv = io.save ? io.side + (size_t)quad * B * B : nullptr;
+            // every read of the tile's inputs ended at GEMM 1's last barrier
+            for (int e = tid; e < B * B; e += NTH) {
+                int rl, cl;
+                if (R < Cc) { rl = e % B; cl = e / B; }
+                else { cl = e % B; rl = e / B; }  // stored (Cc, R): element (cl, rl)
+                if (sv) sv[e] = dst[e];
+                dst[e] = os[(c * B + cl) * U::OLD + rl];
             }
         }
         __syncthreads();
     }
 }
 
-// One tile per workgroup: tile i = (tiles[2 i], tiles[2 i + 1]).
+// Only the critical quadrants qmask[i] of tile i, one tile per workgroup:
+// their original blocks are saved to side + 4 i B^2 (+ quad B^2) and the new
+// ones written in place.  A mask within one column half takes T for that half
+// only (3/8 of a tile's products for one block); B = 32 always takes all of T.
 template <int B, class T>
-__global__ void __launch_bounds__(256, 2)
-k_update_a(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
-           const int *__restrict__ flags, const int *__restrict__ tiles) {
+__global__ void __launch_bounds__(256, 1)
+k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
+                const int *__restrict__ flags, const int *__restrict__ tiles, const int *__restrict__ qmask,
+                T *__restrict__ side) {
     extern __shared__ double lds_raw[];
-    const int p = tiles[2 * blockIdx.x], q = tiles[2 * blockIdx.x + 1];
+    const int i = blockIdx.x;
+    const int p = tiles[2 * i], q = tiles[2 * i + 1];
     const bool idp = flags[p] != 0, idq = flags[q] != 0;
-    if (idp && idq) return;
-    ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, reinterpret_cast<T *>(lds_raw), true);
+    if (idp && idq) return;  // the tile does not change (and its rest is skipped the same way)
+    TileIO<T> io;
+    io.wmask = qmask[i] & 15;
+    io.save = true;
+    io.side = side + (size_t)4 * i * B * B;
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    if constexpr (B == 64) {
+        if ((io.wmask & 10) == 0 || (io.wmask & 5) == 0) {  // one column half (bits 1, 4: column 0; 2, 8: column 1)
+            ua_tile<B, T, 256, true>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io,
+                                     (io.wmask & 5) ? 0 : 1);
+            return;
+        }
+    }
+    ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io);
 }
 
-// One tile per workgroup of eight waves: the tiles that the next round's
-// subproblems wait for, where latency matters more than throughput.
-template <int B, class T>
-__global__ void __launch_bounds__(512, 1)
-k_update_a8(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
-            const int *__restrict__ flags, const int *__restrict__ tiles) {
-    extern __shared__ double lds_raw[];
-    const int p = tiles[2 * blockIdx.x], q = tiles[2 * blockIdx.x + 1];
-    const bool idp = flags[p] != 0, idq = flags[q] != 0;
-    if (idp && idq) return;
-    ua_tile<B, T, 512>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, reinterpret_cast<T *>(lds_raw), true);
-}
-
-// The same tiles on a bounded set of CUs (as k_update_q_bounded): 512 threads,
-// two 256-thread halves with their own LDS, each one tile at a time (tile
-// 2 (k gridDim + blockIdx) + half); the LDS request keeps one workgroup per
-// CU, so a grid of CUs - reserve leaves `reserve` CUs free.
+// The same tiles on a bounded set of CUs (as k_update_q_bounded): 512 threads
+// and an LDS request that keeps one workgroup per CU, so a grid of
+// CUs - reserve leaves `reserve` CUs free.  b = 64: one tile at a time on all
+// eight waves (one 16-column tile of T each), tile k gridDim + blockIdx;
+// b = 32: two 256-thread halves with their own LDS, each one tile at a time
+// (tile 2 (k gridDim + blockIdx) + half).  The first nq tiles are critical
+// tiles whose quadrants qmask[i] were done by k_update_a_crit: those are read
+// from their saved originals and not written.
 template <int B, class T>
 __global__ void __launch_bounds__(512, 1)
 k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
-                   const int *__restrict__ flags, const int *__restrict__ tiles, int ntiles) {
-    using U = UaCfg<B>;
+                   const int *__restrict__ flags, const int *__restrict__ tiles, int ntiles,
+                   const int *__restrict__ qmask, int nq, T *__restrict__ side) {
     extern __shared__ double lds_raw[];
-    const int half = threadIdx.x >> 8, t = threadIdx.x & 255;
-    T *lds = reinterpret_cast<T *>(reinterpret_cast<char *>(lds_raw) + half * U::LDS_BYTES);
-    for (int i0 = 2 * blockIdx.x; i0 < ntiles; i0 += 2 * gridDim.x) {
-        const int i = i0 + half;
-        const int p = i < ntiles ? tiles[2 * i] : 0, q = i < ntiles ? tiles[2 * i + 1] : 1;
-        const bool idp = flags[p] != 0, idq = flags[q] != 0;
-        const bool active = i < ntiles && !(idp && idq);
-        ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, t, lds, active);
+    auto tile_io = [&](int i) {
+        TileIO<T> io;
+        if (i < nq) {
+            io.rmask = qmask[i] & 15;
+            io.wmask = 15 & ~io.rmask;
+            io.side = side + (size_t)4 * i * B * B;
+        }
+        return io;
+    };
+    if constexpr (B == 64) {
+        T *lds = reinterpret_cast<T *>(lds_raw);
+        for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+            const int p = tiles[2 * i], q = tiles[2 * i + 1];
+            const bool idp = flags[p] != 0, idq = flags[q] != 0;
+            if (idp && idq) continue;  // uniform over the workgroup
+            ua_tile<B, T, 512>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, tile_io(i));
+        }
+    } else {
+        using U = UaCfg<B>;
+        const int half = threadIdx.x >> 8, t = threadIdx.x & 255;
+        T *lds = reinterpret_cast<T *>(reinterpret_cast<char *>(lds_raw) + half * U::LDS_BYTES);
+        for (int i0 = 2 * blockIdx.x; i0 < ntiles; i0 += 2 * gridDim.x) {
+            const int i = i0 + half;
+            const int p = i < ntiles ? tiles[2 * i] : 0, q = i < ntiles ? tiles[2 * i + 1] : 1;
+            const bool idp = flags[p] != 0, idq = flags[q] != 0;
+            const bool active = i < ntiles && !(idp && idq);
+            ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, t, lds, active, tile_io(i));
+        }
     }
 }
 
@@ -409,67 +473,66 @@ k_update_q_bounded(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
 }
 constexpr size_t UQ_BOUNDED_LDS = 81 * 1024;  // > half of the 160 KB LDS: one workgroup per CU
 
-template <int B, class T>
-void launch_ua_t(int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
-                 int ntiles, hipStream_t s) {
-    using U = UaCfg<B>;
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a<B, T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::LDS_BYTES));
-        attr = true;
-    }
-    (void)npairs;
-    hipLaunchKernelGGL((k_update_a<B, T>), dim3(ntiles), dim3(256), U::LDS_BYTES, s, pairs, ablk, vhat, flags,
-                       tiles);
-    JX_LAUNCHED();
-}
-
 int device_cus();
 
 template <int B, class T>
 void launch_ua_bounded(const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles, int ntiles,
-                       int reserve, hipStream_t s) {
-    using U = UaCfg<B>;
-    // two halves' LDS, and more than half a CU's in any case: one workgroup per CU
-    const size_t lds = std::max<size_t>(2 * U::LDS_BYTES, 81 * 1024);
+                       int reserve, const int *qmask, int nq, T *side, hipStream_t s) {
+    // one tile's LDS (b = 64) or two halves' (b = 32), and more than half a
+    // CU's in any case: one workgroup per CU
+    size_t need = 2 * UaCfg<B>::LDS_BYTES;
+    if constexpr (B == 64) need = UaCfg<B, 512>::LDS_BYTES;
+    const size_t lds = std::max<size_t>(need, 81 * 1024);
     static bool attr = false;
     if (!attr) {
         JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a_bounded<B, T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = true;
     }
-    const int grid = std::max(1, std::min(device_cus() - reserve, (ntiles + 1) / 2));
+    const int grid = std::max(1, std::min(device_cus() - reserve, B == 64 ? ntiles : (ntiles + 1) / 2));
     hipLaunchKernelGGL((k_update_a_bounded<B, T>), dim3(grid), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
-                       ntiles);
+                       ntiles, qmask, nq, side);
+    JX_LAUNCHED();
+}
+
+template <int B, class T>
+void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles, int ntiles,
+                    const int *qmask, T *side, hipStream_t s) {
+    using U = UaCfg<B>;
+    // more than half a CU's LDS: no CU shared with the bounded kernels on the
+    // other stream, nor with a second critical tile
+    const size_t lds = std::max<size_t>(U::LDS_BYTES, 81 * 1024);
+    static bool attr = false;
+    if (!attr) {
+        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a_crit<B, T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles), dim3(256), lds, s, pairs, ablk, vhat, flags, tiles,
+                       qmask, side);
     JX_LAUNCHED();
 }
 
 template <class T>
 void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
-               int ntiles, int reserve, hipStream_t s) {
+               int ntiles, int reserve, const int *qmask, int nq, T *side, hipStream_t s) {
     if (ntiles <= 0) return;
     if (b != 64 && b != 32) { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
-    if (reserve > 0) {
-        if (b == 64) launch_ua_bounded<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
-        else launch_ua_bounded<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
+    if ((reserve == UA_QUAD || nq > 0) && (!qmask || !side || nq > ntiles)) {
+        set_error("update kernel: quadrant split without masks or side blocks");
+        throw HipFail{hipErrorInvalidValue};
+    }
+    if (reserve == UA_QUAD) {
+        if (b == 64) launch_ua_crit<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, qmask, side, s);
+        else launch_ua_crit<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, qmask, side, s);
         return;
     }
-    if (reserve == UA_LATENCY && b == 64) {  // eight waves per tile (b = 32 keeps four: 16 columns each)
-        using U = UaCfg<64, 512>;
-        static bool attr = false;
-        if (!attr) {
-            JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a8<64, T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)U::LDS_BYTES));
-            attr = true;
-        }
-        hipLaunchKernelGGL((k_update_a8<64, T>), dim3(ntiles), dim3(512), U::LDS_BYTES, s, pairs, ablk, vhat, flags,
-                           tiles);
-        JX_LAUNCHED();
-        return;
+    if (reserve <= 0) {
+        set_error("update kernel: reserve must be positive (bounded kernel) or UA_QUAD");
+        throw HipFail{hipErrorInvalidValue};
     }
-    if (b == 64) launch_ua_t<64, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
-    else launch_ua_t<32, T>(npairs, pairs, ablk, vhat, flags, tiles, ntiles, s);
+    if (b == 64) launch_ua_bounded<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq, side, s);
+    else launch_ua_bounded<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq, side, s);
 }
 
 // CUs of the current device (cached per device).
@@ -521,12 +584,16 @@ void launch_uq(int b, int npairs, const int *pairs, T *Q, int ldq, int n_rows, c
 }  // namespace
 
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
-                     const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve) {
-    launch_ua<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
+                     const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve,
+                     const int *qmask, int nq, void *side) {
+    launch_ua<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq,
+                      static_cast<double *>(side), s);
 }
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
-                       const int *tiles, int ntiles, hipStream_t s, int reserve) {
-    launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, s);
+                       const int *tiles, int ntiles, hipStream_t s, int reserve, const int *qmask, int nq,
+                       void *side) {
+    launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq,
+                     static_cast<float *>(side), s);
 }
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s, int reserve) {
