@@ -115,6 +115,9 @@ void padded_rounds_pub(int N, int ordering, std::vector<int> &pairs, std::vector
 
 static int default_block(int n) { return n > 512 ? 64 : 32; }
 
+// V_hat / flag buffers of consecutive rounds (see EigState)
+constexpr int NVBUF = 3;
+
 EigPlan plan_eig(int n, const jacobi_opts &o) {
     EigPlan p{};
     p.n = n;
@@ -138,10 +141,10 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     if (p.mixed) {
         p.off_ablk32 = wb.add(sizeof(float) * nb * p.b * p.b);
         p.off_q32 = wb.add(sizeof(float) * npad * npad);
-        p.off_v32 = wb.add(sizeof(float) * 2 * p.H * m2sq);
+        p.off_v32 = wb.add(sizeof(float) * NVBUF * p.H * m2sq);
     }
-    p.off_v = wb.add(sizeof(double) * 2 * p.H * m2sq);
-    p.off_flags = wb.add(sizeof(int) * 2 * p.H);
+    p.off_v = wb.add(sizeof(double) * NVBUF * p.H * m2sq);
+    p.off_flags = wb.add(sizeof(int) * NVBUF * p.H);
     p.off_pairs = wb.add(sizeof(int) * 2 * (size_t)p.R * p.H);
     p.off_force = wb.add(sizeof(int) * (size_t)p.R * p.H);
     p.off_tiles = wb.add(sizeof(int) * (size_t)p.R * p.H * (p.H - 1));  // per round, critical tiles first
@@ -177,12 +180,16 @@ struct EigState {
     int inner;
     double tol;
     int any_force;
-    // second stream for the Q updates, which overlap the next rounds'
-    // subproblem solves (the V_hat / flag buffers are double-buffered)
+    // second stream for the rest of the tile updates and the Q updates,
+    // which overlap the next round's subproblem solves.  The V_hat / flag
+    // buffers rotate over NVBUF = 3 rounds: round r + 3's subproblem kernel
+    // (which rewrites buffer r mod 3) follows round r + 2's critical tiles on
+    // s, which wait for round r + 1's rest tiles on sq, which follow round r's
+    // Q update on sq; so no round reuses a buffer that is still read.
     hipStream_t sq = nullptr;
-    hipEvent_t ev_v[2] = {nullptr, nullptr};   // V_hat(r) ready (on s)
-    hipEvent_t ev_q[2] = {nullptr, nullptr};   // Q update of the round using buffer i done (on sq)
-    bool q_pending[2] = {false, false};
+    hipEvent_t ev_v = nullptr;   // critical tiles of the last round done (on s)
+    hipEvent_t ev_q = nullptr;   // Q update of the last round done (on sq)
+    bool q_pending = false;
     // per round: the first ncrit[r] tiles of its list hold the blocks the next
     // round's subproblems read (qmask: which of their four blocks); those
     // blocks are done first, the rest of every tile on sq beside the next
@@ -194,9 +201,9 @@ struct EigState {
     int *h_flaglog = nullptr;
     int flog_cap = 0, flog_count = 0, flog_base = 0;
 
-    double *Vbuf(int r) const { return V + (size_t)(r & 1) * p.H * (2 * p.b) * (2 * p.b); }
-    float *Vbuf32(int r) const { return V32 + (size_t)(r & 1) * p.H * (2 * p.b) * (2 * p.b); }
-    int *Fbuf(int r) const { return flags + (size_t)(r & 1) * p.H; }
+    double *Vbuf(int r) const { return V + (size_t)(r % NVBUF) * p.H * (2 * p.b) * (2 * p.b); }
+    float *Vbuf32(int r) const { return V32 + (size_t)(r % NVBUF) * p.H * (2 * p.b) * (2 * p.b); }
+    int *Fbuf(int r) const { return flags + (size_t)(r % NVBUF) * p.H; }
 
     // {Xi(A)^2, sum of squared diagonal}
     void norms(double &off2, double &dia2) {
@@ -234,11 +241,6 @@ struct EigState {
                 a.ablk32 = ablk32;
                 a.vout32 = Vbuf32(r);
             }
-            const int buf = r & 1;
-            if (sq && q_pending[buf]) {  // the Q update still reading this buffer
-                JX_HIP(hipStreamWaitEvent(s, ev_q[buf], 0));
-                q_pending[buf] = false;
-            }
             // flags of this round land in the profiler's flag log at `slot`
             const int slot_next = (h_flaglog && flog_count < flog_cap) ? flog_base + flog_count * p.H : -1;
             {
@@ -272,8 +274,8 @@ struct EigState {
                     if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, side);
                     else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, side);
                 }
-                JX_HIP(hipEventRecord(ev_v[buf], s));
-                JX_HIP(hipStreamWaitEvent(sq, ev_v[buf], 0));
+                JX_HIP(hipEventRecord(ev_v, s));
+                JX_HIP(hipStreamWaitEvent(sq, ev_v, 0));
                 {
                     ProfScope ps(PROF_UPDATE_A_REST, sq, 1.0, 0.0, slot, p.H, m2);
                     if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
@@ -292,9 +294,9 @@ struct EigState {
                     else launch_update_q(p.b, p.H, pr, Q, p.npad, p.npad, Vbuf(r), Fbuf(r), qs, reserve);
                 }
             }
-            if (sq) {  // V_hat / flag buffer `buf` free once sq is past this round
-                JX_HIP(hipEventRecord(ev_q[buf], sq));
-                q_pending[buf] = true;
+            if (sq && p.need_q) {
+                JX_HIP(hipEventRecord(ev_q, sq));
+                q_pending = true;
             }
         }
         // A and Q complete before anyone reads them (norms, refinement, output)
@@ -302,27 +304,22 @@ struct EigState {
             JX_HIP(hipStreamWaitEvent(s, ev_rest, 0));
             rest_pending = false;
         }
-        for (int i = 0; i < 2; ++i)
-            if (sq && q_pending[i]) {
-                JX_HIP(hipStreamWaitEvent(s, ev_q[i], 0));
-                q_pending[i] = false;
-            }
+        if (q_pending) {
+            JX_HIP(hipStreamWaitEvent(s, ev_q, 0));
+            q_pending = false;
+        }
     }
 
     void make_streams() {
         JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
-        for (int i = 0; i < 2; ++i) {
-            JX_HIP(hipEventCreateWithFlags(&ev_v[i], hipEventDisableTiming));
-            JX_HIP(hipEventCreateWithFlags(&ev_q[i], hipEventDisableTiming));
-        }
+        JX_HIP(hipEventCreateWithFlags(&ev_v, hipEventDisableTiming));
+        JX_HIP(hipEventCreateWithFlags(&ev_q, hipEventDisableTiming));
         JX_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
     }
     ~EigState() {
         if (sq) (void)hipStreamSynchronize(sq);
-        for (int i = 0; i < 2; ++i) {
-            if (ev_v[i]) (void)hipEventDestroy(ev_v[i]);
-            if (ev_q[i]) (void)hipEventDestroy(ev_q[i]);
-        }
+        if (ev_v) (void)hipEventDestroy(ev_v);
+        if (ev_q) (void)hipEventDestroy(ev_q);
         if (ev_rest) (void)hipEventDestroy(ev_rest);
         if (sq) (void)hipStreamDestroy(sq);
     }

@@ -293,10 +293,126 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
     }
 }
 
+// One block of tile (p, q) for b = 64: row half h, column half c, by 256
+// threads (wave w owns T's 16 columns 64 c + 16 w ..), latency first.  The
+// whole input tile goes to LDS with one round of global loads (64 values per
+// thread, plus the wave's 32 V_q operands), then GEMM 1 (32 k-steps x 8 row
+// tiles) and GEMM 2 for row half h only (V_p operands one output tile ahead).
+// The original block is saved to `side` and the new one written in place.
+// `lds` holds 128 x 129 values.
+template <class T>
+__device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__restrict__ ablk,
+                                           const T *__restrict__ vhat, int p, int q, bool idp, bool idq, int h,
+                                           int c, T *__restrict__ side, T *lds) {
+    using MT = MfmaTraits<T>;
+    typedef typename MT::acc_t acc_t;
+    constexpr int B = 64, M2 = 128, XLD = M2 + 1, NTH = 256, PB = B * B / NTH;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, x = lane & 15;
+    const int Rr[2] = {pairs[2 * p], pairs[2 * p + 1]};
+    const int Cq[2] = {pairs[2 * q], pairs[2 * q + 1]};
+    const T *vp = vhat + (size_t)p * M2 * M2;
+    const T *vq = vhat + (size_t)q * M2 * M2;
+    auto blk = [&](int hh, int cc) {
+        const int R = Rr[hh], C = Cq[cc];
+        return ablk + ublk(R < C ? R : C, R < C ? C : R) * (size_t)(B * B);
+    };
+
+    // every load at once: the four blocks (contiguous per thread) and V_q
+    T xr[4][PB];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+        const T *src = blk(bb >> 1, bb & 1);
+#pragma unroll
+        for (int m = 0; m < PB; ++m) xr[bb][m] = src[tid + NTH * m];
+    }
+    const int col = 64 * c + 16 * w + x;  // this lane's column of T
+    T bq[M2 / 4];
+#pragma unroll
+    for (int s = 0; s < M2 / 4; ++s) {
+        const int kg = 16 * (s >> 2) + MT::kstep(s & 3, g);
+        bq[s] = idq ? (kg == col ? T(1) : T(0)) : vq[MT::vidx(kg, col, M2)];
+    }
+    // X(row, k) at lds[k XLD + row]: block (hh, cc) holds rows 64 hh .., k 64 cc ..
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+        const int hh = bb >> 1, cc = bb & 1;
+        const bool tr = Rr[hh] > Cq[cc];  // stored as the mirror (column block, row block)
+#pragma unroll
+        for (int m = 0; m < PB; ++m) {
+            const int e = tid + NTH * m;
+            const int rl = tr ? e / B : e % B, kl = tr ? e % B : e / B;
+            lds[(64 * cc + kl) * XLD + 64 * hh + rl] = xr[bb][m];
+        }
+    }
+    // V_p operands of output row tile ot (row 64 h + 16 ot + x of V_p^T T):
+    // step (rt, s) contracts row 16 rt + rrow(g, s) of T
+    auto vpk = [&](int ot, int rt, int s) {
+        const int orow = 64 * h + 16 * ot + x, k = 16 * rt + MT::rrow(g, s);
+        return idp ? (k == orow ? T(1) : T(0)) : vp[MT::vidx(k, orow, M2)];
+    };
+    T af[M2 / 16][4];
+#pragma unroll
+    for (int rt = 0; rt < M2 / 16; ++rt)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) af[rt][s4] = vpk(0, rt, s4);
+    __syncthreads();
+
+    // GEMM 1: T(:, col tile) = X V_q(:, col tile)
+    acc_t acc[M2 / 16];
+#pragma unroll
+    for (int rt = 0; rt < M2 / 16; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < M2 / 4; ++s) {
+        const int kl = 16 * (s >> 2) + MT::kstep(s & 3, g);
+#pragma unroll
+        for (int rt = 0; rt < M2 / 16; ++rt) acc[rt] = MT::mma(lds[kl * XLD + 16 * rt + x], bq[s], acc[rt]);
+    }
+    __syncthreads();  // X no longer read: the output block takes its place
+
+    // GEMM 2: out(:, col tile) = V_p(:, row half h)^T T, one 16-row tile at a time
+    T *os = lds;  // [column 0 .. 63][row 0 .. 63], stride B + 1
+#pragma unroll
+    for (int ot = 0; ot < B / 16; ++ot) {
+        T cur[M2 / 16][4];
+#pragma unroll
+        for (int rt = 0; rt < M2 / 16; ++rt)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) cur[rt][s4] = af[rt][s4];
+        if (ot + 1 < B / 16) {
+#pragma unroll
+            for (int rt = 0; rt < M2 / 16; ++rt)
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) af[rt][s4] = vpk(ot + 1, rt, s4);
+        }
+        acc_t o = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int rt = 0; rt < M2 / 16; ++rt)
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) o = MT::mma(cur[rt][s4], acc[rt][s4], o);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) os[(16 * w + x) * (B + 1) + 16 * ot + MT::rrow(g, v)] = o[v];
+    }
+    __syncthreads();
+
+    // block (Rr[h], Cq[c]): original to side, new value in place
+    const int R = Rr[h], C = Cq[c];
+    T *dst = blk(h, c);
+    T *sv = side + (size_t)(2 * h + c) * B * B;
+#pragma unroll
+    for (int m = 0; m < PB; ++m) {
+        const int e = tid + NTH * m;
+        const int rl = R < C ? e % B : e / B, cl = R < C ? e / B : e % B;  // element (rl, cl) of block (R, C)
+        sv[e] = dst[e];
+        dst[e] = os[cl * (B + 1) + rl];
+    }
+}
+
 // Only the critical quadrants qmask[i] of tile i, one tile per workgroup:
 // their original blocks are saved to side + 4 i B^2 (+ quad B^2) and the new
-// ones written in place.  A mask within one column half takes T for that half
-// only (3/8 of a tile's products for one block); B = 32 always takes all of T.
+// ones written in place.  One block (b = 64) takes T for its column half only
+// and V_p^T T for its row half only: 3/8 of a tile's products.  Two blocks,
+// and b = 32, take all of T.
 template <int B, class T>
 __global__ void __launch_bounds__(256, 1)
 k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
@@ -313,9 +429,10 @@ k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__
     io.side = side + (size_t)4 * i * B * B;
     T *lds = reinterpret_cast<T *>(lds_raw);
     if constexpr (B == 64) {
-        if ((io.wmask & 10) == 0 || (io.wmask & 5) == 0) {  // one column half (bits 1, 4: column 0; 2, 8: column 1)
-            ua_tile<B, T, 256, true>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io,
-                                     (io.wmask & 5) ? 0 : 1);
+        const int m = io.wmask;
+        if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c
+            const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
+            ua_block64<T>(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, io.side, lds);
             return;
         }
     }
@@ -500,8 +617,10 @@ void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, 
                     const int *qmask, T *side, hipStream_t s) {
     using U = UaCfg<B>;
     // more than half a CU's LDS: no CU shared with the bounded kernels on the
-    // other stream, nor with a second critical tile
-    const size_t lds = std::max<size_t>(U::LDS_BYTES, 81 * 1024);
+    // other stream, nor with a second critical tile (b = 64: a whole tile)
+    size_t need = U::LDS_BYTES;
+    if constexpr (B == 64) need = std::max(need, sizeof(T) * 128 * 129);
+    const size_t lds = std::max<size_t>(need, 81 * 1024);
     static bool attr = false;
     if (!attr) {
         JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a_crit<B, T>),
