@@ -21,11 +21,30 @@
 // from component v of the GEMM 1 accumulators.  T never leaves registers.
 #include "jx_common.hpp"
 
+#include <type_traits>
+
 namespace jx {
 
 namespace {
 
 constexpr int KC = 16;  // X chunk width (columns)
+
+// 0 and 1 of each type.  The operand of a skipped rotation (V = I) is loaded
+// from here: the address is chosen, not the value, so that operand loads
+// never sit behind a branch and stay in flight together.
+__device__ double kEye64[2] = {0.0, 1.0};
+__device__ float kEye32[2] = {0.0f, 1.0f};
+template <class T>
+__device__ __forceinline__ const T *eye_ptr(bool diag);
+template <>
+__device__ __forceinline__ const double *eye_ptr<double>(bool diag) { return kEye64 + (diag ? 1 : 0); }
+template <>
+__device__ __forceinline__ const float *eye_ptr<float>(bool diag) { return kEye32 + (diag ? 1 : 0); }
+// *p, or entry (diag) of the identity when the rotation is skipped
+template <class T>
+__device__ __forceinline__ T op_or_eye(const T *p, bool id, bool diag) {
+    return *(id ? eye_ptr<T>(diag) : p);
+}
 
 // HALF: T is computed for one column half of the tile only (the columns of
 // one block), which is all that one output block needs.
@@ -157,7 +176,7 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
     // bit for bit)
     auto vqk = [&](int ch, int st, int ct) {
         const int kg = ch * KC + MT::kstep(st, g), col = wc0 + 16 * ct + x;
-        return idq ? (kg == col ? T(1) : T(0)) : vq[MT::vidx(kg, col, M2)];
+        return op_or_eye(vq + MT::vidx(kg, col, M2), idq, kg == col);
     };
     // one column tile per wave: a chunk's V_q operands are fetched one chunk
     // ahead, so that their global-memory latency hides behind the previous
@@ -238,7 +257,7 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
             // component s of lane group g; vidx(k, i) - vidx(0, i) depends on k only
             auto vpk = [&](int rt, int s) {
                 const int k = 16 * rt + MT::rrow(g, s);
-                return idp ? (k == orow ? T(1) : T(0)) : vrow[MT::vidx(k, 0, M2) - MT::vidx(0, 0, M2)];
+                return op_or_eye(vrow + (MT::vidx(k, 0, M2) - MT::vidx(0, 0, M2)), idp, k == orow);
             };
             if constexpr (CT == 1) {
                 // one output column tile per wave: every V_p operand of the
@@ -293,20 +312,22 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
     }
 }
 
-// One block of tile (p, q) for b = 64: row half h, column half c, by 256
-// threads (wave w owns T's 16 columns 64 c + 16 w ..), latency first.  The
-// whole input tile goes to LDS with one round of global loads (64 values per
-// thread, plus the wave's 32 V_q operands), then GEMM 1 (32 k-steps x 8 row
-// tiles) and GEMM 2 for row half h only (V_p operands one output tile ahead).
-// The original block is saved to `side` and the new one written in place.
-// `lds` holds 128 x 129 values.
-template <class T>
-__device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__restrict__ ablk,
-                                           const T *__restrict__ vhat, int p, int q, bool idp, bool idq, int h,
-                                           int c, T *__restrict__ side, T *lds) {
+// One block of tile (p, q) for b = 64 in FP64: row half h, column half c, by
+// 256 threads (wave w owns T's 16 columns 64 c + 16 w ..), latency first.
+// One round of global loads brings the whole input tile (to LDS), the wave's
+// 32 V_q operands and the half of V_p that GEMM 2 reads (each value once, to
+// LDS after GEMM 1); GEMM 1 runs 32 k-steps x 8 row tiles, GEMM 2 the four
+// output row tiles of row half h as four interleaved accumulator chains.  The
+// original block is saved to `side` and the new one written in place.
+// `lds` holds 128 x 129 doubles.
+__device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double *__restrict__ ablk,
+                                           const double *__restrict__ vhat, int p, int q, bool idp, bool idq,
+                                           int h, int c, double *__restrict__ side, double *lds) {
+    using T = double;
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int B = 64, M2 = 128, XLD = M2 + 1, NTH = 256, PB = B * B / NTH;
+    constexpr int VH = M2 * B;  // V_p(:, half h): 128 x 64
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int Rr[2] = {pairs[2 * p], pairs[2 * p + 1]};
@@ -318,7 +339,7 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__r
         return ablk + ublk(R < C ? R : C, R < C ? C : R) * (size_t)(B * B);
     };
 
-    // every load at once: the four blocks (contiguous per thread) and V_q
+    // every load at once: the four blocks (contiguous per thread), V_q, V_p's half
     T xr[4][PB];
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
@@ -331,7 +352,16 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__r
 #pragma unroll
     for (int s = 0; s < M2 / 4; ++s) {
         const int kg = 16 * (s >> 2) + MT::kstep(s & 3, g);
-        bq[s] = idq ? (kg == col ? T(1) : T(0)) : vq[MT::vidx(kg, col, M2)];
+        bq[s] = op_or_eye(vq + MT::vidx(kg, col, M2), idq, kg == col);
+    }
+    // V_p(k, 64 h + il) sits at vperm(k, il, 64) of the half's copy: its 32
+    // runs of 256 values (one per k >> 2) are contiguous in V_hat too
+    T vr[VH / NTH];
+#pragma unroll
+    for (int m = 0; m < VH / NTH; ++m) {
+        const int j = tid + NTH * m;
+        const int k = 4 * (j >> 8) + ((j >> 4) & 3), il = ((j >> 6) & 3) * 16 + (j & 15);
+        vr[m] = op_or_eye(vp + MT::vidx(k, 64 * h + il, M2), idp, k == 64 * h + il);
     }
     // X(row, k) at lds[k XLD + row]: block (hh, cc) holds rows 64 hh .., k 64 cc ..
 #pragma unroll
@@ -345,17 +375,6 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__r
             lds[(64 * cc + kl) * XLD + 64 * hh + rl] = xr[bb][m];
         }
     }
-    // V_p operands of output row tile ot (row 64 h + 16 ot + x of V_p^T T):
-    // step (rt, s) contracts row 16 rt + rrow(g, s) of T
-    auto vpk = [&](int ot, int rt, int s) {
-        const int orow = 64 * h + 16 * ot + x, k = 16 * rt + MT::rrow(g, s);
-        return idp ? (k == orow ? T(1) : T(0)) : vp[MT::vidx(k, orow, M2)];
-    };
-    T af[M2 / 16][4];
-#pragma unroll
-    for (int rt = 0; rt < M2 / 16; ++rt)
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) af[rt][s4] = vpk(0, rt, s4);
     __syncthreads();
 
     // GEMM 1: T(:, col tile) = X V_q(:, col tile)
@@ -368,31 +387,31 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__r
 #pragma unroll
         for (int rt = 0; rt < M2 / 16; ++rt) acc[rt] = MT::mma(lds[kl * XLD + 16 * rt + x], bq[s], acc[rt]);
     }
-    __syncthreads();  // X no longer read: the output block takes its place
+    __syncthreads();  // X no longer read: V_p's half and the output block take its place
+    T *vps = lds;         // V_p(:, half h), vperm order of a 128 x 64 matrix
+    T *os = lds + VH;     // [column 0 .. 63][row 0 .. 63], stride B + 1
+#pragma unroll
+    for (int m = 0; m < VH / NTH; ++m) vps[tid + NTH * m] = vr[m];
+    __syncthreads();
 
-    // GEMM 2: out(:, col tile) = V_p(:, row half h)^T T, one 16-row tile at a time
-    T *os = lds;  // [column 0 .. 63][row 0 .. 63], stride B + 1
+    // GEMM 2: out(:, col tile) = V_p(:, half h)^T T.  Step (rt, s4) contracts
+    // row 16 rt + rrow(g, s4) of T (component s4 of acc[rt]); output row tile
+    // ot's operand for it is vperm(16 rt + rrow(g, s4), 16 ot + x, 64)
+    // = 256 (4 rt + s4) + 64 ot + lane
+    acc_t o[B / 16];
 #pragma unroll
-    for (int ot = 0; ot < B / 16; ++ot) {
-        T cur[M2 / 16][4];
+    for (int ot = 0; ot < B / 16; ++ot) o[ot] = acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int rt = 0; rt < M2 / 16; ++rt)
+    for (int rt = 0; rt < M2 / 16; ++rt)
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) cur[rt][s4] = af[rt][s4];
-        if (ot + 1 < B / 16) {
+        for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-            for (int rt = 0; rt < M2 / 16; ++rt)
+            for (int ot = 0; ot < B / 16; ++ot)
+                o[ot] = MT::mma(vps[256 * (4 * rt + s4) + 64 * ot + lane], acc[rt][s4], o[ot]);
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) af[rt][s4] = vpk(ot + 1, rt, s4);
-        }
-        acc_t o = acc_t{0, 0, 0, 0};
+    for (int ot = 0; ot < B / 16; ++ot)
 #pragma unroll
-        for (int rt = 0; rt < M2 / 16; ++rt)
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) o = MT::mma(cur[rt][s4], acc[rt][s4], o);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) os[(16 * w + x) * (B + 1) + 16 * ot + MT::rrow(g, v)] = o[v];
-    }
+        for (int v = 0; v < 4; ++v) os[(16 * w + x) * (B + 1) + 16 * ot + MT::rrow(g, v)] = o[ot][v];
     __syncthreads();
 
     // block (Rr[h], Cq[c]): original to side, new value in place
@@ -410,9 +429,10 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__r
 
 // Only the critical quadrants qmask[i] of tile i, one tile per workgroup:
 // their original blocks are saved to side + 4 i B^2 (+ quad B^2) and the new
-// ones written in place.  One block (b = 64) takes T for its column half only
-// and V_p^T T for its row half only: 3/8 of a tile's products.  Two blocks,
-// and b = 32, take all of T.
+// ones written in place.  Blocks within one column half (b = 64) take T for
+// that half only, and V_p^T T for the row halves written: 3/8 of a tile's
+// products for one block (FP64: the whole tile staged in LDS at once).  Two
+// opposite blocks, and b = 32, take all of T.
 template <int B, class T>
 __global__ void __launch_bounds__(256, 1)
 k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
@@ -430,9 +450,15 @@ k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__
     T *lds = reinterpret_cast<T *>(lds_raw);
     if constexpr (B == 64) {
         const int m = io.wmask;
-        if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c
-            const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
-            ua_block64<T>(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, io.side, lds);
+        if constexpr (std::is_same<T, double>::value) {
+            if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c
+                const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
+                ua_block64(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, io.side, lds);
+                return;
+            }
+        }
+        if ((m & 10) == 0 || (m & 5) == 0) {  // one column half (bits 1, 4: column 0; 2, 8: column 1)
+            ua_tile<B, T, 256, true>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io, (m & 5) ? 0 : 1);
             return;
         }
     }
