@@ -313,23 +313,26 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
 }
 
 // One block of tile (p, q) for b = 64 in FP64: row half h, column half c, by
-// 256 threads (wave w owns T's 16 columns 64 c + 16 w ..), latency first.
-// One round of global loads brings the whole input tile (to LDS), the wave's
-// 32 V_q operands and the half of V_p that GEMM 2 reads (each value once, to
-// LDS after GEMM 1); GEMM 1 runs 32 k-steps x 8 row tiles, GEMM 2 the four
-// output row tiles of row half h as four interleaved accumulator chains.  The
-// original block is saved to `side` and the new one written in place.
-// `lds` holds 128 x 129 doubles.
+// 512 threads, latency first.  One round of global loads brings the whole
+// input tile (to LDS), the V_q operands and the half of V_p that GEMM 2 reads
+// (each value once, to LDS after GEMM 1).  Wave w = 4 rh + ct computes T's
+// column tile ct (16 columns of half c) for rows 64 rh .. 64 rh + 63 (GEMM 1:
+// 32 k-steps x 4 row tiles) and hands it over through LDS in GEMM 2's operand
+// order; GEMM 2 gives wave w output row tiles 2 rh, 2 rh + 1 of row half h in
+// column tile ct.  Two waves per SIMD: one wave's LDS waits are the other's
+// MFMA time.  The original block is saved to `side` and the new one written
+// in place.  `lds` holds 128 x 129 doubles.
 __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double *__restrict__ ablk,
                                            const double *__restrict__ vhat, int p, int q, bool idp, bool idq,
                                            int h, int c, double *__restrict__ side, double *lds) {
     using T = double;
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
-    constexpr int B = 64, M2 = 128, XLD = M2 + 1, NTH = 256, PB = B * B / NTH;
+    constexpr int B = 64, M2 = 128, XLD = M2 + 1, NTH = 512, PB = B * B / NTH;
     constexpr int VH = M2 * B;  // V_p(:, half h): 128 x 64
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
+    const int ct = w & 3, rh = w >> 2;
     const int Rr[2] = {pairs[2 * p], pairs[2 * p + 1]};
     const int Cq[2] = {pairs[2 * q], pairs[2 * q + 1]};
     const T *vp = vhat + (size_t)p * M2 * M2;
@@ -347,7 +350,7 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double
 #pragma unroll
         for (int m = 0; m < PB; ++m) xr[bb][m] = src[tid + NTH * m];
     }
-    const int col = 64 * c + 16 * w + x;  // this lane's column of T
+    const int col = 64 * c + 16 * ct + x;  // this lane's column of T
     T bq[M2 / 4];
 #pragma unroll
     for (int s = 0; s < M2 / 4; ++s) {
@@ -377,41 +380,49 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double
     }
     __syncthreads();
 
-    // GEMM 1: T(:, col tile) = X V_q(:, col tile)
-    acc_t acc[M2 / 16];
+    // GEMM 1: T(64 rh .. 64 rh + 63, col tile) = X(those rows, :) V_q(:, col tile)
+    acc_t acc[4];
 #pragma unroll
-    for (int rt = 0; rt < M2 / 16; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < M2 / 4; ++s) {
         const int kl = 16 * (s >> 2) + MT::kstep(s & 3, g);
 #pragma unroll
-        for (int rt = 0; rt < M2 / 16; ++rt) acc[rt] = MT::mma(lds[kl * XLD + 16 * rt + x], bq[s], acc[rt]);
+        for (int rt = 0; rt < 4; ++rt) acc[rt] = MT::mma(lds[kl * XLD + 64 * rh + 16 * rt + x], bq[s], acc[rt]);
     }
-    __syncthreads();  // X no longer read: V_p's half and the output block take its place
-    T *vps = lds;         // V_p(:, half h), vperm order of a 128 x 64 matrix
-    T *os = lds + VH;     // [column 0 .. 63][row 0 .. 63], stride B + 1
+    __syncthreads();  // X no longer read: V_p's half and T take its place
+    // T in GEMM 2's B-operand order: step (rt, s4) of column tile ct at
+    // tops[((4 rt + s4) 4 + ct) 64 + lane] = T(16 rt + rrow(g, s4), 16 ct + x),
+    // which is component s4 of this wave's acc[rt - 4 rh]
+    T *vps = lds;       // V_p(:, half h), vperm order of a 128 x 64 matrix
+    T *tops = lds + VH; // 8 x 4 x 4 x 64 values
 #pragma unroll
     for (int m = 0; m < VH / NTH; ++m) vps[tid + NTH * m] = vr[m];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) tops[((4 * (4 * rh + rt) + s4) * 4 + ct) * 64 + lane] = acc[rt][s4];
     __syncthreads();
 
-    // GEMM 2: out(:, col tile) = V_p(:, half h)^T T.  Step (rt, s4) contracts
-    // row 16 rt + rrow(g, s4) of T (component s4 of acc[rt]); output row tile
-    // ot's operand for it is vperm(16 rt + rrow(g, s4), 16 ot + x, 64)
-    // = 256 (4 rt + s4) + 64 ot + lane
-    acc_t o[B / 16];
-#pragma unroll
-    for (int ot = 0; ot < B / 16; ++ot) o[ot] = acc_t{0, 0, 0, 0};
+    // GEMM 2: out(row tiles 2 rh, 2 rh + 1 of half h, col tile) = V_p(:, ..)^T T.
+    // Output row tile ot's operand for step (rt, s4) is
+    // vperm(16 rt + rrow(g, s4), 16 ot + x, 64) = 256 (4 rt + s4) + 64 ot + lane
+    acc_t o[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
 #pragma unroll
     for (int rt = 0; rt < M2 / 16; ++rt)
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const T bt = tops[((4 * rt + s4) * 4 + ct) * 64 + lane];
 #pragma unroll
-            for (int ot = 0; ot < B / 16; ++ot)
-                o[ot] = MT::mma(vps[256 * (4 * rt + s4) + 64 * ot + lane], acc[rt][s4], o[ot]);
+            for (int j = 0; j < 2; ++j)
+                o[j] = MT::mma(vps[256 * (4 * rt + s4) + 64 * (2 * rh + j) + lane], bt, o[j]);
+        }
+    __syncthreads();  // V_p's half and T no longer read
+    T *os = lds;  // [column 0 .. 63][row 0 .. 63], stride B + 1
 #pragma unroll
-    for (int ot = 0; ot < B / 16; ++ot)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) os[(16 * w + x) * (B + 1) + 16 * ot + MT::rrow(g, v)] = o[ot][v];
+        for (int v = 0; v < 4; ++v) os[(16 * ct + x) * (B + 1) + 16 * (2 * rh + j) + MT::rrow(g, v)] = o[j][v];
     __syncthreads();
 
     // block (Rr[h], Cq[c]): original to side, new value in place
@@ -434,7 +445,7 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double
 // products for one block (FP64: the whole tile staged in LDS at once).  Two
 // opposite blocks, and b = 32, take all of T.
 template <int B, class T>
-__global__ void __launch_bounds__(256, 1)
+__global__ void __launch_bounds__(512, 1)
 k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
                 const int *__restrict__ flags, const int *__restrict__ tiles, const int *__restrict__ qmask,
                 T *__restrict__ side) {
@@ -448,21 +459,24 @@ k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__
     io.save = true;
     io.side = side + (size_t)4 * i * B * B;
     T *lds = reinterpret_cast<T *>(lds_raw);
-    if constexpr (B == 64) {
-        const int m = io.wmask;
-        if constexpr (std::is_same<T, double>::value) {
-            if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c
-                const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
-                ua_block64(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, io.side, lds);
-                return;
-            }
-        }
-        if ((m & 10) == 0 || (m & 5) == 0) {  // one column half (bits 1, 4: column 0; 2, 8: column 1)
-            ua_tile<B, T, 256, true>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io, (m & 5) ? 0 : 1);
+    const int m = io.wmask;
+    if constexpr (B == 64 && std::is_same<T, double>::value) {
+        if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c, on all eight waves
+            const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
+            ua_block64(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, io.side, lds);
             return;
         }
     }
-    ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io);
+    // otherwise four waves work, the other four take the same barriers
+    const int t = threadIdx.x & 255;
+    const bool act = threadIdx.x < 256;
+    if constexpr (B == 64) {
+        if ((m & 10) == 0 || (m & 5) == 0) {  // one column half (bits 1, 4: column 0; 2, 8: column 1)
+            ua_tile<B, T, 256, true>(pairs, ablk, vhat, p, q, idp, idq, t, lds, act, io, (m & 5) ? 0 : 1);
+            return;
+        }
+    }
+    ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, t, lds, act, io);
 }
 
 // The same tiles on a bounded set of CUs (as k_update_q_bounded): 512 threads
@@ -653,7 +667,7 @@ void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, 
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = true;
     }
-    hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles), dim3(256), lds, s, pairs, ablk, vhat, flags, tiles,
+    hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
                        qmask, side);
     JX_LAUNCHED();
 }
