@@ -312,9 +312,13 @@ struct EigState {
 
     void make_streams() {
         JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
-        JX_HIP(hipEventCreateWithFlags(&ev_v, hipEventDisableTiming));
-        JX_HIP(hipEventCreateWithFlags(&ev_q, hipEventDisableTiming));
-        JX_HIP(hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming));
+        // ordering between the two streams of one device only: the kernels'
+        // own completion makes their writes visible device-wide, so the
+        // events need no system-scope fence (cache write-back) of their own
+        const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
+        JX_HIP(hipEventCreateWithFlags(&ev_v, fl));
+        JX_HIP(hipEventCreateWithFlags(&ev_q, fl));
+        JX_HIP(hipEventCreateWithFlags(&ev_rest, fl));
     }
     ~EigState() {
         if (sq) (void)hipStreamSynchronize(sq);
