@@ -226,6 +226,156 @@ __device__ __forceinline__ int pkm(int i, int j) { return i <= j ? pk(i, j) : pk
 // Addresses of the 32 x 32 pair problems' sweeps (compile-time table).
 __device__ const SweepTable<32, 64> kSweep32 = make_sweep_table<32, 64>();
 
+// Cross rotations of a 32 x 32 pair problem of blocks ba (local indices
+// 0..15) and bb (16..31) whose within-block pairs were rotated in an earlier
+// block round of the same inner sweep: 16 rounds, round sh pairs k with
+// q(k, sh) = 16 + (k + sh) mod 16, so that each (ba, bb) index pair is
+// rotated once.  One wave.  S: upper triangle, entry (a, b), a <= b, at
+// S[32 a + b].  prm: two rounds of (c[16], s[16], shift[16]), shift = t a_pq
+// (a_pp -= shift, a_qq += shift).  Every round's (c, s) go to the ring for
+// the follower (follow_cross); the round's 120 pair-blocks (k1 < k2: entries
+// (p1, p2), (p1, q2), (q1, p2), (q1, q2)) are disjoint, two per lane.  Lanes
+// 0..15 own the pair-blocks that hold the next round's pivots ((k, k + 1):
+// entry (p1, q2); (0, 15): entry (q1, p2)), update the two diagonal entries
+// of that pivot and write the next round's parameters, so a round needs one
+// wave-level ordering.
+__device__ __forceinline__ int cross_q(int k, int sh) { return 16 + ((k + sh) & 15); }
+__device__ __forceinline__ int cross_at(int a, int b) { return a < b ? 32 * a + b : 32 * b + a; }
+__device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
+    constexpr int H = 16, NI = 120;
+    // parameters of round 0: pivots (k, 16 + k)
+    if (lane < H) {
+        const int p = lane, q = cross_q(lane, 0);
+        rot_params(S[33 * p], S[33 * q], S[cross_at(p, q)], prm, lane, H);
+        double *rb = vr.ring + (vr.base & (VR_DEPTH - 1)) * 2 * H;
+        lds_wait_geq(vr.vdone, vr.base + 1 - VR_DEPTH, vr.fail, vr.spin);
+        rb[lane] = prm[lane];
+        rb[H + lane] = prm[H + lane];
+    }
+    wave_lds_sync();
+    lds_store_release(vr.sdone, vr.base + 1);
+
+    // this lane's pair-blocks it = lane, lane + 64: 0..14 (k, k+1), 15 (0, 15),
+    // then distance d = 2 .. 14 in order of d and k1
+    int k1[2], k2[2];
+    bool ok[2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) {
+        const int it = lane + 64 * ii;
+        ok[ii] = it < NI;
+        int a = 0, b = 1;
+        if (it < 15) { a = it; b = it + 1; }
+        else if (it == 15) { a = 0; b = 15; }
+        else if (it < NI) {
+            int r = it - 16, d = 2;
+            while (r >= H - d) { r -= H - d; ++d; }
+            a = r; b = r + d;
+        }
+        k1[ii] = a;
+        k2[ii] = b;
+    }
+    const bool prod = lane < H;  // item 0 holds the pivot of pair `lane` for the next round
+    const int kn = (lane + 1) & 15;
+    for (int sh = 0; sh < H; ++sh) {
+        const double *cur = prm + (sh & 1) * 3 * H;
+        double *nxt = prm + ((sh + 1) & 1) * 3 * H;
+        double nv[2][4];
+        // producer: the two diagonal entries of pair `lane`'s next pivot
+        // (p of this pair, q of the next pair), read before the round's stores
+        double dp = 0.0, dq = 0.0, shp = 0.0, shq = 0.0;
+        if (prod) {
+            dp = S[33 * lane];
+            dq = S[33 * cross_q(kn, sh)];
+            shp = cur[2 * H + lane];
+            shq = cur[2 * H + kn];
+        }
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+            const int a = k1[ii], b = k2[ii], qa = cross_q(a, sh), qb = cross_q(b, sh);
+            const double c1 = cur[a], s1 = cur[H + a], c2 = cur[b], s2 = cur[H + b];
+            const double b00 = S[cross_at(a, b)], b01 = S[cross_at(a, qb)];
+            const double b10 = S[cross_at(qa, b)], b11 = S[cross_at(qa, qb)];
+            // rows: J1^T, then columns: J2 (J = [[c, s], [-s, c]] on (p, q))
+            const double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;
+            const double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
+            nv[ii][0] = c2 * r00 - s2 * r01;
+            nv[ii][1] = s2 * r00 + c2 * r01;
+            nv[ii][2] = c2 * r10 - s2 * r11;
+            nv[ii][3] = s2 * r10 + c2 * r11;
+        }
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+            if (!ok[ii]) continue;
+            const int a = k1[ii], b = k2[ii], qa = cross_q(a, sh), qb = cross_q(b, sh);
+            S[cross_at(a, b)] = nv[ii][0];
+            S[cross_at(a, qb)] = nv[ii][1];
+            S[cross_at(qa, b)] = nv[ii][2];
+            S[cross_at(qa, qb)] = nv[ii][3];
+        }
+        if (prod) {
+            const double app = dp - shp, aqq = dq + shq;
+            S[33 * lane] = app;
+            S[33 * cross_q(kn, sh)] = aqq;
+            S[cross_at(lane, cross_q(lane, sh))] = 0.0;  // this round's pivot (no item holds it)
+            if (sh + 1 < H) {
+                const double apq = lane < 15 ? nv[0][1] : nv[0][2];
+                rot_params(app, aqq, apq, nxt, lane, H);
+                const int n = vr.base + sh + 1;
+                double *rb = vr.ring + (n & (VR_DEPTH - 1)) * 2 * H;
+                lds_wait_geq(vr.vdone, n + 1 - VR_DEPTH, vr.fail, vr.spin);
+                rb[lane] = nxt[lane];
+                rb[H + lane] = nxt[H + lane];
+            }
+        }
+        wave_lds_sync();
+        if (sh + 1 < H) lds_store_release(vr.sdone, vr.base + sh + 2);
+    }
+}
+
+// The follower of cross_sweep: W (32 x 32) <- W J for every round, lane
+// 2 r + h holding row r at 16 positions.  h = 0: columns 0..15 (block ba)
+// in order; h = 1: block bb, rotated so that in round sh position j holds
+// column 16 + (j + sh) mod 16, the partner of column j.  After 16 rounds
+// positions equal columns again.
+__device__ void follow_cross(const VRing &vr, int lane, double *V) {
+    constexpr int H = 16;
+    const int r = lane >> 1, h = lane & 1;
+#pragma unroll
+    for (int j = 0; j < H; ++j) V[j] = (r == 16 * h + j) ? 1.0 : 0.0;
+    for (int sh = 0; sh < H; ++sh) {
+        const int n = vr.base + sh;
+        lds_wait_geq(vr.sdone, n + 1, vr.fail, vr.spin);
+        const double *rb = vr.ring + (n & (VR_DEPTH - 1)) * 2 * H;
+        // four positions at a time (the V role keeps V_hat^T in half of its
+        // registers); the partner lane's positions (same row, other block)
+        // come from DPP quad permutation [1, 0, 3, 2], which swaps the lanes
+        // of each pair; column p = c p - s q, column q = s p + c q
+#pragma unroll
+        for (int j0 = 0; j0 < H; j0 += 4) {
+            double vc[4], vs[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                vc[j] = rb[j0 + j];
+                vs[j] = rb[H + j0 + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double pt = dpp_quad_t<(1 | 0 << 2 | 3 << 4 | 2 << 6)>(V[j0 + j]);
+                V[j0 + j] = h ? vs[j] * pt + vc[j] * V[j0 + j] : vc[j] * V[j0 + j] - vs[j] * pt;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // this round's slot is read: free it
+        lds_store_release(vr.vdone, n + 1);
+        if (h) {
+            const double v0 = V[0];
+#pragma unroll
+            for (int j = 0; j < H - 1; ++j) V[j] = V[j + 1];
+            V[H - 1] = v0;
+        }
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
     using namespace tl;
@@ -319,28 +469,40 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
                 // ---- phase 1: one sweep on the 32 x 32 problem of block pair k;
                 //      local index l < 16 is row l of block ba, l >= 16 row
                 //      l - 16 of block bb
+                //      (block round 0: a full sweep; later block rounds: the
+                //      16 rounds of cross pairs only, the within-block pairs
+                //      having been rotated in block round 0)
                 const int ba = index_at(2 * k, t, NB), bb = index_at(2 * k + 1, t, NB);
                 auto glob = [&](int l) { return l < BS ? BS * ba + l : BS * bb + (l - BS); };
+                const bool cross = t > 0;
                 int ai[NG];  // A_hat (packed) index of each entry
 #pragma unroll
                 for (int i = 0; i < NG; ++i) ai[i] = pkm(glob(lr[i] & 255), glob(lr[i] >> 8));
+                // S index of entry i: slot order for the full sweep, plain for the cross rounds
+                auto sx = [&](int i) { return cross ? (lr[i] & 255) * 32 + (lr[i] >> 8) : si[i]; };
                 {
                     double v[NG];
 #pragma unroll
                     for (int i = 0; i < NG; ++i) v[i] = Ap[ai[i]];
 #pragma unroll
                     for (int i = 0; i < NG; ++i)
-                        if (lane + 64 * i < 528) S[si[i]] = v[i];
+                        if (lane + 64 * i < 528) S[sx(i)] = v[i];
                 }
                 wave_lds_sync();
                 const VRing vr{rings + k * RING, ctr + k, ctr + 4 + k, rnd, ctr + 8, spin};
-                scalar_sweeps<32, 64, true, true, true>(S, prm, nullptr, lane, 1, false, 0.0, nullptr, &kSweep32, vr);
-                rnd += 31;
+                if (cross) {
+                    cross_sweep(S, prm, lane, vr);
+                    rnd += 16;
+                } else {
+                    scalar_sweeps<32, 64, true, true, true>(S, prm, nullptr, lane, 1, false, 0.0, nullptr, &kSweep32,
+                                                            vr);
+                    rnd += 31;
+                }
                 __syncthreads();  // X: W of this round written by the V role; D back into A_hat
                 {
                     double v[NG];
 #pragma unroll
-                    for (int i = 0; i < NG; ++i) v[i] = S[si[i]];
+                    for (int i = 0; i < NG; ++i) v[i] = S[sx(i)];
 #pragma unroll
                     for (int i = 0; i < NG; ++i)
                         if (lane + 64 * i < 528) Ap[ai[i]] = v[i];
@@ -474,8 +636,13 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
                 // h = lane mod 2
                 const VRing vr{rings + c * RING, ctr + c, ctr + 4 + c, rnd, ctr + 8, spin};
                 double Vl[16];
-                follow_sweep<32>(vr, lane, Vl);
-                rnd += 31;
+                if (t > 0) {  // cross rounds (as the solver role)
+                    follow_cross(vr, lane, Vl);
+                    rnd += 16;
+                } else {
+                    follow_sweep<32>(vr, lane, Vl);
+                    rnd += 31;
+                }
                 double *W = Ap + AP + c * SW + WOFF;
                 const int r = lane >> 1, h = lane & 1;
 #pragma unroll
