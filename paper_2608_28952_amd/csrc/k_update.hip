@@ -526,11 +526,12 @@ k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T 
 
 // Q(r0 .. r0+127, [I,J]) <- Q(r0 .. r0+127, [I,J]) V_p, computed as
 // out^T = V_p^T X^T so that lanes hold consecutive rows of the column-major Q.
-// 256 threads (t = 0 .. 255) in a 2 x 2 wave layout: wave (wi, wj) owns out
-// columns b wi .. b wi + b-1 (of the 2b pair columns) and Q rows
-// r0 + 64 wj .. r0 + 64 wj + 63.  `active` false: no work, but the barrier
-// before the in-place store is still taken (the caller's barrier count).
-template <int B, class T>
+// NW waves (t = 0 .. 64 NW - 1) in a 2 x NW/2 layout: wave (wi, wj) owns out
+// columns b wi .. b wi + b-1 (of the 2b pair columns) and 128 / (NW / 2) Q
+// rows from r0 + wj 128 / (NW / 2).  `active` false: no work, but the
+// barrier before the in-place store is still taken (the caller's barrier
+// count).
+template <int B, class T, int NW = 4>
 __device__ __forceinline__ void uq_item(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
                                         const T *__restrict__ vhat, int p, int rb, int t, bool active) {
     using MT = MfmaTraits<T>;
@@ -538,13 +539,14 @@ __device__ __forceinline__ void uq_item(const int *__restrict__ pairs, T *__rest
     constexpr int M2 = 2 * B;
     constexpr int HALF = M2 / 2;     // out columns per wave
     constexpr int IT = HALF / 16;    // 16-tiles of out columns per wave
-    constexpr int JT = 4;            // 16-tiles of rows per wave (64 rows)
+    constexpr int RW = 128 / (NW / 2);  // rows per wave
+    constexpr int JT = RW / 16;      // 16-tiles of rows per wave
     const int I = active ? pairs[2 * p] : 0, J = active ? pairs[2 * p + 1] : 0;
     const T *vp = vhat + (size_t)p * M2 * M2;
     const int lane = t & 63, w = t >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int wi = w & 1, wj = w >> 1;
-    const size_t r0 = (size_t)rb * 128 + 64 * wj;
+    const size_t r0 = (size_t)rb * 128 + RW * wj;
 
     acc_t acc[IT][JT];
 #pragma unroll
@@ -610,22 +612,20 @@ k_update_q(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
     uq_item<B, T>(pairs, Q, ldq, vhat, p, blockIdx.x, threadIdx.x, true);
 }
 
-// The same work on a bounded set of CUs: 512 threads (two 256-thread halves,
-// each one row block of one pair at a time) and a dynamic LDS request larger
-// than half a CU's, so each workgroup holds a CU of its own and a grid of
-// CUs - reserve workgroups leaves `reserve` CUs free for the subproblem kernel
-// that runs beside it.  Item i = 2 (k gridDim + blockIdx) + half, row block
-// i mod nrb of pair i / nrb; every half takes every barrier.
+// The same work on a bounded set of CUs: 512 threads, one row block of one
+// pair at a time on all eight waves (item k gridDim + blockIdx: row block
+// i mod nrb of pair i / nrb), and a dynamic LDS request larger than half a
+// CU's, so each workgroup holds a CU of its own and a grid of CUs - reserve
+// workgroups leaves `reserve` CUs free for the subproblem kernel that runs
+// beside it.
 template <int B, class T>
 __global__ void __launch_bounds__(512, 1)
 k_update_q_bounded(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
                    const T *__restrict__ vhat, const int *__restrict__ flags, int nrb, int nwork) {
-    const int half = threadIdx.x >> 8, t = threadIdx.x & 255;
-    for (int i0 = 2 * blockIdx.x; i0 < nwork; i0 += 2 * gridDim.x) {
-        const int i = i0 + half;
+    for (int i = blockIdx.x; i < nwork; i += gridDim.x) {
         const int p = i / nrb, rb = i - p * nrb;
-        const bool active = i < nwork && !flags[i < nwork ? p : 0];
-        uq_item<B, T>(pairs, Q, ldq, vhat, active ? p : 0, active ? rb : 0, t, active);
+        if (flags[p]) continue;  // V_p = I (uniform over the workgroup)
+        uq_item<B, T, 8>(pairs, Q, ldq, vhat, p, rb, threadIdx.x, true);
     }
 }
 constexpr size_t UQ_BOUNDED_LDS = 81 * 1024;  // > half of the 160 KB LDS: one workgroup per CU
@@ -718,7 +718,7 @@ void launch_uq_bounded(int npairs, const int *pairs, T *Q, int ldq, int n_rows, 
         attr = true;
     }
     const int nrb = n_rows / 128, nwork = nrb * npairs;
-    const int grid = std::max(1, std::min(device_cus() - reserve, (nwork + 1) / 2));
+    const int grid = std::max(1, std::min(device_cus() - reserve, nwork));
     hipLaunchKernelGGL((k_update_q_bounded<B, T>), dim3(grid), dim3(512), UQ_BOUNDED_LDS, s, pairs, Q, ldq, vhat,
                        flags, nrb, nwork);
     JX_LAUNCHED();
