@@ -40,12 +40,14 @@ N = 4096
 BLOCK = 64
 SEED = 2
 PEAK = {"fp64_tflops": 78.6, "hbm_gbs": 8000.0}
-KINDS = {0: "k_subproblem2", 1: "k_update_a_crit", 2: "k_update_q", 3: "k_gemm_f64", 5: "k_update_a_bounded"}
+KINDS = {0: "k_subproblem2", 1: "k_update_a_crit", 2: "k_update_q", 3: "k_gemm_f64", 5: "k_update_a_bounded",
+         6: "k_update_aq_bounded"}
 SOURCES = {"k_subproblem2": ["k_subproblem.hip", "jx_sweep.hpp"], "k_update_a_crit": ["k_update.hip"],
-           "k_update_q": ["k_update.hip"], "k_gemm_f64": ["k_gemm.hip"], "k_update_a_bounded": ["k_update.hip"]}
+           "k_update_q": ["k_update.hip"], "k_gemm_f64": ["k_gemm.hip"], "k_update_a_bounded": ["k_update.hip"],
+           "k_update_aq_bounded": ["k_update.hip"]}
 # kernels on the second stream, beside the next round's subproblems (not on
 # the solve's critical path): not candidates for the dominant kernel
-SIDE = {"k_update_q", "k_update_a_bounded"}
+SIDE = {"k_update_q", "k_update_a_bounded", "k_update_aq_bounded"}
 
 
 def kernel_source_hash(name):

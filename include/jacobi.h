@@ -295,8 +295,10 @@ enum jacobi_prof_kind {
     JACOBI_PROF_UPDATE_Q = 2,   /* Q(:, [I,J]) V_hat                              */
     JACOBI_PROF_GEMM = 3,       /* refinement GEMMs                              */
     JACOBI_PROF_GRAM = 4,       /* Gram blocks of the one-sided SVD              */
-    JACOBI_PROF_UPDATE_A_REST = 5 /* pair tiles no next-round subproblem waits for,
-                                     on the second stream beside the subproblems  */
+    JACOBI_PROF_UPDATE_A_REST = 5, /* pair tiles no next-round subproblem waits for,
+                                      on the second stream beside the subproblems  */
+    JACOBI_PROF_UPDATE_AQ = 6      /* b = 64: those tiles and the Q update in one
+                                      launch on the second stream                 */
 };
 
 /*

@@ -263,6 +263,9 @@ struct EigState {
             const int *tl = tiles + (size_t)2 * r * ntiles;
             const int *qm = qmask + (size_t)r * p.H;
             const int nc = ncrit[r];
+            // b = 64: the rest of the tiles and the Q update share one
+            // persistent launch (no tail of idle CUs between the two)
+            const bool fuse = p.b == 64;
             if (rest_pending) {
                 JX_HIP(hipStreamWaitEvent(s, ev_rest, 0));
                 rest_pending = false;
@@ -276,7 +279,15 @@ struct EigState {
                 }
                 JX_HIP(hipEventRecord(ev_v, s));
                 JX_HIP(hipStreamWaitEvent(sq, ev_v, 0));
-                {
+                if (fuse) {  // the rest of the tiles and the Q update in one launch
+                    ProfScope ps(PROF_UPDATE_AQ, sq, p.need_q ? (double)p.npad : 0.0, 0.0, slot, p.H, m2);
+                    if (f32)
+                        launch_update_aq32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, qm, nc, side,
+                                           p.need_q ? Q32 : nullptr, p.npad, p.npad, p.H, sq);
+                    else
+                        launch_update_aq(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, qm, nc, side,
+                                         p.need_q ? Q : nullptr, p.npad, p.npad, p.H, sq);
+                } else {
                     ProfScope ps(PROF_UPDATE_A_REST, sq, 1.0, 0.0, slot, p.H, m2);
                     if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
                     else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
@@ -284,7 +295,7 @@ struct EigState {
                 JX_HIP(hipEventRecord(ev_rest, sq));
                 rest_pending = true;
             }
-            if (p.need_q) {
+            if (p.need_q && !fuse) {
                 hipStream_t qs = sq ? sq : s;
                 {
                     ProfScope ps(PROF_UPDATE_Q, qs, (double)p.npad, 0.0, slot, p.H, m2);

@@ -196,6 +196,15 @@ void launch_scale_scatter(int m, int n, const double *G, int ldg, const double *
 // (CUs - reserve) CUs, leaving `reserve` CUs free for a kernel running beside it.
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s, int reserve = 0);
+// The rest-of-tile update (as a bounded launch_update_a with nq critical
+// tiles) and the Q update (Q may be NULL) of one round in one persistent
+// launch on at most (CUs - reserve) CUs; b = 64 only.
+void launch_update_aq(int b, int npairs, const int *pairs, double *ablk, const double *vhat, const int *flags,
+                      const int *tiles, int ntiles, const int *qmask, int nq, void *side, double *Q, int ldq,
+                      int n_rows, int reserve, hipStream_t s);
+void launch_update_aq32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
+                        const int *tiles, int ntiles, const int *qmask, int nq, void *side, float *Q, int ldq,
+                        int n_rows, int reserve, hipStream_t s);
 // FP32 versions (FP32 storage, FP32 MFMA with FP32 accumulation, V_hat in vperm32 order).
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
                        const int *tiles, int ntiles, hipStream_t s, int reserve = 0, const int *qmask = nullptr,

@@ -15,7 +15,8 @@ enum ProfKind {
     PROF_UPDATE_Q = 2,
     PROF_GEMM = 3,
     PROF_GRAM = 4,
-    PROF_UPDATE_A_REST = 5   // the other tiles, beside the next round's subproblems
+    PROF_UPDATE_A_REST = 5,  // the other tiles, beside the next round's subproblems
+    PROF_UPDATE_AQ = 6       // the other tiles and the Q update in one launch (b = 64)
 };
 
 bool prof_on();

@@ -630,6 +630,76 @@ k_update_q_bounded(const int *__restrict__ pairs, T *__restrict__ Q, int ldq,
 }
 constexpr size_t UQ_BOUNDED_LDS = 81 * 1024;  // > half of the 160 KB LDS: one workgroup per CU
 
+// The rest of every tile (as k_update_a_bounded, b = 64) and the Q update (as
+// k_update_q_bounded) of one round in one persistent kernel on a bounded set
+// of CUs, all eight waves on one item at a time.  Items 0 .. ntiles-1 are
+// tiles, ntiles .. ntiles + nqw - 1 row blocks of Q (item ntiles + j: row
+// block j mod nrb of pair j / nrb).  Workgroup b takes items b + k G (G =
+// gridDim) while they fill whole rounds; the last, partial round goes to the
+// workgroups that took one tile fewer (from ntiles mod G on), since a tile
+// costs about two row blocks.
+template <class T>
+__global__ void __launch_bounds__(512, 1)
+k_update_aq_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
+                    const int *__restrict__ flags, const int *__restrict__ tiles, int ntiles,
+                    const int *__restrict__ qmask, int nq, T *__restrict__ side, T *__restrict__ Q, int ldq,
+                    int nrb, int nqw) {
+    constexpr int B = 64;
+    extern __shared__ double lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    const int G = gridDim.x, b = blockIdx.x;
+    const int nwork = ntiles + nqw, nfull = nwork / G * G, nh = ntiles % G;
+    for (int v = b; v < nfull + G; v += G) {  // every workgroup visits the partial round's slot
+        int i = v;
+        if (v >= nfull) {  // the partial round: workgroup b takes item nfull + (b - nh) mod G
+            const int pos = (b - nh + G) % G;
+            if (pos >= nwork - nfull) break;
+            i = nfull + pos;
+        }
+        if (i < ntiles) {
+            const int p = tiles[2 * i], q = tiles[2 * i + 1];
+            const bool idp = flags[p] != 0, idq = flags[q] != 0;
+            if (idp && idq) continue;  // uniform over the workgroup
+            TileIO<T> io;
+            if (i < nq) {
+                io.rmask = qmask[i] & 15;
+                io.wmask = 15 & ~io.rmask;
+                io.side = side + (size_t)4 * i * B * B;
+            }
+            ua_tile<B, T, 512>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io);
+        } else {
+            const int j = i - ntiles, p = j / nrb, rb = j - p * nrb;
+            if (flags[p]) continue;  // V_p = I
+            uq_item<B, T, 8>(pairs, Q, ldq, vhat, p, rb, threadIdx.x, true);
+        }
+    }
+}
+
+int device_cus();
+
+template <class T>
+void launch_uaq(int b, int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
+                int ntiles, const int *qmask, int nq, T *side, T *Q, int ldq, int n_rows, int reserve, hipStream_t s) {
+    if (b != 64 || reserve <= 0 || n_rows % 128 != 0 || (nq > 0 && (!qmask || !side)) || nq > ntiles) {
+        set_error("fused update kernel: b = 64, a positive reserve, 128-row blocks of Q");
+        throw HipFail{hipErrorInvalidValue};
+    }
+    const size_t lds = std::max<size_t>(UaCfg<64, 512>::LDS_BYTES, 81 * 1024);
+    static bool attr = false;
+    if (!attr) {
+        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_aq_bounded<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+    }
+    const int nrb = n_rows / 128, nqw = Q ? nrb * npairs : 0;
+    const int nwork = std::max(ntiles, 0) + nqw;
+    if (nwork <= 0) return;
+    const int grid = std::max(1, std::min(device_cus() - reserve, nwork));
+    hipLaunchKernelGGL((k_update_aq_bounded<T>), dim3(grid), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
+                       std::max(ntiles, 0), qmask, nq, side, Q, ldq, nrb, nqw);
+    JX_LAUNCHED();
+}
+
 int device_cus();
 
 template <int B, class T>
@@ -753,6 +823,18 @@ void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const f
                        void *side) {
     launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq,
                      static_cast<float *>(side), s);
+}
+void launch_update_aq(int b, int npairs, const int *pairs, double *ablk, const double *vhat, const int *flags,
+                      const int *tiles, int ntiles, const int *qmask, int nq, void *side, double *Q, int ldq,
+                      int n_rows, int reserve, hipStream_t s) {
+    launch_uaq<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, qmask, nq, static_cast<double *>(side), Q,
+                       ldq, n_rows, reserve, s);
+}
+void launch_update_aq32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
+                        const int *tiles, int ntiles, const int *qmask, int nq, void *side, float *Q, int ldq,
+                        int n_rows, int reserve, hipStream_t s) {
+    launch_uaq<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, qmask, nq, static_cast<float *>(side), Q,
+                      ldq, n_rows, reserve, s);
 }
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s, int reserve) {

@@ -134,6 +134,14 @@ extern "C" int jacobi_profile_query(int kind, int *launches, double *total_ms, d
                     const double share = r.flops > 0.0 ? r.flops : 1.0;
                     f *= share;
                     b *= share;
+                } else if (kind == PROF_UPDATE_AQ) {  // all tiles, and Q when r.flops (its row count) > 0
+                    tile_work(fl_, r.npairs, r.m2, f, b);
+                    if (r.flops > 0.0) {
+                        double fq = 0.0, bq = 0.0;
+                        qupd_work(fl_, r.npairs, r.m2, r.flops, fq, bq);
+                        f += fq;
+                        b += bq;
+                    }
                 } else if (kind == PROF_SUBPROBLEM) {  // r.flops / r.bytes: per rotated pair
                     for (int q = 0; q < r.npairs; ++q)
                         if (!fl_[q]) {
@@ -145,7 +153,7 @@ extern "C" int jacobi_profile_query(int kind, int *launches, double *total_ms, d
                 }
                 fl += f;
                 by += b;
-            } else if (kind != PROF_UPDATE_A && kind != PROF_UPDATE_A_REST) {
+            } else if (kind != PROF_UPDATE_A && kind != PROF_UPDATE_A_REST && kind != PROF_UPDATE_AQ) {
                 fl += r.flops;
                 by += r.bytes;
             }
