@@ -231,7 +231,8 @@ __device__ const SweepTable<32, 64> kSweep32 = make_sweep_table<32, 64>();
 // block round of the same inner sweep: 16 rounds, round sh pairs k with
 // q(k, sh) = 16 + (k + sh) mod 16, so that each (ba, bb) index pair is
 // rotated once.  One wave.  S: upper triangle, entry (a, b), a <= b, at
-// S[32 a + b].  prm: two rounds of (c[16], s[16], shift[16]), shift = t a_pq
+// S[32 a + (a + b) mod 32] (rows rotated by their index, so that the lanes
+// of a round spread over the LDS banks).  prm: two rounds of (c[16], s[16], shift[16]), shift = t a_pq
 // (a_pp -= shift, a_qq += shift).  Every round's (c, s) go to the ring for
 // the follower (follow_cross); the round's 120 pair-blocks (k1 < k2: entries
 // (p1, p2), (p1, q2), (q1, p2), (q1, q2)) are disjoint, two per lane.  Lanes
@@ -240,13 +241,13 @@ __device__ const SweepTable<32, 64> kSweep32 = make_sweep_table<32, 64>();
 // of that pivot and write the next round's parameters, so a round needs one
 // wave-level ordering.
 __device__ __forceinline__ int cross_q(int k, int sh) { return 16 + ((k + sh) & 15); }
-__device__ __forceinline__ int cross_at(int a, int b) { return a < b ? 32 * a + b : 32 * b + a; }
+__device__ __forceinline__ int cross_at(int a, int b) { return 32 * (a < b ? a : b) + ((a + b) & 31); }
 __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
     constexpr int H = 16, NI = 120;
     // parameters of round 0: pivots (k, 16 + k)
     if (lane < H) {
         const int p = lane, q = cross_q(lane, 0);
-        rot_params(S[33 * p], S[33 * q], S[cross_at(p, q)], prm, lane, H);
+        rot_params(S[cross_at(p, p)], S[cross_at(q, q)], S[cross_at(p, q)], prm, lane, H);
         double *rb = vr.ring + (vr.base & (VR_DEPTH - 1)) * 2 * H;
         lds_wait_geq(vr.vdone, vr.base + 1 - VR_DEPTH, vr.fail, vr.spin);
         rb[lane] = prm[lane];
@@ -284,8 +285,8 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
         // (p of this pair, q of the next pair), read before the round's stores
         double dp = 0.0, dq = 0.0, shp = 0.0, shq = 0.0;
         if (prod) {
-            dp = S[33 * lane];
-            dq = S[33 * cross_q(kn, sh)];
+            dp = S[cross_at(lane, lane)];
+            dq = S[cross_at(cross_q(kn, sh), cross_q(kn, sh))];
             shp = cur[2 * H + lane];
             shq = cur[2 * H + kn];
         }
@@ -314,8 +315,8 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
         }
         if (prod) {
             const double app = dp - shp, aqq = dq + shq;
-            S[33 * lane] = app;
-            S[33 * cross_q(kn, sh)] = aqq;
+            S[cross_at(lane, lane)] = app;
+            S[cross_at(cross_q(kn, sh), cross_q(kn, sh))] = aqq;
             S[cross_at(lane, cross_q(lane, sh))] = 0.0;  // this round's pivot (no item holds it)
             if (sh + 1 < H) {
                 const double apq = lane < 15 ? nv[0][1] : nv[0][2];
@@ -479,7 +480,7 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
 #pragma unroll
                 for (int i = 0; i < NG; ++i) ai[i] = pkm(glob(lr[i] & 255), glob(lr[i] >> 8));
                 // S index of entry i: slot order for the full sweep, plain for the cross rounds
-                auto sx = [&](int i) { return cross ? (lr[i] & 255) * 32 + (lr[i] >> 8) : si[i]; };
+                auto sx = [&](int i) { return cross ? cross_at(lr[i] & 255, lr[i] >> 8) : si[i]; };
                 {
                     double v[NG];
 #pragma unroll
