@@ -178,11 +178,14 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
         const int kg = ch * KC + MT::kstep(st, g), col = wc0 + 16 * ct + x;
         return op_or_eye(vq + MT::vidx(kg, col, M2), idq, kg == col);
     };
-    // one column tile per wave: a chunk's V_q operands are fetched one chunk
-    // ahead, so that their global-memory latency hides behind the previous
-    // chunk (with two column tiles the registers are not there)
+    // X chunks (and, with one column tile per wave, their V_q operands) are
+    // fetched two chunks ahead, so that global-memory latency hides behind
+    // two chunks' MFMAs; chunk ch is staged in LDS buffer ch mod 2 after chunk
+    // ch - 1's products (with two column tiles the registers for V_q are not
+    // there: those are loaded per k-step)
     constexpr bool PF = CT == 1;
-    T bnext[KC / 4];
+    T reg2[U::PER];
+    T bnext[KC / 4], bnext2[KC / 4];
     if (active) {
         fetch(0, reg);
         if constexpr (PF) {
@@ -190,19 +193,28 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
             for (int st = 0; st < KC / 4; ++st) bnext[st] = vqk(0, st, 0);
         }
         stage(0, lds, reg);
+        if (U::NCH > 1) {
+            fetch(KC, reg);  // reg: chunk 1 until it is staged
+            if constexpr (PF) {
+#pragma unroll
+                for (int st = 0; st < KC / 4; ++st) bnext2[st] = vqk(1, st, 0);
+            }
+        }
     }
     __syncthreads();
     for (int ch = 0; ch < U::NCH; ++ch) {
         T *xs = lds + (size_t)(ch & 1) * KC * U::XLD;
         T bcur[KC / 4];
 #pragma unroll
-        for (int st = 0; st < KC / 4; ++st) bcur[st] = bnext[st];
-        if (active && ch + 1 < U::NCH) {
-            const int k0 = (ch + 1) * KC;
-            fetch(k0, reg);
+        for (int st = 0; st < KC / 4; ++st) {
+            bcur[st] = bnext[st];
+            bnext[st] = bnext2[st];
+        }
+        if (active && ch + 2 < U::NCH) {
+            fetch((ch + 2) * KC, reg2);
             if constexpr (PF) {
 #pragma unroll
-                for (int st = 0; st < KC / 4; ++st) bnext[st] = vqk(ch + 1, st, 0);
+                for (int st = 0; st < KC / 4; ++st) bnext2[st] = vqk(ch + 2, st, 0);
             }
         }
         if constexpr (PF) {
@@ -231,8 +243,9 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
             }
         }
         if (active && ch + 1 < U::NCH) {
-            const int k0 = (ch + 1) * KC;
-            stage(k0, lds + (size_t)((ch + 1) & 1) * KC * U::XLD, reg);
+            stage((ch + 1) * KC, lds + (size_t)((ch + 1) & 1) * KC * U::XLD, reg);
+#pragma unroll
+            for (int m = 0; m < U::PER; ++m) reg[m] = reg2[m];
         }
         __syncthreads();
     }
@@ -557,15 +570,18 @@ __device__ __forceinline__ void uq_item(const int *__restrict__ pairs, T *__rest
     auto colof = [&](int k) { return k < B ? I * B + k : J * B + (k - B); };
 
     if (active) {
-        T an[IT], bn[JT];
-        {
-            const int k = MT::kstep(0, g);
+        // operands of step st: V_p rows and Q columns (contraction index k),
+        // fetched a step ahead
+        auto fetch = [&](int st, T *a, T *b) {
+            const int k = 16 * (st >> 2) + MT::kstep(st & 3, g);
             const T *qc = Q + (size_t)colof(k) * ldq + r0;
 #pragma unroll
-            for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
+            for (int i = 0; i < IT; ++i) a[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
 #pragma unroll
-            for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
-        }
+            for (int j = 0; j < JT; ++j) b[j] = qc[16 * j + x];
+        };
+        T an[IT], bn[JT];
+        fetch(0, an, bn);
 #pragma unroll 4
         for (int st = 0; st < M2 / 4; ++st) {
             T a_[IT], b_[JT];
@@ -573,14 +589,7 @@ __device__ __forceinline__ void uq_item(const int *__restrict__ pairs, T *__rest
             for (int i = 0; i < IT; ++i) a_[i] = an[i];
 #pragma unroll
             for (int j = 0; j < JT; ++j) b_[j] = bn[j];
-            if (st + 1 < M2 / 4) {
-                const int k = 16 * ((st + 1) >> 2) + MT::kstep((st + 1) & 3, g);
-                const T *qc = Q + (size_t)colof(k) * ldq + r0;
-#pragma unroll
-                for (int i = 0; i < IT; ++i) an[i] = vp[MT::vidx(k, HALF * wi + 16 * i + x, M2)];
-#pragma unroll
-                for (int j = 0; j < JT; ++j) bn[j] = qc[16 * j + x];
-            }
+            if (st + 1 < M2 / 4) fetch(st + 1, an, bn);
 #pragma unroll
             for (int i = 0; i < IT; ++i)
 #pragma unroll
