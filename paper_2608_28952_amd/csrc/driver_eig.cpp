@@ -149,7 +149,10 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     p.off_force = wb.add(sizeof(int) * (size_t)p.R * p.H);
     p.off_tiles = wb.add(sizeof(int) * (size_t)p.R * p.H * (p.H - 1));  // per round, critical tiles first
     p.off_qmask = wb.add(sizeof(int) * (size_t)p.R * p.H);               // per critical tile: its next-round blocks
-    p.off_side = wb.add(sizeof(double) * 4 * (size_t)p.H * p.b * p.b);   // their originals (FP64 or FP32)
+    p.off_side = wb.add(sizeof(double) * 8 * (size_t)p.H * p.b * p.b);   // their originals, 2 rounds (FP64 or FP32)
+    p.off_smap = wb.add(sizeof(int) * 4 * ((size_t)p.R * p.H * (p.H - 1) / 2 + 1));  // where a tile's blocks are copied
+    p.off_xcopy = wb.add(sizeof(int) * 8 * (size_t)p.R * p.H);          // other copies per round
+    p.off_copy0 = wb.add(sizeof(int) * 8 * (size_t)p.H);                // copies before a sweep's round 0
     p.off_partial = wb.add(sizeof(double) * 2 * nb);
     p.off_scal = wb.add(sizeof(double) * 8);
     p.off_w = wb.add(sizeof(double) * npad);
@@ -172,8 +175,10 @@ struct EigState {
     char *ws;
     hipStream_t s;
     double *ablk, *Q, *V, *partial, *scal;
-    int *flags, *pairs, *force, *tiles, *qmask;
-    void *side;
+    int *flags, *pairs, *force, *tiles, *qmask, *smap, *xcopy, *copy0;
+    int ncopy0 = 0;
+    std::vector<int> nxcopy;
+    char *side;  // two rounds' copies of the critical blocks' originals
     float *ablk32 = nullptr, *Q32 = nullptr, *V32 = nullptr;
     bool f32 = false;  // current phase works on the FP32 copies
     double *h_scal;  // pinned
@@ -201,6 +206,11 @@ struct EigState {
     int *h_flaglog = nullptr;
     int flog_cap = 0, flog_count = 0, flog_base = 0;
 
+    // copies of round r's critical blocks' originals (4 blocks per critical
+    // tile), in the current precision; rounds alternate between two buffers
+    void *sidebuf(int r) const {
+        return side + (size_t)(r & 1) * 4 * p.H * p.b * p.b * (f32 ? sizeof(float) : sizeof(double));
+    }
     double *Vbuf(int r) const { return V + (size_t)(r % NVBUF) * p.H * (2 * p.b) * (2 * p.b); }
     float *Vbuf32(int r) const { return V32 + (size_t)(r % NVBUF) * p.H * (2 * p.b) * (2 * p.b); }
     int *Fbuf(int r) const { return flags + (size_t)(r % NVBUF) * p.H; }
@@ -224,6 +234,10 @@ struct EigState {
         const double k1_flops = (double)p.H * std::max(1, inner) * (m2 - 1) *
                                 (24.0 * hi * (hi - 1) / 2 + 6.0 * m2 * hi);
         const double k1_bytes = (double)p.H * 6.0 * p.b * p.b * sizeof(double);
+        // round 0's critical blocks as they stand (later rounds' copies are
+        // written by the round before, as it produces those blocks)
+        if (f32) launch_copy_blocks32(p.b, ablk32, copy0, ncopy0, sidebuf(0), s);
+        else launch_copy_blocks(p.b, ablk, copy0, ncopy0, sidebuf(0), s);
         for (int r = 0; r < p.R; ++r) {
             const int *pr = pairs + (size_t)2 * r * p.H;
             SubArgs a{};
@@ -274,23 +288,35 @@ struct EigState {
                 {
                     // one block of a tile: 3/8 of its products (b = 64), 3/4 (b = 32)
                     ProfScope ps(PROF_UPDATE_A, s, (p.b == 64 ? 0.375 : 0.75) * nc / ntiles, 0.0, slot, p.H, m2);
-                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, side);
-                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, side);
+                    void *sd = sidebuf(r);
+                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, sd);
+                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, nc, s, UA_QUAD, qm, nc, sd);
                 }
                 JX_HIP(hipEventRecord(ev_v, s));
                 JX_HIP(hipStreamWaitEvent(sq, ev_v, 0));
+                // this round's tiles also write the copies of the next round's
+                // critical blocks; blocks they do not produce are copied after them
+                void *sd = sidebuf(r), *sn = r + 1 < p.R ? sidebuf(r + 1) : nullptr;
+                const int *sm = smap + 4 * (size_t)r * ntiles;
                 if (fuse) {  // the rest of the tiles and the Q update in one launch
                     ProfScope ps(PROF_UPDATE_AQ, sq, p.need_q ? (double)p.npad : 0.0, 0.0, slot, p.H, m2);
                     if (f32)
-                        launch_update_aq32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, qm, nc, side,
+                        launch_update_aq32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, qm, nc, sd, sn, sm,
                                            p.need_q ? Q32 : nullptr, p.npad, p.npad, p.H, sq);
                     else
-                        launch_update_aq(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, qm, nc, side,
+                        launch_update_aq(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, qm, nc, sd, sn, sm,
                                          p.need_q ? Q : nullptr, p.npad, p.npad, p.H, sq);
                 } else {
                     ProfScope ps(PROF_UPDATE_A_REST, sq, 1.0, 0.0, slot, p.H, m2);
-                    if (f32) launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
-                    else launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, side);
+                    if (f32)
+                        launch_update_a32(p.b, p.H, pr, ablk32, Vbuf32(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, sd,
+                                          sn, sm);
+                    else
+                        launch_update_a(p.b, p.H, pr, ablk, Vbuf(r), Fbuf(r), tl, ntiles, sq, p.H, qm, nc, sd, sn, sm);
+                }
+                if (sn && nxcopy[r] > 0) {
+                    if (f32) launch_copy_blocks32(p.b, ablk32, xcopy + (size_t)8 * r * p.H, nxcopy[r], sn, sq);
+                    else launch_copy_blocks(p.b, ablk, xcopy + (size_t)8 * r * p.H, nxcopy[r], sn, sq);
                 }
                 JX_HIP(hipEventRecord(ev_rest, sq));
                 rest_pending = true;
@@ -381,6 +407,9 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     st.tiles = reinterpret_cast<int *>(ws + p.off_tiles);
     st.qmask = reinterpret_cast<int *>(ws + p.off_qmask);
     st.side = ws + p.off_side;
+    st.smap = reinterpret_cast<int *>(ws + p.off_smap);
+    st.xcopy = reinterpret_cast<int *>(ws + p.off_xcopy);
+    st.copy0 = reinterpret_cast<int *>(ws + p.off_copy0);
     st.partial = reinterpret_cast<double *>(ws + p.off_partial);
     st.scal = reinterpret_cast<double *>(ws + p.off_scal);
     st.h_scal = pin.ptr;
@@ -446,6 +475,67 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     if (!ht.empty())
         JX_HIP(hipMemcpyAsync(st.tiles, ht.data(), sizeof(int) * ht.size(), hipMemcpyHostToDevice, s));
     JX_HIP(hipMemcpyAsync(st.qmask, hq.data(), sizeof(int) * hq.size(), hipMemcpyHostToDevice, s));
+    // Copies of the critical blocks' originals (the critical kernel reads
+    // them, and writes the blocks in place).  Round r + 1's critical blocks
+    // are pairs of round r + 2, so within a sweep round r's tiles produce
+    // them: smap[r][tile][quad] names the slot (4 ci + quad of the next
+    // round's critical tile ci) the quadrant's new value is also written to
+    // (-1: none).  A block outside round r's tiles (a placeholder pair of
+    // round r, never rotated) is copied after them (xcopy); round 0's
+    // blocks are copied at each sweep's start (copy0).
+    {
+        const int ntiles = p.H * (p.H - 1) / 2;
+        std::vector<int> hsm(4 * ((size_t)p.R * ntiles + 1), -1), hx((size_t)8 * p.R * p.H, 0), hc0;
+        st.nxcopy.assign(p.R, 0);
+        std::vector<int> pos(p.N, 0), half(p.N, 0), tix((size_t)p.H * p.H, -1);
+        auto block_of = [&](int rr, int ci, int quad) {  // (row, column) block of quadrant quad of crit tile ci
+            const int lo = ht[2 * ((size_t)rr * ntiles + ci)], hi = ht[2 * ((size_t)rr * ntiles + ci) + 1];
+            return std::make_pair(hp[2 * ((size_t)rr * p.H + lo) + (quad >> 1)],
+                                  hp[2 * ((size_t)rr * p.H + hi) + (quad & 1)]);
+        };
+        for (int r = 0; r + 1 < p.R; ++r) {
+            for (int k = 0; k < p.H; ++k) {
+                pos[hp[2 * ((size_t)r * p.H + k)]] = k;
+                pos[hp[2 * ((size_t)r * p.H + k) + 1]] = k;
+                half[hp[2 * ((size_t)r * p.H + k)]] = 0;
+                half[hp[2 * ((size_t)r * p.H + k) + 1]] = 1;
+            }
+            for (int i = 0; i < ntiles; ++i)
+                tix[(size_t)ht[2 * ((size_t)r * ntiles + i)] * p.H + ht[2 * ((size_t)r * ntiles + i) + 1]] = i;
+            const int rn = r + 1;
+            for (int ci = 0; ci < st.ncrit[rn]; ++ci)
+                for (int quad = 0; quad < 4; ++quad) {
+                    if (!((hq[(size_t)rn * p.H + ci] >> quad) & 1)) continue;
+                    const auto bl = block_of(rn, ci, quad);
+                    const int X = bl.first, Y = bl.second, slot = 4 * ci + quad;
+                    const int a = pos[X], b = pos[Y];
+                    if (a != b) {
+                        const int i = tix[(size_t)std::min(a, b) * p.H + std::max(a, b)];
+                        const int h2 = a < b ? half[X] : half[Y], c2 = a < b ? half[Y] : half[X];
+                        const int q2 = 2 * h2 + c2;
+                        hsm[4 * ((size_t)r * ntiles + i) + q2] = slot;
+                    } else {
+                        int &n = st.nxcopy[r];
+                        hx[(size_t)8 * r * p.H + 2 * n] = (int)ublk(std::min(X, Y), std::max(X, Y));
+                        hx[(size_t)8 * r * p.H + 2 * n + 1] = slot;
+                        ++n;
+                    }
+                }
+        }
+        for (int ci = 0; ci < st.ncrit[0]; ++ci)
+            for (int quad = 0; quad < 4; ++quad) {
+                if (!((hq[ci] >> quad) & 1)) continue;
+                const auto bl = block_of(0, ci, quad);
+                hc0.push_back((int)ublk(std::min(bl.first, bl.second), std::max(bl.first, bl.second)));
+                hc0.push_back(4 * ci + quad);
+            }
+        st.ncopy0 = (int)hc0.size() / 2;
+        JX_HIP(hipMemcpyAsync(st.smap, hsm.data(), sizeof(int) * hsm.size(), hipMemcpyHostToDevice, s));
+        JX_HIP(hipMemcpyAsync(st.xcopy, hx.data(), sizeof(int) * hx.size(), hipMemcpyHostToDevice, s));
+        if (!hc0.empty())
+            JX_HIP(hipMemcpyAsync(st.copy0, hc0.data(), sizeof(int) * hc0.size(), hipMemcpyHostToDevice, s));
+        JX_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    }
 
     // A -> upper block storage; Q = I or Q0 (then A <- Q0^T A Q0)
     double *A0 = p.refine ? reinterpret_cast<double *>(ws + p.off_a0) : nullptr;
@@ -604,6 +694,7 @@ int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *
     const size_t o_t = wb.add(sizeof(int) * (size_t)H * (H - 1) + sizeof(int));
     const size_t o_m = wb.add(sizeof(int) * (size_t)H * (H - 1) / 2 + sizeof(int));
     const size_t o_s = wb.add(sizeof(double) * 4 * (size_t)b * b * (H * (H - 1) / 2 + 1));
+    const size_t o_l = wb.add(sizeof(int) * 8 * (size_t)(H * (H - 1) / 2 + 1));
     buf.alloc(wb.total());
     double *ablk = reinterpret_cast<double *>(buf.ptr + o_ab);
     double *V = reinterpret_cast<double *>(buf.ptr + o_v);
@@ -630,6 +721,18 @@ int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *
     launch_pack_sym(n, n, b, dA, n, 'U', ablk, s);
     launch_vperm_from_colmajor(H, m2, dV, V, s);
     launch_write_pair_blocks(H, b, pairs, dD, ablk, s);
+    // copies of the critical blocks' originals, which the critical kernel reads
+    std::vector<int> hl;
+    for (int i = 0; i < nq; ++i)
+        for (int quad = 0; quad < 4; ++quad) {
+            if (!((hq[i] >> quad) & 1)) continue;
+            const int X = hPairs[2 * ht[2 * i] + (quad >> 1)], Y = hPairs[2 * ht[2 * i + 1] + (quad & 1)];
+            hl.push_back((int)ublk(std::min(X, Y), std::max(X, Y)));
+            hl.push_back(4 * i + quad);
+        }
+    int *lst = reinterpret_cast<int *>(buf.ptr + o_l);
+    if (!hl.empty()) JX_HIP(hipMemcpyAsync(lst, hl.data(), sizeof(int) * hl.size(), hipMemcpyHostToDevice, s));
+    launch_copy_blocks(b, ablk, lst, (int)hl.size() / 2, side, s);
     launch_update_a(b, H, pairs, ablk, V, flags, tiles, nq, s, UA_QUAD, qmask, nq, side);
     launch_update_a(b, H, pairs, ablk, V, flags, tiles, ntiles, s, 1, qmask, nq, side);
     if (dQ) launch_update_q(b, H, pairs, dQ, n, n, V, flags, s);

@@ -172,15 +172,23 @@ size_t batched_lds_bytes(int bs, int m2); // dynamic LDS of the class kernel
 
 // Fused two-sided update of the off-diagonal pair tiles of one round:
 // A[p,q] <- V_p^T A[p,q] V_q for p < q (pair indices of the round).
-// reserve > 0: on at most (CUs - reserve) CUs.  UA_QUAD: one workgroup per
-// tile, only the blocks qmask[i] of tile i (bit 2 h + c: row block h of pair
-// p, column block c of pair q), their originals saved to side (4 blocks per
-// tile).  A bounded launch with nq > 0 then does the rest of its first nq
-// tiles (same qmask and side) and the other tiles whole.
+// reserve > 0: on at most (CUs - reserve) CUs.  UA_QUAD: only the blocks
+// qmask[i] of tile i (bit 2 h + c: row block h of pair p, column block c of
+// pair q), read from copies of their originals at side + (4 i + 2 h + c) b^2
+// (made beforehand, e.g. by launch_copy_blocks) and written in place.  A
+// bounded launch with nq > 0 then does the rest of its first nq tiles (same
+// qmask and side) and the other tiles whole.  snext / smap (bounded launch):
+// quadrant quad of tile i, once written, is also copied to snext + slot b^2,
+// slot = smap[4 i + quad] (negative: none).
 constexpr int UA_QUAD = -2;
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
                      const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve = 0,
-                     const int *qmask = nullptr, int nq = 0, void *side = nullptr);
+                     const int *qmask = nullptr, int nq = 0, void *side = nullptr, void *snext = nullptr,
+                     const int *smap = nullptr);
+// Block copies: block lst[2 j] (slot of the upper block storage) of ablk to
+// side + lst[2 j + 1] b^2, j < n.
+void launch_copy_blocks(int b, const double *ablk, const int *lst, int n, void *side, hipStream_t s);
+void launch_copy_blocks32(int b, const float *ablk, const int *lst, int n, void *side, hipStream_t s);
 // Gram blocks of the one-sided SVD: ahat[p] = G(:, [I,J])^T G(:, [I,J]) over the
 // first m_rows rows (nchunks equal row chunks, partial sums added in order).
 void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, int m_rows, int nchunks,
@@ -200,15 +208,15 @@ void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, in
 // tiles) and the Q update (Q may be NULL) of one round in one persistent
 // launch on at most (CUs - reserve) CUs; b = 64 only.
 void launch_update_aq(int b, int npairs, const int *pairs, double *ablk, const double *vhat, const int *flags,
-                      const int *tiles, int ntiles, const int *qmask, int nq, void *side, double *Q, int ldq,
-                      int n_rows, int reserve, hipStream_t s);
+                      const int *tiles, int ntiles, const int *qmask, int nq, void *side, void *snext,
+                      const int *smap, double *Q, int ldq, int n_rows, int reserve, hipStream_t s);
 void launch_update_aq32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
-                        const int *tiles, int ntiles, const int *qmask, int nq, void *side, float *Q, int ldq,
-                        int n_rows, int reserve, hipStream_t s);
+                        const int *tiles, int ntiles, const int *qmask, int nq, void *side, void *snext,
+                        const int *smap, float *Q, int ldq, int n_rows, int reserve, hipStream_t s);
 // FP32 versions (FP32 storage, FP32 MFMA with FP32 accumulation, V_hat in vperm32 order).
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
                        const int *tiles, int ntiles, hipStream_t s, int reserve = 0, const int *qmask = nullptr,
-                       int nq = 0, void *side = nullptr);
+                       int nq = 0, void *side = nullptr, void *snext = nullptr, const int *smap = nullptr);
 void launch_update_q32(int b, int npairs, const int *pairs, float *Q, int ldq, int n_rows, const float *vhat,
                        const int *flags, hipStream_t s, int reserve = 0);
 

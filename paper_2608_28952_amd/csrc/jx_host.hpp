@@ -50,7 +50,7 @@ struct PinnedScalars {
 struct EigPlan {
     int n, npad, b, N, H, R;
     bool vectors, refine, mixed, need_q;
-    size_t off_ablk, off_q, off_v, off_flags, off_pairs, off_force, off_tiles, off_qmask, off_side, off_partial,
+    size_t off_ablk, off_q, off_v, off_flags, off_pairs, off_force, off_tiles, off_qmask, off_side, off_smap, off_xcopy, off_copy0, off_partial,
         off_scal, off_w, off_rank, off_a0, off_t1, off_t2, off_ablk32, off_q32, off_v32;
     size_t total;
 };

@@ -67,17 +67,21 @@ struct UaCfg {
 // Which blocks of a tile are read from and written to where.  Quadrant
 // (h, c) = block (row block h of pair p, column block c of pair q) has bit
 // 2 h + c.  A tile's blocks that the next round's subproblems read (its
-// "critical" quadrants) are computed first and alone; the rest of the tile
-// later, from the saved originals of those blocks:
+// "critical" quadrants) are computed first and alone, from copies of their
+// originals made beforehand (the critical kernel writes them in place); the
+// rest of the tile later, from the same copies:
 //   wmask  quadrants written back (the others are computed or not, but left)
 //   rmask  quadrants whose input block comes from side + quad B^2, not ablk
-//   save   before a quadrant is written, its original goes to side + quad B^2
-// (side holds four blocks of B x B, each stored as its block is in ablk).
+//   snext, smap  quadrant quad written back also goes to snext + slot B^2,
+//          slot = smap[quad] (negative: none): the copies the next round's
+//          critical kernel reads
+// (side blocks are B x B, each stored as its block is in ablk).
 template <class T>
 struct TileIO {
     int wmask = 15, rmask = 0;
-    bool save = false;
     T *side = nullptr;
+    T *snext = nullptr;
+    const int *smap = nullptr;  // 4 slots
 };
 
 // Fetch the PER values of X chunk `ch` (columns c0 .. c0+KC-1 of one block
@@ -311,41 +315,56 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
             const int quad = 2 * h + c;
             if (!hact || !((io.wmask >> quad) & 1)) continue;
             T *dst = ablk + ublk(R < Cc ? R : Cc, R < Cc ? Cc : R) * (size_t)(B * B);
-            T *sv = io.save ? io.side + (size_t)quad * B * B : nullptr;
+            const int slot = io.smap ? io.smap[quad] : -1;
+            T *nx = io.snext && slot >= 0 ? io.snext + (size_t)slot * B * B : nullptr;
             // every read of the tile's inputs ended at GEMM 1's last barrier
             for (int e = tid; e < B * B; e += NTH) {
                 int rl, cl;
                 if (R < Cc) { rl = e % B; cl = e / B; }
                 else { cl = e % B; rl = e / B; }  // stored (Cc, R): element (cl, rl)
-                if (sv) sv[e] = dst[e];
-                dst[e] = os[(c * B + cl) * U::OLD + rl];
+                const T v = os[(c * B + cl) * U::OLD + rl];
+                dst[e] = v;
+                if (nx) nx[e] = v;
             }
         }
         __syncthreads();
     }
 }
 
-// One block of tile (p, q) for b = 64 in FP64: row half h, column half c, by
-// 512 threads, latency first.  One round of global loads brings the whole
-// input tile (to LDS), the V_q operands and the half of V_p that GEMM 2 reads
-// (each value once, to LDS after GEMM 1).  Wave w = 4 rh + ct computes T's
-// column tile ct (16 columns of half c) for rows 64 rh .. 64 rh + 63 (GEMM 1:
-// 32 k-steps x 4 row tiles) and hands it over through LDS in GEMM 2's operand
-// order; GEMM 2 gives wave w output row tiles 2 rh, 2 rh + 1 of row half h in
-// column tile ct.  Two waves per SIMD: one wave's LDS waits are the other's
-// MFMA time.  The original block is saved to `side` and the new one written
-// in place.  `lds` holds 128 x 129 doubles.
+// Workgroups per critical block (b = 64, FP64): each owns 64 / CRIT_SPLIT of
+// the block's columns.  The critical blocks run while the rest of the GPU
+// waits for them, so their products are spread over more CUs.
+constexpr int CRIT_SPLIT = 4;
+
+// Columns part * 64 / NS .. of one block of tile (p, q) for b = 64 in FP64:
+// row half h, column half c, by 512 threads, latency first.  One round of
+// global loads brings the whole input tile (to LDS; the block itself from
+// its copy `orig`, which no workgroup writes), the V_q operands of the
+// part's columns and the half of V_p that GEMM 2 reads (each value once, to
+// LDS after GEMM 1).  Wave w = CTW rg + ctl (CTW = 4 / NS column tiles of 16)
+// computes T's column tile ctl for row tiles RTW rg .. (GEMM 1) and hands it
+// over through LDS in GEMM 2's operand order; GEMM 2 gives the waves the
+// output tiles (row tile ot of half h, column tile ctl).  Two waves per SIMD:
+// one wave's LDS waits are the other's MFMA time.  The part's columns of the
+// new block are written in place.  `lds` holds 128 x 129 doubles.
+template <int NS>
 __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double *__restrict__ ablk,
                                            const double *__restrict__ vhat, int p, int q, bool idp, bool idq,
-                                           int h, int c, double *__restrict__ side, double *lds) {
+                                           int h, int c, int part, const double *__restrict__ orig, double *lds) {
     using T = double;
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int B = 64, M2 = 128, XLD = M2 + 1, NTH = 512, PB = B * B / NTH;
-    constexpr int VH = M2 * B;  // V_p(:, half h): 128 x 64
+    constexpr int VH = M2 * B;           // V_p(:, half h): 128 x 64
+    constexpr int CTW = 4 / NS;          // column tiles of this part
+    constexpr int RW = 8 / CTW;          // row groups of GEMM 1
+    constexpr int RTW = 8 / RW;          // row tiles per wave in GEMM 1
+    constexpr int NOT = 4 * CTW;         // output tiles of GEMM 2
+    constexpr int OTW = NOT >= 8 ? NOT / 8 : 1;  // output tiles per working wave
+    static_assert(NS == 1 || NS == 2 || NS == 4, "split of a critical block");
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, x = lane & 15;
-    const int ct = w & 3, rh = w >> 2;
+    const int ctl = w % CTW, rg = w / CTW;
     const int Rr[2] = {pairs[2 * p], pairs[2 * p + 1]};
     const int Cq[2] = {pairs[2 * q], pairs[2 * q + 1]};
     const T *vp = vhat + (size_t)p * M2 * M2;
@@ -359,11 +378,12 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double
     T xr[4][PB];
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-        const T *src = blk(bb >> 1, bb & 1);
+        const T *src = bb == 2 * h + c ? orig : blk(bb >> 1, bb & 1);
 #pragma unroll
         for (int m = 0; m < PB; ++m) xr[bb][m] = src[tid + NTH * m];
     }
-    const int col = 64 * c + 16 * ct + x;  // this lane's column of T
+    const int c0 = 16 * CTW * part;              // first column of this part within the block
+    const int col = 64 * c + c0 + 16 * ctl + x;  // this lane's column of T
     T bq[M2 / 4];
 #pragma unroll
     for (int s = 0; s < M2 / 4; ++s) {
@@ -393,94 +413,127 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double
     }
     __syncthreads();
 
-    // GEMM 1: T(64 rh .. 64 rh + 63, col tile) = X(those rows, :) V_q(:, col tile)
-    acc_t acc[4];
+    // GEMM 1: T(row tiles RTW rg .., col tile ctl) = X(those rows, :) V_q(:, col tile)
+    acc_t acc[RTW];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+    for (int rt = 0; rt < RTW; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < M2 / 4; ++s) {
         const int kl = 16 * (s >> 2) + MT::kstep(s & 3, g);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) acc[rt] = MT::mma(lds[kl * XLD + 64 * rh + 16 * rt + x], bq[s], acc[rt]);
+        for (int rt = 0; rt < RTW; ++rt)
+            acc[rt] = MT::mma(lds[kl * XLD + 16 * (RTW * rg + rt) + x], bq[s], acc[rt]);
     }
     __syncthreads();  // X no longer read: V_p's half and T take its place
-    // T in GEMM 2's B-operand order: step (rt, s4) of column tile ct at
-    // tops[((4 rt + s4) 4 + ct) 64 + lane] = T(16 rt + rrow(g, s4), 16 ct + x),
-    // which is component s4 of this wave's acc[rt - 4 rh]
+    // T in GEMM 2's B-operand order: step (rt, s4) of column tile ctl at
+    // tops[((4 rt + s4) CTW + ctl) 64 + lane] = T(16 rt + rrow(g, s4), ..),
+    // which is component s4 of this wave's acc[rt - RTW rg]
     T *vps = lds;       // V_p(:, half h), vperm order of a 128 x 64 matrix
-    T *tops = lds + VH; // 8 x 4 x 4 x 64 values
+    T *tops = lds + VH; // 8 x 4 x CTW x 64 values
 #pragma unroll
     for (int m = 0; m < VH / NTH; ++m) vps[tid + NTH * m] = vr[m];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int rt = 0; rt < RTW; ++rt)
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) tops[((4 * (4 * rh + rt) + s4) * 4 + ct) * 64 + lane] = acc[rt][s4];
+        for (int s4 = 0; s4 < 4; ++s4)
+            tops[((4 * (RTW * rg + rt) + s4) * CTW + ctl) * 64 + lane] = acc[rt][s4];
     __syncthreads();
 
-    // GEMM 2: out(row tiles 2 rh, 2 rh + 1 of half h, col tile) = V_p(:, ..)^T T.
-    // Output row tile ot's operand for step (rt, s4) is
-    // vperm(16 rt + rrow(g, s4), 16 ot + x, 64) = 256 (4 rt + s4) + 64 ot + lane
-    acc_t o[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
+    // GEMM 2: output tile n = OTW w + j (row tile ot = n / CTW of half h,
+    // column tile n mod CTW) = V_p(:, ..)^T T.  Row tile ot's operand for step
+    // (rt, s4) is vperm(16 rt + rrow(g, s4), 16 ot + x, 64) = 256 (4 rt + s4) + 64 ot + lane
+    const bool g2 = OTW * w < NOT;  // waves with output tiles
+    acc_t o[OTW];
 #pragma unroll
-    for (int rt = 0; rt < M2 / 16; ++rt)
+    for (int j = 0; j < OTW; ++j) o[j] = acc_t{0, 0, 0, 0};
+    if (g2) {
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            const T bt = tops[((4 * rt + s4) * 4 + ct) * 64 + lane];
+        for (int rt = 0; rt < M2 / 16; ++rt)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                o[j] = MT::mma(vps[256 * (4 * rt + s4) + 64 * (2 * rh + j) + lane], bt, o[j]);
-        }
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int j = 0; j < OTW; ++j) {
+                    const int n = OTW * w + j, ot = n / CTW, cn = n % CTW;
+                    o[j] = MT::mma(vps[256 * (4 * rt + s4) + 64 * ot + lane],
+                                   tops[((4 * rt + s4) * CTW + cn) * 64 + lane], o[j]);
+                }
+    }
     __syncthreads();  // V_p's half and T no longer read
-    T *os = lds;  // [column 0 .. 63][row 0 .. 63], stride B + 1
+    T *os = lds;  // [part column 0 .. 16 CTW - 1][row 0 .. 63], stride B + 1
+    if (g2) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < OTW; ++j) {
+            const int n = OTW * w + j, ot = n / CTW, cn = n % CTW;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) os[(16 * ct + x) * (B + 1) + 16 * (2 * rh + j) + MT::rrow(g, v)] = o[j][v];
+            for (int v = 0; v < 4; ++v) os[(16 * cn + x) * (B + 1) + 16 * ot + MT::rrow(g, v)] = o[j][v];
+        }
+    }
     __syncthreads();
 
-    // block (Rr[h], Cq[c]): original to side, new value in place
+    // columns c0 .. c0 + 16 CTW - 1 of block (Rr[h], Cq[c]), in place
     const int R = Rr[h], C = Cq[c];
     T *dst = blk(h, c);
-    T *sv = side + (size_t)(2 * h + c) * B * B;
+    constexpr int PW = 16 * CTW;  // columns of the part
 #pragma unroll
-    for (int m = 0; m < PB; ++m) {
-        const int e = tid + NTH * m;
-        const int rl = R < C ? e % B : e / B, cl = R < C ? e / B : e % B;  // element (rl, cl) of block (R, C)
-        sv[e] = dst[e];
-        dst[e] = os[cl * (B + 1) + rl];
+    for (int m = 0; m < B * PW / NTH; ++m) {
+        const int e = tid + NTH * m;  // element (rl, c0 + cl) of block (R, C)
+        const int rl = R < C ? e % B : e / PW, cl = R < C ? e / B : e % PW;
+        const int at = R < C ? (c0 + cl) * B + rl : rl * B + c0 + cl;
+        dst[at] = os[cl * (B + 1) + rl];
     }
 }
 
-// Only the critical quadrants qmask[i] of tile i, one tile per workgroup:
-// their original blocks are saved to side + 4 i B^2 (+ quad B^2) and the new
-// ones written in place.  Blocks within one column half (b = 64) take T for
-// that half only, and V_p^T T for the row halves written: 3/8 of a tile's
-// products for one block (FP64: the whole tile staged in LDS at once).  Two
-// opposite blocks, and b = 32, take all of T.
+// A tile whose two rotations are both skipped does not change; the copies
+// its blocks owe the next round (smap: 4 slots, as in TileIO) are made from
+// ablk.
+template <int B, class T, int NTH>
+__device__ __forceinline__ void copy_skipped(const int *__restrict__ pairs, const T *__restrict__ ablk, int p,
+                                             int q, T *__restrict__ snext, const int *smap, int tid) {
+#pragma unroll
+    for (int quad = 0; quad < 4; ++quad) {
+        const int slot = smap[quad];
+        if (slot < 0) continue;
+        const int R = pairs[2 * p + (quad >> 1)], C = pairs[2 * q + (quad & 1)];
+        const T *src = ablk + ublk(R < C ? R : C, R < C ? C : R) * (size_t)(B * B);
+        T *dst = snext + (size_t)slot * B * B;
+        for (int e = tid; e < B * B; e += NTH) dst[e] = src[e];
+    }
+}
+
+// Only the critical quadrants qmask[i] of tile i, one tile per workgroup
+// (CRIT_SPLIT workgroups for the one-block FP64 case of b = 64), from copies
+// of their originals at side + 4 i B^2 (+ quad B^2), made beforehand; the
+// new blocks are written in place.  Blocks within one column half (b = 64)
+// take T for that half only, and V_p^T T for the row halves written: 3/8 of
+// a tile's products for one block (FP64: the whole tile staged in LDS at
+// once).  Two opposite blocks, and b = 32, take all of T.
 template <int B, class T>
 __global__ void __launch_bounds__(512, 1)
 k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
                 const int *__restrict__ flags, const int *__restrict__ tiles, const int *__restrict__ qmask,
-                T *__restrict__ side) {
+                const T *__restrict__ side) {
     extern __shared__ double lds_raw[];
-    const int i = blockIdx.x;
+    constexpr int NS = B == 64 && std::is_same<T, double>::value ? CRIT_SPLIT : 1;
+    const int i = blockIdx.x / NS, part = blockIdx.x % NS;
     const int p = tiles[2 * i], q = tiles[2 * i + 1];
     const bool idp = flags[p] != 0, idq = flags[q] != 0;
     if (idp && idq) return;  // the tile does not change (and its rest is skipped the same way)
     TileIO<T> io;
     io.wmask = qmask[i] & 15;
-    io.save = true;
-    io.side = side + (size_t)4 * i * B * B;
+    io.rmask = io.wmask;
+    io.side = const_cast<T *>(side) + (size_t)4 * i * B * B;
     T *lds = reinterpret_cast<T *>(lds_raw);
     const int m = io.wmask;
     if constexpr (B == 64 && std::is_same<T, double>::value) {
-        if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c, on all eight waves
+        if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c
             const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
-            ua_block64(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, io.side, lds);
+            ua_block64<NS>(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, part,
+                           io.side + (size_t)quad * B * B, lds);
             return;
         }
     }
-    // otherwise four waves work, the other four take the same barriers
+    if (part != 0) return;  // the other masks take one workgroup per tile
+    // four waves work, the other four take the same barriers
     const int t = threadIdx.x & 255;
     const bool act = threadIdx.x < 256;
     if constexpr (B == 64) {
@@ -490,6 +543,15 @@ k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__
         }
     }
     ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, t, lds, act, io);
+}
+
+// Copies of n blocks of ablk: block lst[2 j] (a slot of the upper block
+// storage) to side + lst[2 j + 1] B^2, one block per workgroup.
+template <int B, class T>
+__global__ void k_copy_blocks(const T *__restrict__ ablk, const int *__restrict__ lst, T *__restrict__ side) {
+    const T *src = ablk + (size_t)lst[2 * blockIdx.x] * B * B;
+    T *dst = side + (size_t)lst[2 * blockIdx.x + 1] * B * B;
+    for (int e = threadIdx.x; e < B * B; e += blockDim.x) dst[e] = src[e];
 }
 
 // The same tiles on a bounded set of CUs (as k_update_q_bounded): 512 threads
@@ -504,7 +566,8 @@ template <int B, class T>
 __global__ void __launch_bounds__(512, 1)
 k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
                    const int *__restrict__ flags, const int *__restrict__ tiles, int ntiles,
-                   const int *__restrict__ qmask, int nq, T *__restrict__ side) {
+                   const int *__restrict__ qmask, int nq, T *__restrict__ side, T *__restrict__ snext,
+                   const int *__restrict__ smap) {
     extern __shared__ double lds_raw[];
     auto tile_io = [&](int i) {
         TileIO<T> io;
@@ -513,6 +576,10 @@ k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T 
             io.wmask = 15 & ~io.rmask;
             io.side = side + (size_t)4 * i * B * B;
         }
+        if (snext && i < ntiles) {
+            io.snext = snext;
+            io.smap = smap + 4 * i;
+        }
         return io;
     };
     if constexpr (B == 64) {
@@ -520,7 +587,10 @@ k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T 
         for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
             const int p = tiles[2 * i], q = tiles[2 * i + 1];
             const bool idp = flags[p] != 0, idq = flags[q] != 0;
-            if (idp && idq) continue;  // uniform over the workgroup
+            if (idp && idq) {  // uniform over the workgroup
+                if (snext) copy_skipped<B, T, 512>(pairs, ablk, p, q, snext, smap + 4 * i, threadIdx.x);
+                continue;
+            }
             ua_tile<B, T, 512>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, tile_io(i));
         }
     } else {
@@ -533,6 +603,7 @@ k_update_a_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T 
             const bool idp = flags[p] != 0, idq = flags[q] != 0;
             const bool active = i < ntiles && !(idp && idq);
             ua_tile<B, T>(pairs, ablk, vhat, p, q, idp, idq, t, lds, active, tile_io(i));
+            if (i < ntiles && idp && idq && snext) copy_skipped<B, T, 256>(pairs, ablk, p, q, snext, smap + 4 * i, t);
         }
     }
 }
@@ -651,8 +722,8 @@ template <class T>
 __global__ void __launch_bounds__(512, 1)
 k_update_aq_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
                     const int *__restrict__ flags, const int *__restrict__ tiles, int ntiles,
-                    const int *__restrict__ qmask, int nq, T *__restrict__ side, T *__restrict__ Q, int ldq,
-                    int nrb, int nqw) {
+                    const int *__restrict__ qmask, int nq, T *__restrict__ side, T *__restrict__ snext,
+                    const int *__restrict__ smap, T *__restrict__ Q, int ldq, int nrb, int nqw) {
     constexpr int B = 64;
     extern __shared__ double lds_raw[];
     T *lds = reinterpret_cast<T *>(lds_raw);
@@ -668,12 +739,19 @@ k_update_aq_bounded(const int *__restrict__ pairs, T *__restrict__ ablk, const T
         if (i < ntiles) {
             const int p = tiles[2 * i], q = tiles[2 * i + 1];
             const bool idp = flags[p] != 0, idq = flags[q] != 0;
-            if (idp && idq) continue;  // uniform over the workgroup
+            if (idp && idq) {  // uniform over the workgroup
+                if (snext) copy_skipped<B, T, 512>(pairs, ablk, p, q, snext, smap + 4 * i, threadIdx.x);
+                continue;
+            }
             TileIO<T> io;
             if (i < nq) {
                 io.rmask = qmask[i] & 15;
                 io.wmask = 15 & ~io.rmask;
                 io.side = side + (size_t)4 * i * B * B;
+            }
+            if (snext) {
+                io.snext = snext;
+                io.smap = smap + 4 * i;
             }
             ua_tile<B, T, 512>(pairs, ablk, vhat, p, q, idp, idq, threadIdx.x, lds, true, io);
         } else {
@@ -688,8 +766,10 @@ int device_cus();
 
 template <class T>
 void launch_uaq(int b, int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
-                int ntiles, const int *qmask, int nq, T *side, T *Q, int ldq, int n_rows, int reserve, hipStream_t s) {
-    if (b != 64 || reserve <= 0 || n_rows % 128 != 0 || (nq > 0 && (!qmask || !side)) || nq > ntiles) {
+                int ntiles, const int *qmask, int nq, T *side, T *snext, const int *smap, T *Q, int ldq, int n_rows,
+                int reserve, hipStream_t s) {
+    if (b != 64 || reserve <= 0 || n_rows % 128 != 0 || (nq > 0 && (!qmask || !side)) || nq > ntiles ||
+        (snext && !smap)) {
         set_error("fused update kernel: b = 64, a positive reserve, 128-row blocks of Q");
         throw HipFail{hipErrorInvalidValue};
     }
@@ -705,7 +785,7 @@ void launch_uaq(int b, int npairs, const int *pairs, T *ablk, const T *vhat, con
     if (nwork <= 0) return;
     const int grid = std::max(1, std::min(device_cus() - reserve, nwork));
     hipLaunchKernelGGL((k_update_aq_bounded<T>), dim3(grid), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
-                       std::max(ntiles, 0), qmask, nq, side, Q, ldq, nrb, nqw);
+                       std::max(ntiles, 0), qmask, nq, side, snext, smap, Q, ldq, nrb, nqw);
     JX_LAUNCHED();
 }
 
@@ -713,7 +793,7 @@ int device_cus();
 
 template <int B, class T>
 void launch_ua_bounded(const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles, int ntiles,
-                       int reserve, const int *qmask, int nq, T *side, hipStream_t s) {
+                       int reserve, const int *qmask, int nq, T *side, T *snext, const int *smap, hipStream_t s) {
     // one tile's LDS (b = 64) or two halves' (b = 32), and more than half a
     // CU's in any case: one workgroup per CU
     size_t need = 2 * UaCfg<B>::LDS_BYTES;
@@ -727,13 +807,13 @@ void launch_ua_bounded(const int *pairs, T *ablk, const T *vhat, const int *flag
     }
     const int grid = std::max(1, std::min(device_cus() - reserve, B == 64 ? ntiles : (ntiles + 1) / 2));
     hipLaunchKernelGGL((k_update_a_bounded<B, T>), dim3(grid), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
-                       ntiles, qmask, nq, side);
+                       ntiles, qmask, nq, side, snext, smap);
     JX_LAUNCHED();
 }
 
 template <int B, class T>
 void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles, int ntiles,
-                    const int *qmask, T *side, hipStream_t s) {
+                    const int *qmask, const T *side, hipStream_t s) {
     using U = UaCfg<B>;
     // more than half a CU's LDS: no CU shared with the bounded kernels on the
     // other stream, nor with a second critical tile (b = 64: a whole tile)
@@ -746,18 +826,24 @@ void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, 
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = true;
     }
-    hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
-                       qmask, side);
+    const int ns = B == 64 && std::is_same<T, double>::value ? CRIT_SPLIT : 1;
+    hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles * ns), dim3(512), lds, s, pairs, ablk, vhat, flags,
+                       tiles, qmask, side);
     JX_LAUNCHED();
 }
 
 template <class T>
 void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, const int *flags, const int *tiles,
-               int ntiles, int reserve, const int *qmask, int nq, T *side, hipStream_t s) {
+               int ntiles, int reserve, const int *qmask, int nq, T *side, T *snext, const int *smap,
+               hipStream_t s) {
     if (ntiles <= 0) return;
     if (b != 64 && b != 32) { set_error("update kernel: block size must be 32 or 64"); throw HipFail{hipErrorInvalidValue}; }
     if ((reserve == UA_QUAD || nq > 0) && (!qmask || !side || nq > ntiles)) {
         set_error("update kernel: quadrant split without masks or side blocks");
+        throw HipFail{hipErrorInvalidValue};
+    }
+    if (snext && !smap) {
+        set_error("update kernel: next-round copies without their slot map");
         throw HipFail{hipErrorInvalidValue};
     }
     if (reserve == UA_QUAD) {
@@ -769,8 +855,9 @@ void launch_ua(int b, int npairs, const int *pairs, T *ablk, const T *vhat, cons
         set_error("update kernel: reserve must be positive (bounded kernel) or UA_QUAD");
         throw HipFail{hipErrorInvalidValue};
     }
-    if (b == 64) launch_ua_bounded<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq, side, s);
-    else launch_ua_bounded<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq, side, s);
+    if (b == 64) launch_ua_bounded<64, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq, side, snext,
+                                          smap, s);
+    else launch_ua_bounded<32, T>(pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq, side, snext, smap, s);
 }
 
 // CUs of the current device (cached per device).
@@ -823,27 +910,43 @@ void launch_uq(int b, int npairs, const int *pairs, T *Q, int ldq, int n_rows, c
 
 void launch_update_a(int b, int npairs, const int *pairs, double *ablk, const double *vhat,
                      const int *flags, const int *tiles, int ntiles, hipStream_t s, int reserve,
-                     const int *qmask, int nq, void *side) {
+                     const int *qmask, int nq, void *side, void *snext, const int *smap) {
     launch_ua<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq,
-                      static_cast<double *>(side), s);
+                      static_cast<double *>(side), static_cast<double *>(snext), smap, s);
 }
 void launch_update_a32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
                        const int *tiles, int ntiles, hipStream_t s, int reserve, const int *qmask, int nq,
-                       void *side) {
+                       void *side, void *snext, const int *smap) {
     launch_ua<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, reserve, qmask, nq,
-                     static_cast<float *>(side), s);
+                     static_cast<float *>(side), static_cast<float *>(snext), smap, s);
 }
 void launch_update_aq(int b, int npairs, const int *pairs, double *ablk, const double *vhat, const int *flags,
-                      const int *tiles, int ntiles, const int *qmask, int nq, void *side, double *Q, int ldq,
-                      int n_rows, int reserve, hipStream_t s) {
-    launch_uaq<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, qmask, nq, static_cast<double *>(side), Q,
-                       ldq, n_rows, reserve, s);
+                      const int *tiles, int ntiles, const int *qmask, int nq, void *side, void *snext,
+                      const int *smap, double *Q, int ldq, int n_rows, int reserve, hipStream_t s) {
+    launch_uaq<double>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, qmask, nq, static_cast<double *>(side),
+                       static_cast<double *>(snext), smap, Q, ldq, n_rows, reserve, s);
 }
 void launch_update_aq32(int b, int npairs, const int *pairs, float *ablk, const float *vhat, const int *flags,
-                        const int *tiles, int ntiles, const int *qmask, int nq, void *side, float *Q, int ldq,
-                        int n_rows, int reserve, hipStream_t s) {
-    launch_uaq<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, qmask, nq, static_cast<float *>(side), Q,
-                      ldq, n_rows, reserve, s);
+                        const int *tiles, int ntiles, const int *qmask, int nq, void *side, void *snext,
+                        const int *smap, float *Q, int ldq, int n_rows, int reserve, hipStream_t s) {
+    launch_uaq<float>(b, npairs, pairs, ablk, vhat, flags, tiles, ntiles, qmask, nq, static_cast<float *>(side),
+                      static_cast<float *>(snext), smap, Q, ldq, n_rows, reserve, s);
+}
+void launch_copy_blocks(int b, const double *ablk, const int *lst, int n, void *side, hipStream_t s) {
+    if (n <= 0) return;
+    if (b == 64)
+        hipLaunchKernelGGL((k_copy_blocks<64, double>), dim3(n), dim3(256), 0, s, ablk, lst, static_cast<double *>(side));
+    else
+        hipLaunchKernelGGL((k_copy_blocks<32, double>), dim3(n), dim3(256), 0, s, ablk, lst, static_cast<double *>(side));
+    JX_LAUNCHED();
+}
+void launch_copy_blocks32(int b, const float *ablk, const int *lst, int n, void *side, hipStream_t s) {
+    if (n <= 0) return;
+    if (b == 64)
+        hipLaunchKernelGGL((k_copy_blocks<64, float>), dim3(n), dim3(256), 0, s, ablk, lst, static_cast<float *>(side));
+    else
+        hipLaunchKernelGGL((k_copy_blocks<32, float>), dim3(n), dim3(256), 0, s, ablk, lst, static_cast<float *>(side));
+    JX_LAUNCHED();
 }
 void launch_update_q(int b, int npairs, const int *pairs, double *Q, int ldq, int n_rows,
                      const double *vhat, const int *flags, hipStream_t s, int reserve) {

@@ -72,11 +72,11 @@ def test_opts_defaults_and_workspace():
     # upper block triangle (65 MiB) + Q + three refinement buffers
     assert w64 > 4096 * 4096 * 8 * 4
     # eigenvalues only: the upper block triangle (64 x 65 / 2 blocks of 64 x 64),
-    # three rounds' V_hat (32 pairs x 128 x 128), the saved originals of the
-    # critical blocks (4 x 32 blocks) and less than 2 MiB of lists and scalars
+    # three rounds' V_hat (32 pairs x 128 x 128), two rounds' copies of the
+    # critical blocks (2 x 4 x 32 blocks) and less than 2 MiB of lists and scalars
     ublk = 64 * 65 // 2 * 64 * 64 * 8
     vhat = 3 * 32 * 128 * 128 * 8
-    side = 4 * 32 * 64 * 64 * 8
+    side = 2 * 4 * 32 * 64 * 64 * 8
     w = jx.jacobi_eig_workspace(4096, jx.opts_default(want_vectors=0, refine=0))
     assert ublk + vhat + side <= w < ublk + vhat + side + 2 * 2 ** 20
     assert jx.jacobi_eig_workspace(100) > 0
