@@ -171,6 +171,18 @@ def test_eig_blocks_orderings_triangles(jx, b, order, uplo):
     _check_against_oracle(A, W, Q)
 
 
+def test_eig_antidiag_four_blocks(jx):
+    """Alg. 3's groups on N = 4 blocks: a placeholder pair of round r + 2 is a
+    rotated pair of round r, so its block reaches the next round's critical
+    kernel through the copy made after round r (not through a tile)."""
+    n = 256
+    A, _ = inputs.eig_normal(n, 81)
+    print("eig n=256 b=64 antidiag", flush=True)
+    W, Q, info = eig_gpu(jx, A, block=64, ordering=1)
+    assert info["status"] == 0
+    _check_against_oracle(A, W, Q)
+
+
 def test_eig_graded_512_relative_accuracy(jx):
     """Graded spectrum lambda_i = +-10^(-8 i / n): absolute 1e-12 and per-eigenvalue
     relative 1e-10 for |lambda| >= 1e-6 ||A||_2 against the oracle."""
