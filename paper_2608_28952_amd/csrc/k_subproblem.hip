@@ -685,23 +685,25 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
         }
     }
 
-    // ---- D_hat (A_hat is final after the last barrier of the solver role);
-    //      NaN if a hand-off wait ran out (the caller sees a non-finite iterate)
-    __syncthreads();
-    if (ctr[8]) {
-        for (int e = tid; e < AP; e += NT) Ap[e] = __builtin_nan("");
-        __syncthreads();
-    }
-    if (MODE == SUB_PLAIN) {
-        double *dd = a.dout + (size_t)pr * M2 * M2;
-        for (int e = tid; e < M2 * M2; e += NT) dd[e] = Ap[pkm(e % M2, e / M2)];
-    } else if (MODE == SUB_EIG) {  // A([I,J],[I,J]) <- D_hat
-        const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
-        const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
-                     oij = ublk(I, J) * (size_t)(B * B);
-        for (int e = tid; e < M2 * M2; e += NT) {
-            const int rr = e % M2, cc = e / M2;
-            store_dhat<M2>(a, oii, ojj, oij, rr, cc, Ap[pkm(rr, cc)]);
+    // ---- D_hat: A_hat is final after the last block round's barrier Z, and
+    //      every hand-off wait ended before it, so the solver waves write it
+    //      while the V role applies the last W and stores V_hat; NaN if a
+    //      hand-off wait ran out (the caller sees a non-finite iterate)
+    if (wv < 4) {
+        constexpr int NS = NT / 2;  // solver threads
+        const bool bad = ctr[8] != 0;
+        auto dval = [&](int rr, int cc) { return bad ? __builtin_nan("") : Ap[pkm(rr, cc)]; };
+        if (MODE == SUB_PLAIN) {
+            double *dd = a.dout + (size_t)pr * M2 * M2;
+            for (int e = tid; e < M2 * M2; e += NS) dd[e] = dval(e % M2, e / M2);
+        } else if (MODE == SUB_EIG) {  // A([I,J],[I,J]) <- D_hat
+            const int I = a.pairs[2 * pr], J = a.pairs[2 * pr + 1];
+            const size_t oii = ublk(I, I) * (size_t)(B * B), ojj = ublk(J, J) * (size_t)(B * B),
+                         oij = ublk(I, J) * (size_t)(B * B);
+            for (int e = tid; e < M2 * M2; e += NS) {
+                const int rr = e % M2, cc = e / M2;
+                store_dhat<M2>(a, oii, ojj, oij, rr, cc, dval(rr, cc));
+            }
         }
     }
 }
