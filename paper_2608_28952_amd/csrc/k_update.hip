@@ -12,13 +12,21 @@
 // symmetric, §3 notes the full matrix is kept only for bookkeeping).  The
 // diagonal tiles A[p, p] are replaced by D_hat in the subproblem kernel.
 //
-// GEMM 1 (T = X V_q): X staged through LDS in 32-column chunks (transposed on
+// GEMM 1 (T = X V_q): X staged through LDS in 16-column chunks (transposed on
 // the fly when the stored block is the mirror), V_q read from global memory in
-// the MFMA-operand order of vperm().  Each wave owns 2b/4 columns of T.
+// the MFMA-operand order of vperm().  Each wave owns 16 or 32 columns of T.
 // GEMM 2 (out = V_p^T T): the contraction index of T is its row; the FP64
 // MFMA result layout holds row 16 a + g + 4 v in lane group g, component v,
 // so step (a, v) of GEMM 2 (k = 16 a + 4 v + g) takes its B operand straight
-// from component v of the GEMM 1 accumulators.  T never leaves registers.
+// from component v of the GEMM 1 accumulators: T stays in registers (the
+// critical-block path, whose waves split T's rows, hands it over through LDS
+// in that operand order).
+//
+// Per round: k_update_a_crit computes, on the solve's stream, only the
+// blocks the next round's subproblems read; k_update_aq_bounded (b = 64;
+// k_update_a_bounded and k_update_q_bounded for b = 32) the rest of every
+// tile and the Q update on a bounded set of CUs beside the next round's
+// subproblems.
 #include "jx_common.hpp"
 
 #include <type_traits>
