@@ -284,6 +284,16 @@ int jacobi_subproblem_solve(int count, int m2, const double *dAhat, double *dV, 
 int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
                       const double *dV, const double *dD, jacobi_stream_t stream);
 
+/*
+ * The same step of Alg. 2 (§3) by the FP32 kernels of the precision ladder's
+ * FP32 phase (JACOBI_PREC_MIXED_FP32): A, Q, V and D are rounded to FP32 on
+ * entry, the tile and Q updates run on FP32 MFMA with FP32 accumulation, and
+ * A and Q are widened back to FP64 in place.  Arguments, layouts, ownership
+ * and error codes as for jacobi_block_step.
+ */
+int jacobi_block_step32(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
+                        const double *dV, const double *dD, jacobi_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Kernel profiling (benchmarks)                                             */
 /* ------------------------------------------------------------------------ */

@@ -181,8 +181,8 @@ int jacobi_subproblem_solve(int count, int m2, const double *dAhat, double *dV, 
     });
 }
 
-int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
-                      const double *dV, const double *dD, jacobi_stream_t stream) {
+static int block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs, const double *dV,
+                      const double *dD, bool f32, jacobi_stream_t stream) {
     if (b != 32 && b != 64) return -2;
     if (n <= 0 || n % (2 * b) || n % 128) return -1;
     if (npairs != n / (2 * b)) return -5;
@@ -194,8 +194,18 @@ int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const in
         seen[I] = seen[J] = 1;
     }
     return guarded(nullptr, [&]() -> int {
-        return run_block_step(n, b, dA, dQ, npairs, hPairs, dV, dD, reinterpret_cast<hipStream_t>(stream));
+        return run_block_step(n, b, dA, dQ, npairs, hPairs, dV, dD, f32, reinterpret_cast<hipStream_t>(stream));
     });
+}
+
+int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
+                      const double *dV, const double *dD, jacobi_stream_t stream) {
+    return block_step(n, b, dA, dQ, npairs, hPairs, dV, dD, false, stream);
+}
+
+int jacobi_block_step32(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
+                        const double *dV, const double *dD, jacobi_stream_t stream) {
+    return block_step(n, b, dA, dQ, npairs, hPairs, dV, dD, true, stream);
 }
 
 }  // extern "C"

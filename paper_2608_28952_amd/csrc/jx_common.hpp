@@ -250,6 +250,7 @@ void launch_block_norms32(int npad, int b, const float *ablk, double *partial, d
 
 // Test helpers: column-major V_hat -> vperm order; D_hat -> pair blocks.
 void launch_vperm_from_colmajor(int count, int m2, const double *src, double *dst, hipStream_t s);
+void launch_vperm32_from_colmajor(int count, int m2, const double *src, float *dst, hipStream_t s);
 void launch_write_pair_blocks(int count, int b, const int *pairs, const double *D, double *ablk,
                               hipStream_t s);
 

@@ -73,7 +73,8 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             jacobi_info *info, hipStream_t s);
 int run_subproblem(int count, int m2, const double *dAhat, double *dV, double *dD, int inner,
                    hipStream_t s);
+// f32: the same step by the FP32 kernels (inputs rounded, results widened)
 int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
-                   const double *dV, const double *dD, hipStream_t s);
+                   const double *dV, const double *dD, bool f32, hipStream_t s);
 
 }  // namespace jx

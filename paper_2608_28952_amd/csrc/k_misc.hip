@@ -285,6 +285,16 @@ __global__ void k_vperm_from_colmajor(int m2, const double *__restrict__ src, do
     }
 }
 
+// The same in FP32, in the vperm32 order of the FP32 MFMA kernels.
+__global__ void k_vperm32_from_colmajor(int m2, const double *__restrict__ src, float *__restrict__ dst) {
+    const double *s = src + (size_t)blockIdx.x * m2 * m2;
+    float *d = dst + (size_t)blockIdx.x * m2 * m2;
+    for (int e = threadIdx.x; e < m2 * m2; e += blockDim.x) {
+        const int k = e % m2, i = e / m2;  // element (k, i), column-major
+        d[vperm32(k, i, m2)] = (float)s[e];
+    }
+}
+
 // A([I,J],[I,J]) <- D for each pair (upper block storage).
 __global__ void k_write_pair_blocks(int b, const int *__restrict__ pairs, const double *__restrict__ D,
                                     double *__restrict__ ablk) {
@@ -305,6 +315,12 @@ __global__ void k_write_pair_blocks(int b, const int *__restrict__ pairs, const 
 void launch_vperm_from_colmajor(int count, int m2, const double *src, double *dst, hipStream_t s) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_vperm_from_colmajor, dim3(count), dim3(256), 0, s, m2, src, dst);
+    JX_LAUNCHED();
+}
+
+void launch_vperm32_from_colmajor(int count, int m2, const double *src, float *dst, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_vperm32_from_colmajor, dim3(count), dim3(256), 0, s, m2, src, dst);
     JX_LAUNCHED();
 }
 

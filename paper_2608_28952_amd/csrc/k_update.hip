@@ -1,5 +1,6 @@
 // k_update.hip -- rotation-apply kernels of one parallel step of block Jacobi
-// on gfx950 FP64 MFMA (v_mfma_f64_16x16x4_f64).
+// on gfx950 FP64 MFMA (v_mfma_f64_16x16x4_f64), and on FP32 MFMA
+// (v_mfma_f32_16x16x4_f32) for the FP32 phase of the precision ladder.
 //
 // Alg. 2 (§3) updates, for every pair (I, J) of a group, block rows I, J of A
 // on the left by V^T, block columns I, J of A on the right by V, and block
@@ -339,13 +340,14 @@ __device__ __forceinline__ void ua_tile(const int *__restrict__ pairs, T *__rest
     }
 }
 
-// Workgroups per critical block (b = 64, FP64): each owns 64 / CRIT_SPLIT of
-// the block's columns.  The critical blocks run while the rest of the GPU
+// Workgroups per critical block (b = 64): each owns 64 / CRIT_SPLIT of the
+// block's columns.  The critical blocks run while the rest of the GPU
 // waits for them, so their products are spread over more CUs.
 constexpr int CRIT_SPLIT = 4;
 
-// Columns part * 64 / NS .. of one block of tile (p, q) for b = 64 in FP64:
-// row half h, column half c, by 512 threads, latency first.  One round of
+// Columns part * 64 / NS .. of one block of tile (p, q) for b = 64 (FP64 or
+// FP32, the MFMA conventions of MfmaTraits<T>): row half h, column half c, by
+// 512 threads, latency first.  One round of
 // global loads brings the whole input tile (to LDS; the block itself from
 // its copy `orig`, which no workgroup writes), the V_q operands of the
 // part's columns and the half of V_p that GEMM 2 reads (each value once, to
@@ -354,12 +356,11 @@ constexpr int CRIT_SPLIT = 4;
 // over through LDS in GEMM 2's operand order; GEMM 2 gives the waves the
 // output tiles (row tile ot of half h, column tile ctl).  Two waves per SIMD:
 // one wave's LDS waits are the other's MFMA time.  The part's columns of the
-// new block are written in place.  `lds` holds 128 x 129 doubles.
-template <int NS>
-__device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double *__restrict__ ablk,
-                                           const double *__restrict__ vhat, int p, int q, bool idp, bool idq,
-                                           int h, int c, int part, const double *__restrict__ orig, double *lds) {
-    using T = double;
+// new block are written in place.  `lds` holds 128 x 129 values of T.
+template <int NS, class T>
+__device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, T *__restrict__ ablk,
+                                           const T *__restrict__ vhat, int p, int q, bool idp, bool idq, int h,
+                                           int c, int part, const T *__restrict__ orig, T *lds) {
     using MT = MfmaTraits<T>;
     typedef typename MT::acc_t acc_t;
     constexpr int B = 64, M2 = 128, XLD = M2 + 1, NTH = 512, PB = B * B / NTH;
@@ -398,13 +399,18 @@ __device__ __forceinline__ void ua_block64(const int *__restrict__ pairs, double
         const int kg = 16 * (s >> 2) + MT::kstep(s & 3, g);
         bq[s] = op_or_eye(vq + MT::vidx(kg, col, M2), idq, kg == col);
     }
-    // V_p(k, 64 h + il) sits at vperm(k, il, 64) of the half's copy: its 32
-    // runs of 256 values (one per k >> 2) are contiguous in V_hat too
+    // V_p(k, 64 h + il) sits at vidx(k, il, 64) of the half's copy: its 32
+    // runs of 256 values are contiguous in V_hat too.  Position j of the copy
+    // holds il = 16 ((j >> 6) & 3) + (j & 15) and, in run jr = j >> 8, k =
+    // 4 jr + ((j >> 4) & 3) (FP64) or 16 (jr >> 2) + 4 ((j >> 4) & 3) + (jr & 3)
+    // (FP32).
     T vr[VH / NTH];
 #pragma unroll
     for (int m = 0; m < VH / NTH; ++m) {
-        const int j = tid + NTH * m;
-        const int k = 4 * (j >> 8) + ((j >> 4) & 3), il = ((j >> 6) & 3) * 16 + (j & 15);
+        const int j = tid + NTH * m, jr = j >> 8;
+        const int il = ((j >> 6) & 3) * 16 + (j & 15);
+        const int k = std::is_same<T, double>::value ? 4 * jr + ((j >> 4) & 3)
+                                                     : 16 * (jr >> 2) + 4 * ((j >> 4) & 3) + (jr & 3);
         vr[m] = op_or_eye(vp + MT::vidx(k, 64 * h + il, M2), idp, k == 64 * h + il);
     }
     // X(row, k) at lds[k XLD + row]: block (hh, cc) holds rows 64 hh .., k 64 cc ..
@@ -509,19 +515,19 @@ __device__ __forceinline__ void copy_skipped(const int *__restrict__ pairs, cons
 }
 
 // Only the critical quadrants qmask[i] of tile i, one tile per workgroup
-// (CRIT_SPLIT workgroups for the one-block FP64 case of b = 64), from copies
+// (CRIT_SPLIT workgroups for the one-block case of b = 64), from copies
 // of their originals at side + 4 i B^2 (+ quad B^2), made beforehand; the
 // new blocks are written in place.  Blocks within one column half (b = 64)
 // take T for that half only, and V_p^T T for the row halves written: 3/8 of
-// a tile's products for one block (FP64: the whole tile staged in LDS at
-// once).  Two opposite blocks, and b = 32, take all of T.
+// a tile's products for one block (the whole tile staged in LDS at once).
+// Two opposite blocks, and b = 32, take all of T.
 template <int B, class T>
 __global__ void __launch_bounds__(512, 1)
 k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__restrict__ vhat,
                 const int *__restrict__ flags, const int *__restrict__ tiles, const int *__restrict__ qmask,
                 const T *__restrict__ side) {
     extern __shared__ double lds_raw[];
-    constexpr int NS = B == 64 && std::is_same<T, double>::value ? CRIT_SPLIT : 1;
+    constexpr int NS = B == 64 ? CRIT_SPLIT : 1;
     const int i = blockIdx.x / NS, part = blockIdx.x % NS;
     const int p = tiles[2 * i], q = tiles[2 * i + 1];
     const bool idp = flags[p] != 0, idq = flags[q] != 0;
@@ -532,10 +538,10 @@ k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__
     io.side = const_cast<T *>(side) + (size_t)4 * i * B * B;
     T *lds = reinterpret_cast<T *>(lds_raw);
     const int m = io.wmask;
-    if constexpr (B == 64 && std::is_same<T, double>::value) {
+    if constexpr (B == 64) {
         if (m == 1 || m == 2 || m == 4 || m == 8) {  // one block: bit 2 h + c
             const int quad = m == 1 ? 0 : m == 2 ? 1 : m == 4 ? 2 : 3;
-            ua_block64<NS>(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, part,
+            ua_block64<NS, T>(pairs, ablk, vhat, p, q, idp, idq, quad >> 1, quad & 1, part,
                            io.side + (size_t)quad * B * B, lds);
             return;
         }
@@ -834,7 +840,7 @@ void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, 
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = true;
     }
-    const int ns = B == 64 && std::is_same<T, double>::value ? CRIT_SPLIT : 1;
+    const int ns = B == 64 ? CRIT_SPLIT : 1;
     hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles * ns), dim3(512), lds, s, pairs, ablk, vhat, flags,
                        tiles, qmask, side);
     JX_LAUNCHED();

@@ -86,6 +86,7 @@ def lib():
         L.jws_cayley_batched.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
         L.jacobi_subproblem_solve.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
         L.jacobi_block_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
+        L.jacobi_block_step32.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         _lib = L
     return _lib
 
@@ -285,10 +286,11 @@ def jacobi_subproblem_solve(Ahat, inner_sweeps=0):
     return V.transpose(1, 2), D.transpose(1, 2)
 
 
-def jacobi_block_step(A, Q, b, pairs, V, D):
+def jacobi_block_step(A, Q, b, pairs, V, D, fp32=False):
     """One parallel step of Alg. 2 on explicit data (in place on copies):
     returns (A_new, Q_new).  A, Q: n x n float64 CUDA tensors; V, D:
-    len(pairs) x 2b x 2b tensors in the usual indexing."""
+    len(pairs) x 2b x 2b tensors in the usual indexing.  fp32: the FP32
+    kernels of the precision ladder compute it (jacobi_block_step32)."""
     import torch
     n = A.shape[0]
     Ac = A.t().contiguous()   # column-major A
@@ -297,6 +299,7 @@ def jacobi_block_step(A, Q, b, pairs, V, D):
     Dc = D.transpose(1, 2).contiguous()
     flat = [int(v) for pr in pairs for v in pr]
     hp = (ctypes.c_int * len(flat))(*flat)
-    _check(lib().jacobi_block_step(n, b, _ptr(Ac), _ptr(Qc), len(pairs), hp, _ptr(Vc), _ptr(Dc), _stream()))
+    fn = lib().jacobi_block_step32 if fp32 else lib().jacobi_block_step
+    _check(fn(n, b, _ptr(Ac), _ptr(Qc), len(pairs), hp, _ptr(Vc), _ptr(Dc), _stream()))
     torch.cuda.synchronize()
     return Ac.t(), (Qc.t() if Qc is not None else None)

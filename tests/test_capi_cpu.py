@@ -24,7 +24,7 @@ def _jx():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(jacobi_[a-z_]+|jws_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(jacobi_[a-z0-9_]+|jws_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -32,6 +32,7 @@ def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(jx.LIB_PATH)
     names = declared_functions()
     assert "jacobi_eig" in names and "jacobi_svd" in names and "jacobi_eig_batched" in names
+    assert "jacobi_block_step32" in names
     for name in names:
         assert hasattr(L, name), name
 

@@ -110,6 +110,37 @@ def test_block_step_matches_oracle(jx, n, b, rnd):
     assert np.array_equal(Ag, Ag.T)
 
 
+@pytest.mark.parametrize("n,b,rnd", [(256, 64, 0), (384, 64, 2), (256, 32, 3), (512, 32, 5)])
+def test_block_step_fp32_matches_oracle(jx, n, b, rnd):
+    """The FP32 kernels of the precision ladder's FP32 phase (single-block
+    critical tiles split over workgroups, two-block and whole tiles, the Q
+    update) against the oracle's step on the same FP32-rounded inputs."""
+    rng = np.random.default_rng(n + b + 1)
+    A, _ = inputs.eig_uniform(n, 50 + rnd)
+    Q = inputs.haar(n, rng)
+    N = n // b
+    pairs = O.rr_list(N)[rnd]
+    Vh = np.stack([inputs.haar(2 * b, rng) for _ in pairs])
+    Dh = []
+    for _ in pairs:
+        X = rng.standard_normal((2 * b, 2 * b)) * 1e-3
+        Dh.append(np.diag(rng.standard_normal(2 * b)) + X + X.T)
+    Dh = np.stack(Dh)
+    r32 = lambda M: M.astype(np.float32).astype(np.float64)
+    A, Q, Vh, Dh = r32(A), r32(Q), r32(Vh), r32(Dh)
+    print(f"block step fp32 n={n} b={b}", flush=True)
+    Ag, Qg = jx.jacobi_block_step(dev(A), dev(Q), b, pairs, dev(Vh), dev(Dh), fp32=True)
+    Ar, Qr = O.block_step(A, Q, b, pairs, list(Vh), list(Dh))
+    Ag, Qg = host(Ag), host(Qg)
+    # FP32 accumulation: two products of order 2b per entry, rounding of the result
+    eps32 = float(np.finfo(np.float32).eps)
+    assert np.max(np.abs(Ag - Ar)) <= 4 * (2 * b) * eps32 * np.max(np.abs(A))
+    assert np.max(np.abs(Qg - Qr)) <= 4 * (2 * b) * eps32
+    assert np.array_equal(Ag, Ag.T)
+    # FP32 results: the widened values are FP32 numbers
+    assert np.array_equal(r32(Ag), Ag)
+
+
 def test_block_step_identity_rotation_is_exact(jx):
     n, b = 256, 64
     A, _ = inputs.eig_uniform(n, 3)
