@@ -185,8 +185,24 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
                          f32 ? "fp32" : "fp64", hcnt.ptr[0], last_meas);
         return hcnt.ptr[0];
     };
+    // cond(G) estimated from the column norms of the FP32 iterate (max / min
+    // over the nonzero columns), which approach the singular values as the
+    // columns become orthogonal.
+    std::vector<double> hnorm(n);
+    auto cond32 = [&]() -> double {
+        launch_col_norms32(m, n, G32, p.mpad, sigma, s);
+        JX_HIP(hipMemcpyAsync(hnorm.data(), sigma, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        JX_HIP(hipStreamSynchronize(s));
+        double mx = 0.0, mn = HUGE_VAL;
+        for (int j = 0; j < n; ++j) {
+            mx = std::max(mx, hnorm[j]);
+            if (hnorm[j] > 0.0) mn = std::min(mn, hnorm[j]);
+        }
+        return mn < HUGE_VAL ? mx / mn : 1.0;
+    };
     // Sweeps until a sweep rotates no pair (stop <= 0) or the largest relative
-    // cosine drops to stop.  Returns 0, 1 (cap), 2 (non-finite), 4 (FP32 stagnates).
+    // cosine drops to stop.  Returns 0, 1 (cap), 2 (non-finite), 4 (the FP32
+    // phase stagnates or has no more to gain).
     auto phase = [&](double stop, int cap) -> int {
         double prev = -1.0;
         for (;;) {
@@ -197,6 +213,12 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
             if (!std::isfinite(last_meas)) return 2;
             if (rot == 0 || (stop > 0.0 && last_meas <= stop)) return 0;
             if (f32 && prev >= 0.0 && last_meas < 1e-3 && last_meas > 0.5 * prev) return 4;
+            // V from the FP32 phase is accurate to about u32 = 2^-24, so G0 V
+            // gives the columns of the smallest singular values cosines of
+            // about u32 cond(G) again (3.2 u32 cond(G) measured at cond =
+            // 1e6): FP32 sweeps below that level are repeated in FP64.  The
+            // phase ends once the largest cosine is within 2 u32 cond(G).
+            if (f32 && last_meas <= 2.0 * 0x1p-24 * cond32()) return 4;
             prev = last_meas;
         }
     };

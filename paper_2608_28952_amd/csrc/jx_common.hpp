@@ -196,6 +196,7 @@ void launch_gram(int b, int npairs, const int *pairs, const double *G, int ldg, 
 void launch_gram32(int b, int npairs, const int *pairs, const float *G, int ldg, int m_rows, int nchunks,
                    float *partial, double *ahat, hipStream_t s);
 void launch_col_norms(int m, int n, const double *G, int ldg, double *sigma, hipStream_t s);
+void launch_col_norms32(int m, int n, const float *G, int ldg, double *sigma, hipStream_t s);
 void launch_scale_scatter(int m, int n, const double *G, int ldg, const double *sigma, const int *rank,
                           double *U, int ldu, hipStream_t s);
 

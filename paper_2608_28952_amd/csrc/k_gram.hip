@@ -111,13 +111,15 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// sigma[j] = ||G(:, j)||_2 over the first m rows (fixed-order reduction).
-__global__ void __launch_bounds__(256) k_col_norms(int m, const double *__restrict__ G, int ldg,
+// sigma[j] = ||G(:, j)||_2 over the first m rows (fixed-order reduction, in
+// FP64 for either storage type).
+template <class T>
+__global__ void __launch_bounds__(256) k_col_norms(int m, const T *__restrict__ G, int ldg,
                                                    double *__restrict__ sigma) {
     __shared__ double red[4];
-    const double *c = G + (size_t)blockIdx.x * ldg;
+    const T *c = G + (size_t)blockIdx.x * ldg;
     double s = 0.0;
-    for (int i = threadIdx.x; i < m; i += 256) s += c[i] * c[i];
+    for (int i = threadIdx.x; i < m; i += 256) s += (double)c[i] * (double)c[i];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -168,7 +170,12 @@ void launch_gram32(int b, int npairs, const int *pairs, const float *G, int ldg,
 
 void launch_col_norms(int m, int n, const double *G, int ldg, double *sigma, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_col_norms, dim3(n), dim3(256), 0, s, m, G, ldg, sigma);
+    hipLaunchKernelGGL(k_col_norms<double>, dim3(n), dim3(256), 0, s, m, G, ldg, sigma);
+    JX_LAUNCHED();
+}
+void launch_col_norms32(int m, int n, const float *G, int ldg, double *sigma, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_col_norms<float>, dim3(n), dim3(256), 0, s, m, G, ldg, sigma);
     JX_LAUNCHED();
 }
 
