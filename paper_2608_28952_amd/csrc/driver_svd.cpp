@@ -49,8 +49,10 @@ SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
     WorkspaceBuilder wb;
     p.off_g = wb.add(sizeof(double) * (size_t)p.mpad * p.npad);
     p.off_v = wb.add(sizeof(double) * (size_t)p.npad * p.npad);
-    p.off_vhat = wb.add(sizeof(double) * p.H * m2sq);
-    p.off_flags = wb.add(sizeof(int) * p.H);
+    // one V_hat and one flag set per round of a sweep: the V update of round
+    // r runs later, on a second stream (run_svd)
+    p.off_vhat = wb.add(sizeof(double) * (size_t)p.R * p.H * m2sq);
+    p.off_flags = wb.add(sizeof(int) * (size_t)p.R * p.H);
     p.off_pairs = wb.add(sizeof(int) * 2 * (size_t)p.R * p.H);
     p.off_force = wb.add(sizeof(int) * (size_t)p.R * p.H);
     p.off_partial = wb.add(sizeof(double) * (size_t)p.H * p.nchunks * m2sq);
@@ -62,7 +64,7 @@ SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
     if (p.mixed) {
         p.off_g32 = wb.add(sizeof(float) * (size_t)p.mpad * p.npad);
         p.off_v32 = wb.add(sizeof(float) * (size_t)p.npad * p.npad);
-        p.off_vhat32 = wb.add(sizeof(float) * p.H * m2sq);
+        p.off_vhat32 = wb.add(sizeof(float) * (size_t)p.R * p.H * m2sq);
     }
     if (p.refine) {
         p.off_g0 = wb.add(sizeof(double) * (size_t)p.mpad * p.npad);
@@ -75,6 +77,27 @@ SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
 
 // Rounds padded to N/2 pairs (see the eigensolver driver).
 void padded_rounds_pub(int N, int ordering, std::vector<int> &pairs, std::vector<int> &force);
+
+// The second stream of a solve and its two events (ordering within one
+// device only, so no system-scope fence).
+struct SideStream {
+    hipStream_t sq = nullptr;
+    hipEvent_t ev_go = nullptr, ev_done = nullptr;
+    SideStream() {
+        JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
+        const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
+        JX_HIP(hipEventCreateWithFlags(&ev_go, fl));
+        JX_HIP(hipEventCreateWithFlags(&ev_done, fl));
+    }
+    ~SideStream() {
+        if (sq) (void)hipStreamSynchronize(sq);
+        if (ev_go) (void)hipEventDestroy(ev_go);
+        if (ev_done) (void)hipEventDestroy(ev_done);
+        if (sq) (void)hipStreamDestroy(sq);
+    }
+    SideStream(const SideStream &) = delete;
+    SideStream &operator=(const SideStream &) = delete;
+};
 
 int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int ldu, double *dV, int ldv,
             void *dWork, size_t workBytes, const jacobi_opts &o, jacobi_info *info, hipStream_t s) {
@@ -132,6 +155,24 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
     bool f32 = false;
     int sweeps = 0, sweeps32 = 0, status = 1;
     double last_meas = 0.0;
+    // V is read only after a sweep, so each round's V update runs on a second
+    // stream, on at most CUs - H CUs, once the next round's Gram blocks are
+    // done: beside that round's subproblems, which hold H CUs.  Round r keeps
+    // its own V_hat and flags for it; the solve's stream joins once a sweep.
+    SideStream side;
+    const size_t m2sq = (size_t)m2 * m2;
+    auto vhat_r = [&](int r) { return Vh + (size_t)r * p.H * m2sq; };
+    auto vhat32_r = [&](int r) { return Vh32 + (size_t)r * p.H * m2sq; };
+    auto flags_r = [&](int r) { return flags + (size_t)r * p.H; };
+    auto update_v = [&](int r) {  // after round r's subproblems and round r + 1's Gram blocks
+        JX_HIP(hipEventRecord(side.ev_go, s));
+        JX_HIP(hipStreamWaitEvent(side.sq, side.ev_go, 0));
+        const int *pr = pairs + (size_t)2 * r * p.H;
+        ProfScope ps(PROF_UPDATE_Q, side.sq, (double)p.H * 2.0 * p.npad * m2 * m2,
+                     (double)p.H * 2.0 * p.npad * m2 * (f32 ? sizeof(float) : sizeof(double)));
+        if (f32) launch_update_q32(p.b, p.H, pr, V32, p.npad, p.npad, vhat32_r(r), flags_r(r), side.sq, p.H);
+        else launch_update_q(p.b, p.H, pr, V, p.npad, p.npad, vhat_r(r), flags_r(r), side.sq, p.H);
+    };
     auto sweep_once = [&]() -> int {  // returns rotated pair count
         JX_HIP(hipMemsetAsync(cnt, 0, sizeof(int), s));
         for (int r = 0; r < p.R; ++r) {
@@ -144,36 +185,35 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
                                   ahat, s);
                 else launch_gram(p.b, p.H, pr, G, p.mpad, p.mpad, p.nchunks, partial, ahat, s);
             }
+            if (r > 0) update_v(r - 1);
             SubArgs a{};
             a.mode = SUB_GRAM;
             a.m2 = m2;
             a.count = p.H;
             a.pairs = pr;
             a.ahat = ahat;
-            a.vout = Vh;
-            a.flags = flags;
+            a.vout = vhat_r(r);
+            a.flags = flags_r(r);
             a.skip_thr = tol;
             a.inner_sweeps = o.inner_max_sweeps;
             a.inner_off = meas + (size_t)r * p.H;
             a.force_skip = any_force ? force + (size_t)r * p.H : nullptr;
             a.rot_count = cnt;
-            if (f32) a.vout32 = Vh32;
+            if (f32) a.vout32 = vhat32_r(r);
             {
                 ProfScope ps(PROF_SUBPROBLEM, s, 0.0, 0.0);
                 launch_subproblem(a, s);
             }
             {
-                ProfScope ps(PROF_UPDATE_Q, s, (double)p.H * 2.0 * (p.mpad + p.npad) * m2 * m2,
-                             (double)p.H * 2.0 * (p.mpad + p.npad) * m2 * (f32 ? sizeof(float) : sizeof(double)));
-                if (f32) {
-                    launch_update_q32(p.b, p.H, pr, G32, p.mpad, p.mpad, Vh32, flags, s);
-                    launch_update_q32(p.b, p.H, pr, V32, p.npad, p.npad, Vh32, flags, s);
-                } else {
-                    launch_update_q(p.b, p.H, pr, G, p.mpad, p.mpad, Vh, flags, s);
-                    launch_update_q(p.b, p.H, pr, V, p.npad, p.npad, Vh, flags, s);
-                }
+                ProfScope ps(PROF_UPDATE_Q, s, (double)p.H * 2.0 * p.mpad * m2 * m2,
+                             (double)p.H * 2.0 * p.mpad * m2 * (f32 ? sizeof(float) : sizeof(double)));
+                if (f32) launch_update_q32(p.b, p.H, pr, G32, p.mpad, p.mpad, vhat32_r(r), flags_r(r), s);
+                else launch_update_q(p.b, p.H, pr, G, p.mpad, p.mpad, vhat_r(r), flags_r(r), s);
             }
         }
+        update_v(p.R - 1);
+        JX_HIP(hipEventRecord(side.ev_done, side.sq));
+        JX_HIP(hipStreamWaitEvent(s, side.ev_done, 0));
         JX_HIP(hipMemcpyAsync(hcnt.ptr, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
         JX_HIP(hipMemcpyAsync(hmeas.data(), meas, sizeof(double) * hmeas.size(), hipMemcpyDeviceToHost, s));
         JX_HIP(hipStreamSynchronize(s));
