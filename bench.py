@@ -216,8 +216,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "sharding is described in DESIGN.md, not benchmarked", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU and is measured on one GPU only "
+              f"(got --gpus {args.gpus}); a sharding over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)

@@ -132,7 +132,7 @@ int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, 
 /*
  * Batched symmetric eigendecomposition of `batch` independent matrices of
  * orders h_n[k] (0 <= h_n[k] <= 256; order 0 is skipped), one graph launch
- * (spec addition: batching, not in the paper; the per-matrix method is
+ * (batching is an addition, not in the paper; the per-matrix method is
  * the block Jacobi of §3 with the round-robin ordering, applied inside one
  * workgroup).
  *   h_n, h_offA  host arrays: orders and element offsets (int64) of matrix k in
@@ -188,7 +188,7 @@ int jacobi_batched_autotune(int dtype, int per_bucket, unsigned seed, const char
 int jacobi_batched_graph_stats(int *hits, int *builds);
 
 /* ------------------------------------------------------------------------ */
-/* Learned warm start (spec addition; the paper has no learned part)   */
+/* Learned warm start (an addition; the paper has no learned part)          */
 /* ------------------------------------------------------------------------ */
 /*
  * A small network maps the parameters theta (8) of a matrix family

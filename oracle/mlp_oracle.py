@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, never by the product path.
 
 The network proposes the skew generator of a warm start for the Jacobi
-eigensolver (a spec addition to the paper's method, which has no
-learned component): theta (8) -> 256 -> 256 -> 2016 coordinates of a 64 x 64
+eigensolver (an addition to the paper's method, which has no learned
+component): theta (8) -> 256 -> 256 -> 2016 coordinates of a 64 x 64
 skew-symmetric S (strictly upper entries, row-major).  Hidden layers use the
 tanh form of GELU, the output layer is linear, the loss is the mean squared
 error, and the optimiser is Adam (Kingma & Ba 2015).  The GPU kernels keep

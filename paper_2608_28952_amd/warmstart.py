@@ -1,6 +1,6 @@
 """Learned warm start for batched Jacobi on a parametrised matrix family.
 
-A spec addition (the paper's method has no learned part): for the
+An addition to the paper's method, which has no learned part: for the
 family A(theta) = A0 + sum_k theta_k B_k (order 64, theta in R^8), a small
 network proposes Q0 = Qref cay(S(theta)) and the batched Jacobi solver
 finishes from Q0^T A Q0; a proposal that does not lower the off-norm falls

@@ -2,7 +2,7 @@
 
 Every call goes through the C-ABI library (libjacobi.so) via the ctypes
 binding; the oracle is the plain FP64 scalar Jacobi of oracle/ plus its
-long-double checkers.  Tolerances (the benchmark spec): eigenvalues within 1e-12 of
+long-double checkers.  Tolerances: eigenvalues within 1e-12 of
 the oracle relative to ||A||_2; ||A - Q D Q^T||_F / ||A||_F <= 1e-12 and
 ||Q^T Q - I||_F <= 1e-12 measured in long double.
 """
