@@ -1,9 +1,10 @@
 // k_cayley.hip -- batched Cayley map of the learned warm start:
 // Q0 = Qref (I - S)^{-1} (I + S) for skew-symmetric S (FP64), one workgroup per
 // matrix, n <= 64.  I - S has symmetric part I (x^T (I - S) x = |x|^2), so its
-// leading minors are nonzero and Gaussian elimination needs no pivoting; the
-// elimination runs on the augmented [I - S | I + S] in LDS, the solution
-// columns are back-substituted independently, then multiplied by Qref.
+// leading minors are nonzero and elimination needs no pivoting.  Order 64
+// runs Gauss-Jordan on the augmented [I - S | I + S] in registers; other
+// orders eliminate it in LDS and back-substitute the solution columns
+// independently.  The solution is then multiplied by Qref.
 #include "jx_common.hpp"
 #include "jx_mlp.hpp"
 
@@ -56,6 +57,72 @@ __global__ void __launch_bounds__(NT) k_cayley(int n, const double *S, const dou
     }
 }
 
+// Order 64 (the warm start's family): Gauss-Jordan on [I - S | I + S] held
+// in registers.  Thread (row i = tid mod 64, wave g) holds columns g + 4 q,
+// q < 32, of row i; step k publishes pivot row k and column k through LDS
+// (double-buffered by step parity: one barrier per step), scales the pivot
+// row and eliminates column k from every other row, so that the right half
+// ends as X = (I - S)^{-1} (I + S).  Then Q0 = Qref X with a 4 x 4 register
+// block per thread, both operands from LDS.
+__global__ void __launch_bounds__(NT) k_cayley64(const double *S, const double *Qref, double *Q0) {
+    constexpr int N = 64, W = 2 * N, NQ = W / 4;
+    __shared__ double prow[2][W];
+    __shared__ double mcol[2][N];
+    __shared__ double Qs[N * N];  // Qs[i N + r] = Qref(r, i)
+    __shared__ double Xs[N * N];  // Xs[i N + c] = X(i, c)
+    const int tid = threadIdx.x, i = tid & 63, g = tid >> 6;
+    const double *Sb = S + (size_t)blockIdx.x * N * N;
+    double m[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = g + 4 * q;  // S(i, c) at c N + i (column-major)
+        m[q] = j < N ? (i == j ? 1.0 : 0.0) - Sb[j * N + i] : (i == j - N ? 1.0 : 0.0) + Sb[(j - N) * N + i];
+    }
+    for (int e = tid; e < N * N; e += NT) Qs[e] = Qref[e];  // column-major Qref: e = i N + r
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int b = k & 1;
+        if (i == k) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) prow[b][g + 4 * q] = m[q];
+        }
+        if (g == (k & 3)) mcol[b][i] = m[k >> 2];
+        __syncthreads();
+        const double pinv = 1.0 / prow[b][k];
+        if (i == k) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) m[q] *= pinv;
+        } else {
+            const double f = mcol[b][i] * pinv;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) m[q] -= f * prow[b][g + 4 * q];
+        }
+    }
+#pragma unroll
+    for (int q = NQ / 2; q < NQ; ++q) Xs[i * N + (g + 4 * q - N)] = m[q];
+    __syncthreads();
+    const int r0 = 4 * (tid & 15), c0 = 4 * (tid >> 4);
+    double acc[4][4] = {};
+#pragma unroll 8
+    for (int k = 0; k < N; ++k) {
+        double a[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = Qs[k * N + r0 + u];
+            x[u] = Xs[k * N + c0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * x[v];
+    }
+    double *Qb = Q0 + (size_t)blockIdx.x * N * N;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Qb[(c0 + v) * N + r0 + u] = acc[u][v];
+}
+
 }  // namespace
 
 void cayley_batched(int batch, int n, const double *S, const double *Qref, double *Q0, hipStream_t s) {
@@ -63,6 +130,11 @@ void cayley_batched(int batch, int n, const double *S, const double *Qref, doubl
     if (n > NMAX) {
         set_error("cayley: order above 64");
         throw HipFail{hipErrorInvalidValue};
+    }
+    if (n == NMAX) {
+        hipLaunchKernelGGL(k_cayley64, dim3(batch), dim3(NT), 0, s, S, Qref, Q0);
+        JX_LAUNCHED();
+        return;
     }
     const size_t lds = sizeof(double) * ((size_t)n * 2 * n + (size_t)n * n);
     static bool attr = false;

@@ -42,6 +42,28 @@ class Info(ctypes.Structure):
                 "fallback_used": self.fallback_used, "off_rel": self.off_rel, "seconds": self.seconds}
 
 
+def _info_dtype():
+    """numpy structured dtype with the layout of jacobi_info (Info)."""
+    import numpy as np
+    dt = np.dtype([("status", "i4"), ("sweeps", "i4"), ("sweeps_by_prec", "i4", (3,)), ("fallback_used", "i4"),
+                   ("off_rel", "f8"), ("seconds", "f8")], align=True)
+    assert dt.itemsize == ctypes.sizeof(Info)
+    return dt
+
+
+def _info_dicts(a, count):
+    """as_dict() of the first `count` entries of an Info array held as a
+    numpy structured array, read column by column (per-field ctypes access
+    costs about 2 us per matrix on large batches)."""
+    if count <= 0:
+        return []
+    a = a[:count]
+    st, sw, sp = a["status"].tolist(), a["sweeps"].tolist(), a["sweeps_by_prec"].tolist()
+    fb, off, sec = a["fallback_used"].tolist(), a["off_rel"].tolist(), a["seconds"].tolist()
+    return [{"status": st[k], "sweeps": sw[k], "sweeps_by_prec": sp[k], "fallback_used": fb[k],
+             "off_rel": off[k], "seconds": sec[k]} for k in range(count)]
+
+
 _vp = ctypes.c_void_p
 _ip = ctypes.POINTER(ctypes.c_int)
 
@@ -195,22 +217,30 @@ def jacobi_svd_workspace(m, n, opts=None):
     return lib().jacobi_svd_workspace(m, n, ctypes.byref(o))
 
 
-def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, check=True, out=None):
+def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, check=True, out=None,
+                       info="dicts"):
     """Batched eigendecomposition.  `sizes` (host int sequence), `offsets`
     (host int64 element offsets, len = batch), `packed` a float32 or float64
     CUDA tensor holding each matrix column-major at its offset.  `out` may
     give preallocated (W, Q) float64 tensors (a call with the same sizes,
     pointers and options then replays the cached graph).  Returns (W packed by
-    prefix sums of n_k, Q packed at the offsets, list of info)."""
+    prefix sums of n_k, Q packed at the offsets, per-matrix info): a list of
+    info dicts, or with info="array" one numpy structured array with the
+    same fields (no per-matrix Python objects: large batches)."""
     import numpy as np
     import torch
     o = opts if opts is not None else opts_default()
     batch = len(sizes)
-    hn = (ctypes.c_int * max(batch, 1))(*[int(v) for v in sizes])
-    ho = (ctypes.c_int64 * max(batch, 1))(*[int(v) for v in offsets[:batch]])
+    # host arrays handed over by pointer (at least one element each)
+    hn_a = np.zeros(max(batch, 1), dtype=np.int32)
+    ho_a = np.zeros(max(batch, 1), dtype=np.int64)
+    hn_a[:batch] = np.asarray(sizes, dtype=np.int64)[:batch]
+    ho_a[:batch] = np.asarray(offsets, dtype=np.int64)[:batch]
+    hn = hn_a.ctypes.data_as(_ip)
+    ho = ho_a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     dtype = F32 if packed.dtype == torch.float32 else F64
-    total_w = int(np.sum(np.asarray(sizes, dtype=np.int64)))
-    total_q = max((int(offsets[k]) + int(sizes[k]) ** 2 for k in range(batch)), default=0)
+    total_w = int(hn_a[:batch].astype(np.int64).sum())
+    total_q = int((ho_a[:batch] + hn_a[:batch].astype(np.int64) ** 2).max()) if batch else 0
     if out is not None:
         W, Q = out
         if W.numel() < total_w or (Q is not None and Q.numel() < total_q):
@@ -218,20 +248,25 @@ def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, ch
     else:
         W = torch.empty(total_w, dtype=torch.float64, device=packed.device)
         Q = torch.empty(total_q, dtype=torch.float64, device=packed.device)
-    infos = (Info * max(batch, 1))()
+    if info not in ("dicts", "array"):
+        raise ValueError("info must be 'dicts' or 'array'")
+    infos = np.zeros(max(batch, 1), dtype=_info_dtype())
     rc = lib().jacobi_eig_batched(batch, hn, ho, dtype, _ptr(packed), _ptr(W), _ptr(Q), _ptr(Q0),
                                   _ptr(work), work.numel() * work.element_size() if work is not None else 0,
-                                  ctypes.byref(o), infos, _stream())
+                                  ctypes.byref(o), infos.ctypes.data_as(ctypes.POINTER(Info)), _stream())
     if check:
         _check(rc)
-    return W, Q, [infos[k].as_dict() for k in range(batch)]
+    return W, Q, (infos[:batch] if info == "array" else _info_dicts(infos, batch))
 
 
 def batched_workspace(sizes, dtype_f64=False, opts=None):
     """Device workspace bytes of jacobi_eig_batched for these sizes."""
+    import numpy as np
     o = opts if opts is not None else opts_default()
-    hn = (ctypes.c_int * max(len(sizes), 1))(*[int(v) for v in sizes])
-    return int(lib().jacobi_eig_batched_workspace(len(sizes), hn, F64 if dtype_f64 else F32, ctypes.byref(o)))
+    hn_a = np.zeros(max(len(sizes), 1), dtype=np.int32)
+    hn_a[:len(sizes)] = np.asarray(sizes, dtype=np.int64)
+    return int(lib().jacobi_eig_batched_workspace(len(sizes), hn_a.ctypes.data_as(_ip), F64 if dtype_f64 else F32,
+                                                  ctypes.byref(o)))
 
 
 def batched_tuning(dtype_f64, bucket):
