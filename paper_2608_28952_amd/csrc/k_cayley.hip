@@ -57,16 +57,26 @@ __global__ void __launch_bounds__(NT) k_cayley(int n, const double *S, const dou
     }
 }
 
+// Value of v in lane l of the wave (l < 64, every lane active).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Order 64 (the warm start's family): Gauss-Jordan on [I - S | I + S] held
-// in registers.  Thread (row i = tid mod 64, wave g) holds columns g + 4 q,
-// q < 32, of row i; step k publishes pivot row k and column k through LDS
-// (double-buffered by step parity: one barrier per step), scales the pivot
-// row and eliminates column k from every other row, so that the right half
-// ends as X = (I - S)^{-1} (I + S).  Then Q0 = Qref X with a 4 x 4 register
-// block per thread, both operands from LDS.
+// in registers.  Thread (row i = lane, wave g) holds columns 32 g .. 32 g + 31
+// of row i, so each wave holds the pivot row k of its own columns in lane k
+// and reads it from there (no LDS); only column k (the multipliers, from the
+// wave that holds it) passes through LDS, double-buffered by step parity: one
+// barrier per step.  Every row is updated as m -= f p with p the pivot row:
+// f = a_ik / a_kk eliminates column k from the other rows, f = 1 - 1 / a_kk
+// scales the pivot row itself (m = p in its lane), so no lane takes another
+// path.  The right half ends as X = (I - S)^{-1} (I + S).  Then Q0 = Qref X
+// with a 4 x 4 register block per thread, both operands from LDS.
 __global__ void __launch_bounds__(NT) k_cayley64(const double *S, const double *Qref, double *Q0) {
     constexpr int N = 64, W = 2 * N, NQ = W / 4;
-    __shared__ double prow[2][W];
     __shared__ double mcol[2][N];
     __shared__ double Qs[N * N];  // Qs[i N + r] = Qref(r, i)
     __shared__ double Xs[N * N];  // Xs[i N + c] = X(i, c)
@@ -75,31 +85,24 @@ __global__ void __launch_bounds__(NT) k_cayley64(const double *S, const double *
     double m[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int j = g + 4 * q;  // S(i, c) at c N + i (column-major)
+        const int j = NQ * g + q;  // S(i, c) at c N + i (column-major)
         m[q] = j < N ? (i == j ? 1.0 : 0.0) - Sb[j * N + i] : (i == j - N ? 1.0 : 0.0) + Sb[(j - N) * N + i];
     }
     for (int e = tid; e < N * N; e += NT) Qs[e] = Qref[e];  // column-major Qref: e = i N + r
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int b = k & 1;
-        if (i == k) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) prow[b][g + 4 * q] = m[q];
-        }
-        if (g == (k & 3)) mcol[b][i] = m[k >> 2];
+        if (g == k / NQ) mcol[b][i] = m[k % NQ];
         __syncthreads();
-        const double pinv = 1.0 / prow[b][k];
-        if (i == k) {
+        const double pinv = 1.0 / mcol[b][k];
+        const double f = i == k ? 1.0 - pinv : mcol[b][i] * pinv;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) m[q] *= pinv;
-        } else {
-            const double f = mcol[b][i] * pinv;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) m[q] -= f * prow[b][g + 4 * q];
-        }
+        for (int q = 0; q < NQ; ++q) m[q] -= f * readlane_f64(m[q], k);
     }
+    if (g >= 2) {
 #pragma unroll
-    for (int q = NQ / 2; q < NQ; ++q) Xs[i * N + (g + 4 * q - N)] = m[q];
+        for (int q = 0; q < NQ; ++q) Xs[i * N + NQ * (g - 2) + q] = m[q];
+    }
     __syncthreads();
     const int r0 = 4 * (tid & 15), c0 = 4 * (tid >> 4);
     double acc[4][4] = {};

@@ -221,6 +221,30 @@ __global__ void k_skew(int batch, int n, const float *coords, const float *mean,
     S[e] = v;
 }
 
+// The same, one workgroup per matrix for n(n-1)/2 <= MAXNC: the matrix's
+// coordinates are read once, coalesced, into LDS, and S is written column by
+// column (the lower triangle's gather would otherwise stride by about n).
+template <int MAXNC>
+__global__ void __launch_bounds__(256) k_skew_blk(int n, const float *coords, const float *mean, const float *stdv,
+                                                  double *S) {
+    __shared__ float cs[MAXNC];
+    const int nc = n * (n - 1) / 2, b = blockIdx.x;
+    const float *cb = coords + (size_t)b * nc;
+    for (int k = threadIdx.x; k < nc; k += 256) cs[k] = cb[k] * (stdv ? stdv[k] : 1.0f) + (mean ? mean[k] : 0.0f);
+    __syncthreads();
+    double *Sb = S + (size_t)b * n * n;
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+        const int i = e % n, j = e / n;  // column-major element (i, j)
+        double v = 0.0;
+        if (i != j) {
+            const int lo = min(i, j), hi = max(i, j);
+            const float c = cs[lo * n - lo * (lo + 1) / 2 + (hi - lo - 1)];
+            v = i < j ? (double)c : -(double)c;
+        }
+        Sb[e] = v;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -307,6 +331,12 @@ void skew_from_coords(int batch, int n, const float *coords, const float *mean, 
                       hipStream_t s) {
     const size_t total = (size_t)batch * n * n;
     if (total == 0) return;
+    constexpr int MAXNC = 128 * 127 / 2;
+    if (n * (n - 1) / 2 <= MAXNC) {
+        hipLaunchKernelGGL(k_skew_blk<MAXNC>, dim3(batch), dim3(256), 0, s, n, coords, mean, stdv, S);
+        JX_LAUNCHED();
+        return;
+    }
     hipLaunchKernelGGL(k_skew, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, batch, n, coords, mean, stdv, S);
     JX_LAUNCHED();
 }
