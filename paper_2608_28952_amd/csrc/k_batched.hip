@@ -14,7 +14,8 @@
 //   * low precision: A and Q stored in FP32, tile products in FP32 MFMA with
 //     FP32 accumulation, pair problems and rotation angles in FP64; sweeps
 //     until off(A) <= lp_switch ||A||_F or the decrease stalls;
-//   * FP64 refinement: two Newton-Schulz steps Q <- Q (3 I - Q^T Q) / 2, the
+//   * FP64 refinement: two Newton-Schulz steps Q <- Q (3 I - Q^T Q) / 2 (one
+//     from a warm start Q0), the
 //     recomputed A_1 = Q^T A Q from the input (FP64 MFMA), then FP64 sweeps
 //     until off(A_1) <= tol ||A||_F; eigenvalues sorted ascending with their
 //     vectors.  With a warm start Q0 the refinement starts from Q0 and falls
@@ -365,8 +366,13 @@ __global__ void __launch_bounds__((KCfg<BS, NPP>::NT)) k_batched_hp(BatchArgs a)
         double *Acur = A0;
         int fallback = 0;
         if (warm || sw32 > 0) {
-            // two Newton-Schulz steps, then A_1 = Q^T A Q from the input
-            for (int it = 0; it < 2; ++it) {
+            // Newton-Schulz steps, then A_1 = Q^T A Q from the input.  Q from
+            // the FP32 phase is orthogonal to about FP32 accuracy: two steps.
+            // A warm start (an FP64 Cayley map) is orthogonal to working
+            // accuracy: one step (a start with orthogonality error e leaves
+            // it with about e^2).
+            const int ns = warm ? 1 : 2;
+            for (int it = 0; it < ns; ++it) {
                 gemm_wg<NT, M2>(T, 1.0, true, Q, Q, 0.0, nullptr);
                 gemm_wg<NT, M2>(U, -0.5, false, Q, T, 1.5, Q);
                 double *tmp = Q;
