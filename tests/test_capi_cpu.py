@@ -132,3 +132,23 @@ def test_batched_tuning_defaults_without_cache(monkeypatch):
         assert bs in (8, 16) and mixed in (0, 1) and from_file is False
     with pytest.raises(Exception):
         jx.batched_tuning(False, 5)
+
+
+def test_batched_info_array_matches_the_c_struct():
+    """The numpy structured dtype that receives jacobi_info from the batched
+    call has the C struct's field offsets and size, and its dict form equals
+    the per-struct as_dict()."""
+    import numpy as np
+    jx = _jx()
+    dt = jx._info_dtype()
+    assert dt.itemsize == ctypes.sizeof(jx.Info)
+    for name in dt.names:
+        assert dt.fields[name][1] == getattr(jx.Info, name).offset, name
+    infos = (jx.Info * 5)()
+    for k in range(5):
+        infos[k].status, infos[k].sweeps, infos[k].fallback_used = k % 3, 4 + k, k % 2
+        infos[k].sweeps_by_prec[0], infos[k].sweeps_by_prec[1], infos[k].sweeps_by_prec[2] = k, 2 * k, 3
+        infos[k].off_rel, infos[k].seconds = 1e-15 * (k + 1), 0.25 * k
+    arr = np.frombuffer(bytes(infos), dtype=dt)
+    assert jx._info_dicts(arr, 5) == [infos[k].as_dict() for k in range(5)]
+    assert jx._info_dicts(arr, 0) == []
