@@ -443,10 +443,40 @@ int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
  *   tol     a pair (p, q) is rotated when |g_p^T g_q| > tol sqrt(|g_p|^2 |g_q|^2);
  *           the sweeps stop when a sweep rotates nothing
  *   order   0 = row-cyclic, 1 = round-robin
+ *   nthreads > 1 with order 1: the pairs of a round are disjoint column pairs,
+ *           each rotation touching only its own two columns of G and V, so
+ *           they run in parallel with the same result as one after another
  */
+/* One Hestenes step on columns p, q of G (m rows) and V (n rows); returns 1
+ * when the pair was rotated. */
+static int hestenes_pair(int m, int n, double *G, double *Vw, int p, int q, double tol)
+{
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double gp = G[IDX(i, p, m)], gq = G[IDX(i, q, m)];
+        al += gp * gp;
+        be += gq * gq;
+        ga += gp * gq;
+    }
+    if (!(fabs(ga) > tol * sqrt(al * be))) return 0;
+    double c, s, t;
+    schur2(al, be, ga, &c, &s, &t);
+    for (int i = 0; i < m; ++i) {
+        double gp = G[IDX(i, p, m)], gq = G[IDX(i, q, m)];
+        G[IDX(i, p, m)] = c * gp - s * gq;
+        G[IDX(i, q, m)] = s * gp + c * gq;
+    }
+    for (int i = 0; i < n; ++i) {
+        double vp = Vw[IDX(i, p, n)], vq = Vw[IDX(i, q, n)];
+        Vw[IDX(i, p, n)] = c * vp - s * vq;
+        Vw[IDX(i, q, n)] = s * vp + c * vq;
+    }
+    return 1;
+}
+
 int ora_svd(int m, int n, const double *G_in, int ldg, double *S, double *U, int ldu,
-            double *V, int ldv, double tol, int max_sweeps, int order, int *sweeps_out,
-            long long *rot_out)
+            double *V, int ldv, double tol, int max_sweeps, int order, int nthreads,
+            int *sweeps_out, long long *rot_out)
 {
     if (n < 0) return -2;
     if (m < n) return -1;
@@ -468,7 +498,6 @@ int ora_svd(int m, int n, const double *G_in, int ldg, double *S, double *U, int
         rr_pairs = plist;
         rr_sizes = (int *)malloc(sizeof(int) * (size_t)(n + 1));
         rounds = ora_rr_list(n, rr_pairs, rr_sizes);
-        (void)rounds;
     } else {
         int k = 0;
         for (int p = 0; p < n - 1; ++p)
@@ -478,31 +507,22 @@ int ora_svd(int m, int n, const double *G_in, int ldg, double *S, double *U, int
     long long nrot = 0;
     while (sweeps < max_sweeps) {
         int rotated = 0;
-        for (int k = 0; k < npairs_total; ++k) {
-            int p = plist[2 * k], q = plist[2 * k + 1];
-            double al = 0.0, be = 0.0, ga = 0.0;
-            for (int i = 0; i < m; ++i) {
-                double gp = G[IDX(i, p, m)], gq = G[IDX(i, q, m)];
-                al += gp * gp;
-                be += gq * gq;
-                ga += gp * gq;
+        if (order == 1 && nthreads > 1 && n >= 2) {
+            int base = 0;
+            for (int K = 0; K < rounds; ++K) {
+                const int np = rr_sizes[K];
+                const int *pr = plist + 2 * base;
+                base += np;
+                int rk = 0;
+#pragma omp parallel for num_threads(nthreads) reduction(+ : rk) schedule(dynamic, 1)
+                for (int k = 0; k < np; ++k) rk += hestenes_pair(m, n, G, Vw, pr[2 * k], pr[2 * k + 1], tol);
+                rotated += rk;
             }
-            if (!(fabs(ga) > tol * sqrt(al * be))) continue;
-            double c, s, t;
-            schur2(al, be, ga, &c, &s, &t);
-            for (int i = 0; i < m; ++i) {
-                double gp = G[IDX(i, p, m)], gq = G[IDX(i, q, m)];
-                G[IDX(i, p, m)] = c * gp - s * gq;
-                G[IDX(i, q, m)] = s * gp + c * gq;
-            }
-            for (int i = 0; i < n; ++i) {
-                double vp = Vw[IDX(i, p, n)], vq = Vw[IDX(i, q, n)];
-                Vw[IDX(i, p, n)] = c * vp - s * vq;
-                Vw[IDX(i, q, n)] = s * vp + c * vq;
-            }
-            ++rotated;
-            ++nrot;
+        } else {
+            for (int k = 0; k < npairs_total; ++k)
+                rotated += hestenes_pair(m, n, G, Vw, plist[2 * k], plist[2 * k + 1], tol);
         }
+        nrot += rotated;
         ++sweeps;
         if (!all_finite(m, n, G, m)) { status = 2; break; }
         if (rotated == 0) { status = 0; break; }
@@ -669,7 +689,10 @@ double ora_check_offnorm(int n, const double *A, int lda)
 /*
  * out[0] = ||A - Q diag(W) Q^T||_F / ||A||_F, out[1] = ||Q^T Q - I||_F,
  * out[2] = trace(A) - sum(W), out[3] = ||A||_F^2 - sum(W^2) (relative to ||A||_F^2).
- * All sums in long double; OpenMP-parallel over columns of the products.
+ * All sums in long double.  Column j of Q diag(W) Q^T is accumulated as
+ * sum_k (Q(j,k) W(k)) Q(:,k), so every inner loop runs down a column
+ * (contiguous), and the Gram entries q_i^T q_j as column dot products; the
+ * columns are spread over OpenMP threads.
  */
 void ora_check_eig(int n, const double *A, int lda, const double *W, const double *Q, int ldq,
                    double *out)
@@ -680,20 +703,33 @@ void ora_check_eig(int n, const double *A, int lda, const double *W, const doubl
         sw += W[i];
         sw2 += (long double)W[i] * W[i];
     }
-#pragma omp parallel for reduction(+ : res, nA, orth) schedule(dynamic, 4)
-    for (int j = 0; j < n; ++j) {
-        for (int i = 0; i < n; ++i) {
-            long double s = 0.0L, o = 0.0L;
+#pragma omp parallel reduction(+ : res, nA, orth)
+    {
+        long double *acc = (long double *)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 4)
+        for (int j = 0; j < n; ++j) {
+            for (int i = 0; i < n; ++i) acc[i] = 0.0L;
             for (int k = 0; k < n; ++k) {
-                s += (long double)Q[IDX(i, k, ldq)] * W[k] * Q[IDX(j, k, ldq)];
-                o += (long double)Q[IDX(k, i, ldq)] * Q[IDX(k, j, ldq)];
+                long double f = (long double)Q[IDX(j, k, ldq)] * W[k];
+                const double *qk = Q + IDX(0, k, ldq);
+                for (int i = 0; i < n; ++i) acc[i] += f * qk[i];
             }
-            long double a = A[IDX(i, j, lda)];
-            res += (a - s) * (a - s);
-            nA += a * a;
-            o -= (i == j) ? 1.0L : 0.0L;
-            orth += o * o;
+            for (int i = 0; i < n; ++i) {
+                long double a = A[IDX(i, j, lda)];
+                res += (a - acc[i]) * (a - acc[i]);
+                nA += a * a;
+            }
+            /* Gram entries (i, j), i <= j: the off-diagonal ones count twice */
+            const double *qj = Q + IDX(0, j, ldq);
+            for (int i = 0; i <= j; ++i) {
+                const double *qi = Q + IDX(0, i, ldq);
+                long double o = 0.0L;
+                for (int k = 0; k < n; ++k) o += (long double)qi[k] * qj[k];
+                if (i == j) o -= 1.0L;
+                orth += (i == j ? 1.0L : 2.0L) * o * o;
+            }
         }
+        free(acc);
     }
     out[0] = (double)(sqrtl(res) / (nA > 0 ? sqrtl(nA) : 1.0L));
     out[1] = (double)sqrtl(orth);
@@ -744,38 +780,69 @@ void ora_check_eig_sampled(int n, const double *A, int lda, const double *W, con
 /*
  * SVD invariants: out[0] = ||G - U diag(S) V^T||_F / ||G||_F,
  * out[1] = ||V^T V - I||_F, out[2] = ||U^T U - I||_F over the columns with
- * S > 0 (zero columns of U are left out), all in long double.
+ * S > 0 (zero columns of U are left out), all in long double.  Column j of
+ * U diag(S) V^T is accumulated as sum_k (V(j,k) S(k)) U(:,k) (contiguous
+ * inner loops); Gram entries are column dot products; OpenMP over columns.
  */
 void ora_check_svd(int m, int n, const double *G, int ldg, const double *S, const double *U,
                    int ldu, const double *V, int ldv, double *out)
 {
     long double res = 0.0L, nG = 0.0L, ov = 0.0L, ou = 0.0L;
-#pragma omp parallel for reduction(+ : res, nG) schedule(dynamic, 4)
-    for (int j = 0; j < n; ++j)
-        for (int i = 0; i < m; ++i) {
-            long double s = 0.0L;
-            for (int k = 0; k < n; ++k) s += (long double)U[IDX(i, k, ldu)] * S[k] * V[IDX(j, k, ldv)];
-            long double g = G[IDX(i, j, ldg)];
-            res += (g - s) * (g - s);
-            nG += g * g;
+#pragma omp parallel reduction(+ : res, nG)
+    {
+        long double *acc = (long double *)malloc(sizeof(long double) * (size_t)(m > 0 ? m : 1));
+#pragma omp for schedule(dynamic, 4)
+        for (int j = 0; j < n; ++j) {
+            for (int i = 0; i < m; ++i) acc[i] = 0.0L;
+            for (int k = 0; k < n; ++k) {
+                long double f = (long double)V[IDX(j, k, ldv)] * S[k];
+                const double *uk = U + IDX(0, k, ldu);
+                for (int i = 0; i < m; ++i) acc[i] += f * uk[i];
+            }
+            for (int i = 0; i < m; ++i) {
+                long double g = G[IDX(i, j, ldg)];
+                res += (g - acc[i]) * (g - acc[i]);
+                nG += g * g;
+            }
         }
+        free(acc);
+    }
 #pragma omp parallel for reduction(+ : ov, ou) schedule(dynamic, 4)
     for (int j = 0; j < n; ++j)
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; i <= j; ++i) {
+            const long double w = (i == j) ? 1.0L : 2.0L; /* (i, j) and (j, i) */
             long double s = 0.0L;
             for (int k = 0; k < n; ++k) s += (long double)V[IDX(k, i, ldv)] * V[IDX(k, j, ldv)];
             if (i == j) s -= 1.0L;
-            ov += s * s;
+            ov += w * s * s;
             if (S[i] > 0.0 && S[j] > 0.0) {
                 long double u = 0.0L;
                 for (int k = 0; k < m; ++k) u += (long double)U[IDX(k, i, ldu)] * U[IDX(k, j, ldu)];
                 if (i == j) u -= 1.0L;
-                ou += u * u;
+                ou += w * u * u;
             }
         }
     out[0] = (double)(sqrtl(res) / (nG > 0 ? sqrtl(nG) : 1.0L));
     out[1] = (double)sqrtl(ov);
     out[2] = (double)sqrtl(ou);
+}
+
+/*
+ * Gram block of the one-sided method, eq. (SVD_subproblem) of §6: out =
+ * G(:, ca)^T G(:, cb) for the column lists ca (na entries) and cb (nb), the
+ * sum over all m rows taken in long double and rounded once.  out is na x nb,
+ * column-major (ld = na).
+ */
+void ora_gram(int m, const double *G, int ldg, int na, const int *ca, int nb, const int *cb, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < nb; ++j)
+        for (int i = 0; i < na; ++i) {
+            const double *gi = G + IDX(0, ca[i], ldg), *gj = G + IDX(0, cb[j], ldg);
+            long double s = 0.0L;
+            for (int k = 0; k < m; ++k) s += (long double)gi[k] * gj[k];
+            out[IDX(i, j, na)] = (double)s;
+        }
 }
 
 /* ------------------------------------------------------------------------ */

@@ -29,8 +29,10 @@ def lib():
                               ctypes.POINTER(ctypes.c_longlong)]
         L.ora_svd.restype = ctypes.c_int
         L.ora_svd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int,
-                              _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip,
-                              ctypes.POINTER(ctypes.c_longlong)]
+                              _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              _ip, ctypes.POINTER(ctypes.c_longlong)]
+        L.ora_gram.restype = None
+        L.ora_gram.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip, _dp]
         L.ora_antidiag_list.restype = ctypes.c_int
         L.ora_antidiag_list.argtypes = [ctypes.c_int, _ip, _ip]
         L.ora_rr_list.restype = ctypes.c_int
@@ -90,9 +92,11 @@ def eig(A, tol=1e-14, max_sweeps=50, order=1, Q0=None, want_vectors=True, nthrea
                         rot_identity=chk.value)
 
 
-def svd(G, tol=None, max_sweeps=60, order=1):
+def svd(G, tol=None, max_sweeps=60, order=1, nthreads=1):
     """One-sided Jacobi SVD (Alg. 6 with b = 1, Hestenes).  Returns S
-    descending, U (m x n), V (n x n), sweeps, status."""
+    descending, U (m x n), V (n x n), sweeps, status.  nthreads > 1 (with the
+    round-robin order) rotates the disjoint pairs of a round in parallel,
+    with the same result."""
     G = _f64(G)
     m, n = G.shape
     if tol is None:
@@ -103,8 +107,19 @@ def svd(G, tol=None, max_sweeps=60, order=1):
     sw = ctypes.c_int(0)
     nr = ctypes.c_longlong(0)
     rc = lib().ora_svd(m, n, _p(G), max(m, 1), _p(S), _p(U), max(m, 1), _p(V), max(n, 1),
-                       tol, max_sweeps, order, ctypes.byref(sw), ctypes.byref(nr))
+                       tol, max_sweeps, order, nthreads, ctypes.byref(sw), ctypes.byref(nr))
     return OracleResult(S=S, U=U, V=V, sweeps=sw.value, rotations=nr.value, status=rc)
+
+
+def gram(G, cols_a, cols_b):
+    """G(:, cols_a)^T G(:, cols_b) summed in long double (eq. SVD_subproblem, §6)."""
+    G = _f64(G)
+    m = G.shape[0]
+    ca = np.ascontiguousarray(cols_a, dtype=np.int32)
+    cb = np.ascontiguousarray(cols_b, dtype=np.int32)
+    out = np.zeros((len(ca), len(cb)), order="F")
+    lib().ora_gram(m, _p(G), max(m, 1), len(ca), ca.ctypes.data_as(_ip), len(cb), cb.ctypes.data_as(_ip), _p(out))
+    return out
 
 
 def antidiag_list(P):

@@ -423,3 +423,211 @@ def test_checker_detects_errors():
     assert samp[0] < 1e-14 and samp[1] < 1e-13
     assert O.check_offnorm(np.diag([1.0, 2.0])) == 0.0
     assert abs(O.check_offnorm(np.array([[0.0, 3.0], [4.0, 0.0]])) - 5.0) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# Checkers: planted errors of known size must be reported at that size
+# --------------------------------------------------------------------------
+# Each case perturbs an exact decomposition by a rank-one or 2 x 2 change whose
+# effect on the measured quantity has a closed form, and requires the checker
+# to report that value (relative 1e-3, far above the ~1e-14 rounding of the
+# unperturbed decomposition).  A checker that dropped a term, a column or a
+# sample, or returned zeros, fails here.
+
+def _eig_exact(n, seed):
+    A, _ = inputs.eig_uniform(n, seed)
+    r = O.eig(A)
+    assert r.status == 0
+    return A, r.W, r.Q
+
+
+def _rot(Q, c, d, phi):
+    """Columns c, d of Q rotated by phi: q_c' = cos q_c + sin q_d, q_d' = -sin q_c + cos q_d."""
+    Q = Q.copy()
+    qc, qd = Q[:, c].copy(), Q[:, d].copy()
+    Q[:, c] = math.cos(phi) * qc + math.sin(phi) * qd
+    Q[:, d] = -math.sin(phi) * qc + math.cos(phi) * qd
+    return Q
+
+
+def _close(got, want, rel=1e-3):
+    assert abs(got - want) <= rel * abs(want), (got, want)
+
+
+def test_check_eig_reports_planted_errors():
+    A, W, Q = _eig_exact(24, 11)
+    fro = np.linalg.norm(A)
+    # column c scaled by (1 + e): Q^T Q - I gains (2e + e^2) at (c, c); the
+    # residual gains lambda_c (2e + e^2) q_c q_c^T
+    e, c = 1e-6, 5
+    Qs = Q.copy()
+    Qs[:, c] *= 1.0 + e
+    res, orth, _, _ = O.check_eig(A, W, Qs)
+    _close(orth, 2 * e + e * e)
+    _close(res, abs(W[c]) * (2 * e + e * e) / fro)
+    # two columns rotated by phi: still orthogonal, residual sqrt(2) |l_c - l_d| |sin phi|
+    c, d, phi = 3, 17, 1e-5
+    res, orth, _, _ = O.check_eig(A, W, _rot(Q, c, d, phi))
+    assert orth < 1e-13
+    _close(res, math.sqrt(2) * abs(W[c] - W[d]) * abs(math.sin(phi)) / fro)
+    # an eigenvalue moved by delta: residual |delta| / ||A||_F, trace off by -delta
+    Wd = W.copy()
+    Wd[7] += 3e-7
+    res, orth, dtr, _ = O.check_eig(A, Wd, Q)
+    _close(res, 3e-7 / fro)
+    _close(dtr, -3e-7, rel=1e-6)
+
+
+def test_check_eig_sampled_reports_planted_errors():
+    A, W, Q = _eig_exact(24, 12)
+    fro = np.linalg.norm(A)
+    c, d, phi = 4, 9, 2e-6
+    Qr = _rot(Q, c, d, phi)
+    # A q_c' - l_c q_c' = sin(phi) (l_d - l_c) q_d
+    res, orth = O.check_eig_sampled(A, W, Qr, [0, c, 20])
+    _close(res, abs(math.sin(phi) * (W[d] - W[c])) / fro)
+    assert orth < 1e-13
+    # a column outside the sample is not seen; inside it is
+    res, _ = O.check_eig_sampled(A, W, Qr, [0, 1, 20])
+    assert res < 1e-14
+    e = 4e-7
+    Qs = Q.copy()
+    Qs[:, 11] *= 1.0 + e
+    res, orth = O.check_eig_sampled(A, W, Qs, [2, 11])
+    _close(orth, 2 * e + e * e)
+    assert res < 1e-14  # a scaled eigenvector still satisfies A q = l q
+    Wd = W.copy()
+    Wd[2] -= 5e-8
+    res, orth = O.check_eig_sampled(A, Wd, Q, [2, 11])
+    _close(res, 5e-8 / fro)
+
+
+def _svd_exact(m, n, seed):
+    G, _ = inputs.svd_case(m, n, seed)
+    r = O.svd(G)
+    assert r.status == 0
+    return G, r.S, r.U, r.V
+
+
+def test_check_svd_reports_planted_errors():
+    G, S, U, V = _svd_exact(40, 16, 13)
+    fro = np.linalg.norm(G)
+    res, ov, ou = O.check_svd(G, S, U, V)
+    assert res < 1e-14 and ov < 1e-13 and ou < 1e-13
+    # sigma_c moved by delta: G - U S' V^T = -delta u_c v_c^T
+    Sd = S.copy()
+    Sd[3] += 2e-7
+    res, ov, ou = O.check_svd(G, Sd, U, V)
+    _close(res, 2e-7 / fro)
+    assert ov < 1e-13 and ou < 1e-13
+    # V column scaled: ||V^T V - I|| = 2e + e^2, residual sigma_c e
+    e = 1e-6
+    Vs = V.copy()
+    Vs[:, 5] *= 1.0 + e
+    res, ov, ou = O.check_svd(G, S, U, Vs)
+    _close(ov, 2 * e + e * e)
+    _close(res, S[5] * e / fro)
+    # U column scaled: ||U^T U - I|| = 2e + e^2
+    Us = U.copy()
+    Us[:, 6] *= 1.0 + e
+    res, ov, ou = O.check_svd(G, S, Us, V)
+    _close(ou, 2 * e + e * e)
+    _close(res, S[6] * e / fro)
+    # two U columns rotated by phi: U stays orthonormal, residual
+    # ||(I - R) diag(s_c, s_d)||_F = sqrt((s_c^2 + s_d^2)(2 - 2 cos phi))
+    c, d, phi = 1, 12, 1e-4
+    res, ov, ou = O.check_svd(G, S, _rot(U, c, d, phi), V)
+    assert ou < 1e-13
+    _close(res, math.sqrt((S[c] ** 2 + S[d] ** 2) * (2 - 2 * math.cos(phi))) / fro)
+
+
+def test_check_svd_zero_sigma_columns_left_out():
+    G, S, U, V = _svd_exact(30, 8, 14)
+    S0, U0 = S.copy(), U.copy()
+    S0[-1] = 0.0
+    U0[:, -1] = 0.0
+    _, _, ou = O.check_svd(G, S0, U0, V)
+    assert ou < 1e-13
+
+
+def test_check_svd_sampled_reports_planted_errors():
+    G, S, U, V = _svd_exact(40, 16, 15)
+    fro = np.linalg.norm(G)
+    cols = [0, 5, 11]
+    res, wv, wu = O.check_svd_sampled(G, S, U, V, cols)
+    assert res < 1e-14 and wv < 1e-13 and wu < 1e-13
+    Sd = S.copy()
+    Sd[5] -= 4e-7
+    res, _, _ = O.check_svd_sampled(G, Sd, U, V, cols)
+    _close(res, 4e-7 / fro)
+    e = 2e-6
+    Vs = V.copy()
+    Vs[:, 11] *= 1.0 + e
+    res, wv, _ = O.check_svd_sampled(G, S, U, Vs, cols)
+    _close(wv, 2 * e + e * e)
+    _close(res, S[11] * e / fro)
+    Us = U.copy()
+    Us[:, 0] *= 1.0 + e
+    res, _, wu = O.check_svd_sampled(G, S, Us, V, cols)
+    _close(wu, 2 * e + e * e)
+    _close(res, S[0] * e / fro)
+    # outside the sample: not seen
+    res, wv, wu = O.check_svd_sampled(G, Sd, U, V, [0, 11])
+    assert res < 1e-14
+
+
+def test_full_checker_agrees_with_sampled_on_all_columns():
+    # the two checkers share no code: on every column the sampled maxima are
+    # bounded by the full Frobenius norms, and a single planted error shows in both
+    A, W, Q = _eig_exact(20, 16)
+    Qs = Q.copy()
+    Qs[:, 8] *= 1.0 + 3e-6
+    full = O.check_eig(A, W, Qs)
+    samp = O.check_eig_sampled(A, W, Qs, list(range(20)))
+    _close(samp[1], full[1])
+    assert samp[0] <= full[0] * 1.0001
+
+
+# --------------------------------------------------------------------------
+# Gram blocks (eq. SVD_subproblem, §6)
+# --------------------------------------------------------------------------
+
+def test_gram_exact_on_integers():
+    # small integer entries: every product and partial sum is exact in
+    # binary floating point, so the Gram block equals the integer product
+    rng = np.random.default_rng(21)
+    m, n = 300, 20
+    Gi = rng.integers(-50, 51, size=(m, n))
+    ca, cb = [0, 3, 7, 19, 2], [5, 5, 1, 18]
+    ref = Gi[:, ca].T.astype(np.int64) @ Gi[:, cb].astype(np.int64)
+    out = O.gram(Gi.astype(np.float64), ca, cb)
+    np.testing.assert_array_equal(out, ref.astype(np.float64))
+
+
+def test_gram_matches_numpy_within_bound_and_is_symmetric():
+    rng = np.random.default_rng(22)
+    m, n = 1000, 24
+    G = rng.standard_normal((m, n)) * 10.0 ** rng.uniform(-6, 0, n)
+    I, J = list(range(0, 12)), list(range(12, 24))
+    cols = I + J
+    out = O.gram(G, cols, cols)
+    ref = G[:, cols].T @ G[:, cols]
+    bound = m * EPS * (np.abs(G[:, cols]).T @ np.abs(G[:, cols]))
+    assert np.all(np.abs(out - ref) <= bound)
+    np.testing.assert_array_equal(out, out.T)
+    np.testing.assert_array_equal(O.gram(G, I, J), O.gram(G, J, I).T)
+    # orthonormal columns: the identity
+    Qh = inputs.haar(8, rng, 200)
+    np.testing.assert_allclose(O.gram(Qh, range(8), range(8)), np.eye(8), atol=1e-14)
+
+
+def test_svd_parallel_rounds_equal_sequential():
+    # disjoint pairs of a round touch disjoint columns: the parallel form
+    # gives bit-identical results
+    G, _ = inputs.svd_case(60, 20, 23)
+    a = O.svd(G, nthreads=1)
+    b = O.svd(G, nthreads=4)
+    assert a.status == b.status == 0 and a.sweeps == b.sweeps
+    np.testing.assert_array_equal(a.S, b.S)
+    np.testing.assert_array_equal(a.U, b.U)
+    np.testing.assert_array_equal(a.V, b.V)
