@@ -235,11 +235,22 @@ static void sort_index(int n, const double *key, int *perm, int dir)
  *               off^2(after) = off^2(before) - 2 apq^2 (§1) and the largest
  *               relative deviation is stored here (O(n^2) per rotation).
  *   sweeps_out, rot_out  sweeps performed, rotations applied
+ *   relative    0: the stop test above, every nonzero a_pq rotated.  1: the
+ *               relative threshold of Demmel & Veselic (cited in §1): pair
+ *               (p, q) is rotated only when |a_pq| > tol sqrt(|a_pp a_qq|),
+ *               and the sweeps stop when a sweep rotates no pair (for a
+ *               positive definite A this computes every eigenvalue to high
+ *               relative accuracy).
  */
+static int rotate_it(double app, double aqq, double apq, double tol, int relative)
+{
+    if (apq == 0.0) return 0;
+    return relative ? fabs(apq) > tol * sqrt(fabs(app * aqq)) : 1;
+}
 int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
             const double *Q0, int ldq0, double tol, int max_sweeps, int order,
             int nthreads, long long max_rot, double *check_rot, int *sweeps_out,
-            long long *rot_out)
+            long long *rot_out, int relative)
 {
     if (n < 0) return -1;
     if (lda < (n > 1 ? n : 1)) return -3;
@@ -296,17 +307,20 @@ int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
     long long nrot = 0;
     double worst = 0.0;
 
+    long long rot_before = -1;
     for (;;) {
         double off = ora_offnorm(n, A, n);
         if (!isfinite(off)) { status = 2; break; }
-        if (off <= tol * fro0) { status = 0; break; }
+        if (!relative && off <= tol * fro0) { status = 0; break; }
+        if (relative && nrot == rot_before) { status = 0; break; }  /* the last sweep rotated nothing */
         if (sweeps >= max_sweeps) { status = 1; break; }
         if (max_rot > 0 && nrot >= max_rot) { status = 1; break; }
+        rot_before = nrot;
         if (order == 0) {
             for (int p = 0; p < n - 1; ++p)
                 for (int q = p + 1; q < n; ++q) {
                     double apq = A[IDX(p, q, n)];
-                    if (apq == 0.0) continue;
+                    if (!rotate_it(A[IDX(p, p, n)], A[IDX(q, q, n)], apq, tol, relative)) continue;
                     if (max_rot > 0 && nrot >= max_rot) break;
                     double c, s, t, before = 0.0;
                     if (check_rot) before = ora_offnorm(n, A, n);
@@ -331,7 +345,7 @@ int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
                     for (int k = 0; k < np; ++k) {
                         int p = pr[2 * k], q = pr[2 * k + 1];
                         double apq = A[IDX(p, q, n)];
-                        if (apq == 0.0) continue;
+                        if (!rotate_it(A[IDX(p, p, n)], A[IDX(q, q, n)], apq, tol, relative)) continue;
                         double c, s, t, before = 0.0;
                         if (check_rot) before = ora_offnorm(n, A, n);
                         schur2(A[IDX(p, p, n)], A[IDX(q, q, n)], apq, &c, &s, &t);
@@ -356,6 +370,7 @@ int ora_eig(int n, const double *A_in, int lda, double *W, double *Q, int ldq,
                         double apq = A[IDX(p, q, n)];
                         dpp[k] = A[IDX(p, p, n)];
                         dqq[k] = A[IDX(q, q, n)];
+                        if (!rotate_it(dpp[k], dqq[k], apq, tol, relative)) apq = 0.0;  /* not rotated */
                         cs[4 * k + 3] = apq;
                         if (apq == 0.0) { cs[4 * k] = 1.0; cs[4 * k + 1] = 0.0; cs[4 * k + 2] = 0.0; continue; }
                         schur2(A[IDX(p, p, n)], A[IDX(q, q, n)], apq, &cs[4 * k], &cs[4 * k + 1], &cs[4 * k + 2]);
@@ -843,6 +858,73 @@ void ora_gram(int m, const double *G, int ldg, int na, const int *ca, int nb, co
             for (int k = 0; k < m; ++k) s += (long double)gi[k] * gj[k];
             out[IDX(i, j, na)] = (double)s;
         }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reduced QR (the preprocessing of the one-sided SVD, §6)                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * G = Q R for m >= n: Householder reflections in long double (Golub & Van
+ * Loan §5.2), then the signs chosen so that diag(R) >= 0, which makes the
+ * factorization of a full-rank G unique.  G (m x n, ldg) is read only; Q
+ * (m x n, ldq, may be NULL) and R (n x n, ldr, zero below the diagonal) are
+ * written.  Returns 0, or -1 for m < n.
+ */
+int ora_qr(int m, int n, const double *G, int ldg, double *Q, int ldq, double *R, int ldr)
+{
+    if (m < n) return -1;
+    long double *A = (long double *)malloc(sizeof(long double) * (size_t)m * (n > 0 ? n : 1));
+    long double *V = (long double *)malloc(sizeof(long double) * (size_t)m * (n > 0 ? n : 1));
+    long double *beta = (long double *)calloc((size_t)(n > 0 ? n : 1), sizeof(long double));
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i) A[IDX(i, j, m)] = G[IDX(i, j, ldg)];
+    for (int k = 0; k < n; ++k) {
+        /* reflector H = I - beta v v^T with H A(k:m, k) = alpha e_1 */
+        long double nx = 0.0L;
+        for (int i = k; i < m; ++i) nx += A[IDX(i, k, m)] * A[IDX(i, k, m)];
+        nx = sqrtl(nx);
+        long double x0 = A[IDX(k, k, m)];
+        long double alpha = x0 >= 0.0L ? -nx : nx;
+        for (int i = 0; i < m; ++i) V[IDX(i, k, m)] = 0.0L;
+        if (nx == 0.0L) { beta[k] = 0.0L; continue; }
+        V[IDX(k, k, m)] = x0 - alpha;
+        for (int i = k + 1; i < m; ++i) V[IDX(i, k, m)] = A[IDX(i, k, m)];
+        long double vv = 0.0L;
+        for (int i = k; i < m; ++i) vv += V[IDX(i, k, m)] * V[IDX(i, k, m)];
+        beta[k] = vv > 0.0L ? 2.0L / vv : 0.0L;
+        for (int j = k; j < n; ++j) {
+            long double d = 0.0L;
+            for (int i = k; i < m; ++i) d += V[IDX(i, k, m)] * A[IDX(i, j, m)];
+            d *= beta[k];
+            for (int i = k; i < m; ++i) A[IDX(i, j, m)] -= d * V[IDX(i, k, m)];
+        }
+    }
+    /* signs: D = diag(sgn(r_kk)), R <- D R, Q <- Q D */
+    long double *sg = (long double *)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    for (int k = 0; k < n; ++k) sg[k] = A[IDX(k, k, m)] < 0.0L ? -1.0L : 1.0L;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) R[IDX(i, j, ldr)] = i <= j ? (double)(sg[i] * A[IDX(i, j, m)]) : 0.0;
+    if (Q) {
+        /* Q = H_0 H_1 ... H_{n-1} (first n columns of I), applied backwards */
+        long double *W = (long double *)calloc((size_t)m * (n > 0 ? n : 1), sizeof(long double));
+        for (int j = 0; j < n; ++j) W[IDX(j, j, m)] = 1.0L;
+        for (int k = n - 1; k >= 0; --k)
+            for (int j = 0; j < n; ++j) {
+                long double d = 0.0L;
+                for (int i = k; i < m; ++i) d += V[IDX(i, k, m)] * W[IDX(i, j, m)];
+                d *= beta[k];
+                for (int i = k; i < m; ++i) W[IDX(i, j, m)] -= d * V[IDX(i, k, m)];
+            }
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < m; ++i) Q[IDX(i, j, ldq)] = (double)(W[IDX(i, j, m)] * sg[j]);
+        free(W);
+    }
+    free(sg);
+    free(A);
+    free(V);
+    free(beta);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

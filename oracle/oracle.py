@@ -26,13 +26,15 @@ def lib():
         L.ora_eig.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp,
                               ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                               ctypes.c_int, ctypes.c_longlong, _dp, _ip,
-                              ctypes.POINTER(ctypes.c_longlong)]
+                              ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.ora_svd.restype = ctypes.c_int
         L.ora_svd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int,
                               _dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                               _ip, ctypes.POINTER(ctypes.c_longlong)]
         L.ora_gram.restype = None
         L.ora_gram.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int, _ip, _dp]
+        L.ora_qr.restype = ctypes.c_int
+        L.ora_qr.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_int]
         L.ora_antidiag_list.restype = ctypes.c_int
         L.ora_antidiag_list.argtypes = [ctypes.c_int, _ip, _ip]
         L.ora_rr_list.restype = ctypes.c_int
@@ -72,10 +74,12 @@ class OracleResult(dict):
 
 
 def eig(A, tol=1e-14, max_sweeps=50, order=1, Q0=None, want_vectors=True, nthreads=1,
-        check_rotations=False, max_rotations=0):
+        check_rotations=False, max_rotations=0, relative=False):
     """Scalar cyclic Jacobi (Alg. 1 with b = 1).  Returns W ascending, Q, sweeps,
     rotations, status and (optionally) the largest relative deviation from the
-    per-rotation identity off^2 -= 2 a_pq^2 (§1)."""
+    per-rotation identity off^2 -= 2 a_pq^2 (§1).  relative=True: rotate only
+    when |a_pq| > tol sqrt(|a_pp a_qq|), stop after a sweep without rotations
+    (the Demmel-Veselic threshold)."""
     A = _f64(A)
     n = A.shape[0]
     W = np.zeros(n)
@@ -87,7 +91,7 @@ def eig(A, tol=1e-14, max_sweeps=50, order=1, Q0=None, want_vectors=True, nthrea
     rc = lib().ora_eig(n, _p(A), max(n, 1), _p(W), _p(Q), max(n, 1), _p(Q0a), max(n, 1),
                        tol, max_sweeps, order, nthreads, max_rotations,
                        ctypes.byref(chk) if check_rotations else None, ctypes.byref(sw),
-                       ctypes.byref(nr))
+                       ctypes.byref(nr), 1 if relative else 0)
     return OracleResult(W=W, Q=Q, sweeps=sw.value, rotations=nr.value, status=rc,
                         rot_identity=chk.value)
 
@@ -120,6 +124,18 @@ def gram(G, cols_a, cols_b):
     out = np.zeros((len(ca), len(cb)), order="F")
     lib().ora_gram(m, _p(G), max(m, 1), len(ca), ca.ctypes.data_as(_ip), len(cb), cb.ctypes.data_as(_ip), _p(out))
     return out
+
+
+def qr(G, want_q=True):
+    """Reduced QR G = Q R (m >= n) by Householder reflections in long double,
+    diag(R) >= 0 (the preprocessing of the one-sided SVD, §6)."""
+    G = _f64(G)
+    m, n = G.shape
+    Q = np.zeros((m, n), order="F") if want_q else None
+    R = np.zeros((n, n), order="F")
+    rc = lib().ora_qr(m, n, _p(G), max(m, 1), _p(Q), max(m, 1), _p(R), max(n, 1))
+    assert rc == 0, rc
+    return Q, R
 
 
 def antidiag_list(P):

@@ -11,6 +11,9 @@ matrices of the shapes and spectra the workloads use.
   sigma = 10^U(-6, 0).
 * ``batched_case``: sizes n_k ~ U{nmin..nmax}, lam ~ N(0, 1), stored FP32.
 * ``warmstart_family``: A0, B_1..B_8 symmetric with upper entries N(0, 1/n).
+* ``graded_dhd``: A = D H D, H = I + E (||E||_2 = 1/2, zero diagonal), D
+  diagonal and geometrically graded: positive definite with eigenvalues that
+  the entries fix to high relative accuracy.
 """
 import numpy as np
 
@@ -108,3 +111,16 @@ def warmstart_thetas(count, seed, k=8, scale=0.1):
 def warmstart_matrices(A0, B, thetas):
     """A(theta) = A0 + sum_k theta_k B_k for each row of thetas (count x n x n)."""
     return A0[None, :, :] + np.einsum("ck,kij->cij", thetas, B)
+
+
+def graded_dhd(n, seed, span):
+    """A = D H D with H = I + E (E symmetric N(0, 1) scaled to ||E||_2 = 1/2,
+    diagonal zero) and D = diag(10^(-span i / (n - 1))).  Returns (A, d)."""
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal((n, n))
+    E = 0.5 * (E + E.T)
+    np.fill_diagonal(E, 0.0)
+    E *= 0.5 / np.linalg.norm(E, 2)
+    H = np.eye(n) + E
+    d = 10.0 ** (-span * np.arange(n) / (n - 1))
+    return np.asfortranarray((d[:, None] * H) * d[None, :]), d

@@ -631,3 +631,91 @@ def test_svd_parallel_rounds_equal_sequential():
     np.testing.assert_array_equal(a.S, b.S)
     np.testing.assert_array_equal(a.U, b.U)
     np.testing.assert_array_equal(a.V, b.V)
+
+
+# --------------------------------------------------------------------------
+# Reduced QR (preprocessing of the one-sided SVD, §6)
+# --------------------------------------------------------------------------
+
+def test_qr_recovers_constructed_factors():
+    # G = Q0 R0 with Q0 orthonormal columns and R0 upper triangular with a
+    # positive diagonal: the factorization is unique, so the oracle returns them
+    rng = np.random.default_rng(31)
+    m, n = 90, 30
+    Q0 = inputs.haar(n, rng, m)
+    R0 = np.triu(rng.standard_normal((n, n)))
+    R0[np.diag_indices(n)] = np.abs(R0[np.diag_indices(n)]) + 0.5
+    Q, R = O.qr(Q0 @ R0)
+    np.testing.assert_allclose(R, R0, atol=1e-13 * np.abs(R0).max())
+    np.testing.assert_allclose(Q, Q0, atol=1e-13)
+    assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) > 0)
+
+
+def test_qr_special_cases_and_numpy():
+    rng = np.random.default_rng(32)
+    # upper triangular with positive diagonal: Q = I, R = G
+    T = np.triu(rng.standard_normal((12, 12))) + 3 * np.eye(12)
+    Q, R = O.qr(T)
+    np.testing.assert_allclose(Q, np.eye(12), atol=1e-15)
+    np.testing.assert_allclose(R, T, atol=1e-14)
+    # orthonormal columns: R = I
+    Qh = inputs.haar(10, rng, 40)
+    Q, R = O.qr(Qh)
+    np.testing.assert_allclose(R, np.eye(10), atol=1e-14)
+    # against LAPACK through numpy, with the signs of R's diagonal made positive
+    G, _ = inputs.svd_case(200, 50, 33)
+    Qn, Rn = np.linalg.qr(G)
+    d = np.sign(np.diag(Rn))
+    Q, R = O.qr(G)
+    np.testing.assert_allclose(R, d[:, None] * Rn, atol=1e-13 * np.abs(Rn).max())
+    np.testing.assert_allclose(Q, Qn * d, atol=1e-10)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(50), atol=1e-15 * 50)
+    assert np.linalg.norm(G - Q @ R) <= 1e-15 * np.linalg.norm(G) * 10
+
+
+# --------------------------------------------------------------------------
+# Relative threshold (Demmel & Veselic): graded positive definite D H D
+# --------------------------------------------------------------------------
+
+dhd = inputs.graded_dhd  # A = D H D: eigenvalues graded over 10^-2span, fixed to relative accuracy
+
+
+def test_relative_threshold_diagonal_is_fixed_point():
+    d = 10.0 ** (-np.arange(10) * 2.0)
+    r = O.eig(np.diag(d * d), relative=True)
+    assert r.status == 0 and r.rotations == 0
+    np.testing.assert_array_equal(r.W, np.sort(d * d))
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_relative_threshold_graded_mpmath(order):
+    # every eigenvalue of a graded D H D, down to 1e-22, to high relative
+    # accuracy (mpmath at 60 digits as the reference)
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 60
+    n = 12
+    A, _ = dhd(n, 41, 11.0)
+    ref = np.sort(np.array([float(x) for x in mpmath.eigsy(mpmath.matrix(A.tolist()), eigvals_only=True)]))
+    r = O.eig(A, relative=True, tol=EPS, order=order, nthreads=4 if order else 1)
+    assert r.status == 0
+    assert np.max(np.abs(r.W - ref) / np.abs(ref)) <= 50 * n * EPS
+
+
+def test_relative_threshold_reaches_what_the_absolute_test_misses():
+    # blockdiag(diag(1 .. 0.3), 1e-20 D H D): the absolute stop test sees
+    # off(A) <= 1e-14 ||A||_F at once and returns the small block's diagonal
+    # (relative errors of order one); the relative threshold rotates it
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 60
+    S, _ = dhd(8, 42, 2.0)
+    n = 16
+    A = np.zeros((n, n))
+    A[:8, :8] = np.diag(np.linspace(1.0, 0.3, 8))
+    A[8:, 8:] = 1e-20 * S
+    ref = np.sort(np.array([float(x) for x in mpmath.eigsy(mpmath.matrix(A.tolist()), eigvals_only=True)]))
+    ab = O.eig(A, tol=1e-14)
+    assert ab.status == 0 and ab.sweeps == 0
+    assert np.max(np.abs(ab.W - ref) / np.abs(ref)) > 1e-2
+    r = O.eig(A, relative=True, tol=EPS)
+    assert r.status == 0 and r.sweeps >= 2
+    assert np.max(np.abs(r.W - ref) / np.abs(ref)) <= 50 * n * EPS
