@@ -25,8 +25,14 @@
  *     calls return after the results are complete (they synchronise `stream`),
  *     because the sweep count and status are reported on the host.
  *   - Scratch memory: `dWork`/`workBytes` may supply device workspace of at
- *     least the size returned by the matching *_workspace query; if dWork is
- *     NULL the library allocates (and frees) the workspace itself.
+ *     least the size returned by the matching *_workspace query; then the call
+ *     allocates no device memory.  If dWork is NULL the library allocates (and
+ *     frees) the workspace itself.
+ *   - Per-device context: the first call on a device (or jacobi_init) creates
+ *     a second stream, a few events and 4 KiB of pinned host memory for that
+ *     device, kept until the process ends.  jacobi_eig and jacobi_svd use them
+ *     and run one at a time per device (a mutex); calls on different devices
+ *     run concurrently.
  *   - Return value (also stored in info->status when info is non-NULL):
  *         0    success
  *        -i    argument i (1-based) is invalid
@@ -49,14 +55,19 @@ extern "C" {
 typedef struct ihipStream_t *jacobi_stream_t; /* the same type as hipStream_t */
 
 enum jacobi_order {
-    JACOBI_ORDER_ROUND_ROBIN = 0, /* N-1 rounds of N/2 disjoint block pairs */
-    JACOBI_ORDER_ANTIDIAG = 1     /* Alg. 3: groups I + J = K (mod N)       */
+    JACOBI_ORDER_ROUND_ROBIN = 0,       /* N-1 rounds of N/2 disjoint block pairs     */
+    JACOBI_ORDER_ANTIDIAG = 1,          /* Alg. 3: groups I + J = K (mod N)           */
+    JACOBI_ORDER_ROUND_ROBIN_SORTED = 2 /* eig: round-robin, the indices permuted
+                                           before each sweep so that the diagonal
+                                           is ascending (A <- P^T A P, Q <- Q P);
+                                           svd: as round-robin                     */
 };
 
 enum jacobi_prec {
     JACOBI_PREC_FP64 = 0,       /* every sweep in FP64                            */
     JACOBI_PREC_MIXED_FP32 = 1, /* FP32 MFMA sweeps, then FP64 recovery sweeps    */
-    JACOBI_PREC_MIXED_BF16 = 2  /* BF16 MFMA, then FP32, then FP64 sweeps         */
+    JACOBI_PREC_MIXED_BF16 = 2  /* reserved: BF16 sweeps are not implemented; the
+                                   solvers return the opts argument's error code */
 };
 
 enum jacobi_dtype { JACOBI_F32 = 0, JACOBI_F64 = 1 };
@@ -67,8 +78,11 @@ typedef struct {
                              svd: stop when every column pair has
                              |g_i^T g_j| <= tol * |g_i| |g_j| (sqrt(m) * eps) */
     int max_sweeps;       /* default 60 */
-    int block;            /* b; 0 = default (64 for n > 512, smaller below) */
-    int ordering;         /* enum jacobi_order */
+    int block;            /* b; 0 = default (64 for n > 512, smaller below); eig
+                             also 1 = scalar Jacobi (Alg. 1 with b = 1, round-
+                             robin rounds of n/2 rotations in one workgroup;
+                             n <= 1024, FP64, no warm start) */
+    int ordering;         /* enum jacobi_order; default JACOBI_ORDER_ROUND_ROBIN_SORTED */
     int precision;        /* enum jacobi_prec */
     int inner_max_sweeps; /* cap on inner scalar sweeps per subproblem; 0 = until
                              the subproblem's off-norm <= eps ||A_hat||_F (cap 30).
@@ -81,6 +95,22 @@ typedef struct {
                              mixed precision) */
     int sort;             /* 1 = eigenvalues ascending / sigma descending (default) */
     int want_vectors;     /* 0 = eigenvalues (singular values) only; default 1 */
+    int threshold;        /* eig with block = 1: 0 = absolute stop test above
+                             (default); 1 = the relative threshold of Demmel &
+                             Veselic: a pair is rotated only when |a_pq| > tol *
+                             sqrt(|a_pp a_qq|) (tol default eps), the sweeps stop
+                             once a sweep rotates none -- every eigenvalue of a
+                             graded positive definite A to high relative
+                             accuracy.  Other paths: must be 0 */
+    int precondition;     /* svd: reduced QR first (§6, "Preprocessing with QR"):
+                             G = Q R by CholeskyQR2 on FP64 MFMA (shifted first
+                             pass if the Gram matrix is not numerically positive
+                             definite), one-sided Jacobi on R^T, U = Q V_R and
+                             V = the normalised columns of R^T V_R after
+                             Newton-Schulz steps.  1 or -1 (default) = on; 0 = off
+                             (one-sided Jacobi on G itself).  Falls back to the
+                             plain solve when the factorization fails or a
+                             singular value is zero.  eig: unused */
 } jacobi_opts;
 
 typedef struct {
@@ -94,6 +124,10 @@ typedef struct {
 
 /* Fill *o with the defaults listed above.  Returns 0, or -1 if o is NULL. */
 int jacobi_opts_default(jacobi_opts *o);
+
+/* Create the per-device context of the current HIP device now (otherwise the
+ * first solver call on the device does).  Returns 0, or 3 on a HIP error. */
+int jacobi_init(void);
 
 /* Device workspace in bytes needed by jacobi_eig / jacobi_svd /
  * jacobi_eig_batched for these sizes and options (o may be NULL = defaults). */
@@ -110,7 +144,8 @@ size_t jacobi_eig_batched_workspace(int batch, const int *h_n, int dtype, const 
  *              opts->want_vectors == 0)
  *   dQ0, ldq0  optional orthogonal start (warm start or resume from an
  *              earlier iterate): the sweeps start from Q0^T A Q0 and Q = Q0.
- *              NULL = identity.
+ *              NULL = identity.  Used when eigenvectors are requested or the
+ *              precision is mixed; ignored for FP64 eigenvalues only.
  *   dWork, workBytes, opts (NULL = defaults), info (may be NULL), stream
  */
 int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq,
@@ -144,9 +179,11 @@ int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, 
  *   dQ         out: FP64 eigenvectors (columns) at the offsets h_offA; may be
  *              NULL when opts->want_vectors == 0
  *   dQ0        optional FP64 warm starts in the layout of dQ (NULL = cold): the
- *              FP64 refinement starts from Q0 (two Newton-Schulz steps, then
- *              Q0^T A Q0); a warm start that does not lower the off-norm is
- *              replaced by the cold start (info[k].fallback_used = 1)
+ *              FP64 refinement starts from Q0 (Newton-Schulz steps
+ *              Q <- Q (3 I - Q^T Q) / 2 until one starts from
+ *              ||Q^T Q - I||_F <= 1e-8, at most four, then Q^T A Q); a warm
+ *              start that does not lower the off-norm is replaced by the cold
+ *              start (info[k].fallback_used = 1)
  *   opts       tol (0 = 1e-14: off(A) <= tol ||A||_F per matrix), max_sweeps
  *              (FP64 sweeps), block (0 = tuned per size bucket, or 8 / 16 =
  *              the block size of the two-level scheme), precision
@@ -206,8 +243,12 @@ int jacobi_batched_graph_stats(int *hits, int *builds);
  * the weights from the BF16 copy and the biases from the FP32 vector (dBias
  * = its b1, i.e. element offset 16*256 + 256*256 + 256*2016).
  * Activations: dActs holds jws_acts_bytes(batch) bytes of BF16 values per
- * call (inputs and pre-activations kept for the backward, and its scratch);
- * a backward must use the buffer of the forward of the same batch.
+ * call, row-major B x features, at these element offsets (in units of B):
+ * the forward's input X0 (B x 16, features 8..15 zero) at 0, Z1 at 16, H1 at
+ * 272, Z2 at 528, H2 at 784 (each B x 256; Z = pre-activation, H = GELU(Z));
+ * the backward's dL/dZ2 at 1040 and dL/dZ1 at 1296 (B x 256) and the BF16 copy
+ * of dL/dOut at 1552 (B x 2016).  A backward must use the buffer of the
+ * forward of the same batch.
  * All pointers are device pointers owned by the caller; row-major B x
  * features.  The calls enqueue on `stream` and return without waiting.
  * Returns 0, -i (argument i invalid) or 3 (HIP error).
@@ -239,6 +280,36 @@ int jws_skew_from_coords(int batch, int n, const float *dCoords, const float *dM
 /* dQ0[k] = dQref (I - dS[k])^{-1} (I + dS[k]) for batch skew-symmetric FP64
  * column-major n x n matrices, n <= 64. */
 int jws_cayley_batched(int batch, int n, const double *dS, const double *dQref, double *dQ0, jacobi_stream_t stream);
+
+/* Training data of the warm start.
+ * jws_family_matrices: dA[c] = dA0 + sum_t dTheta[c k + t] dB[t] for c < count,
+ *   every matrix n x n FP64 (dTheta count x k row-major, dB k matrices).
+ * jws_canonical_targets: for count solutions dQ (n x n column-major each, the
+ *   eigenvectors as columns, eigenvalues ascending; 2 <= n <= 64) and the
+ *   reference dQref: W = Qref^T Q, its columns matched to Qref's columns by
+ *   overlap (n times the largest remaining |W_ij|, ties to the lowest
+ *   i n + j), column signs making diag(W) >= 0, the column of smallest
+ *   |W_jj| (lowest j) negated when det W < 0, S = (W - I)(W + I)^{-1} (Gauss-
+ *   Jordan with partial pivoting, FP64) made exactly skew.  dCoords (count x
+ *   n(n-1)/2 FP32, row-major strictly upper entries) receives S, dKeep[c] = 1
+ *   when S is finite with max |S_ij| <= maxabs; otherwise the row is zero and
+ *   dKeep[c] = 0.
+ * jws_column_stats: mean and standard deviation (population, plus eps) of the
+ *   columns of dX (rows x cols FP32) over the rows with dKeep != 0 (`kept`
+ *   of them); dWork: jws_column_stats_work(rows, cols) bytes.  Partial sums
+ *   per 1024 rows in FP64, added in a fixed order.
+ * jws_gather_standardize: for r < kept, dXo[r] = dX[dIdx[r]] (xcols values)
+ *   and dTo[r] = (dT[dIdx[r]] - dMean) / dStd (tcols values), FP32 rows.
+ * All enqueue on `stream`; return 0, -i or 3. */
+int jws_family_matrices(int count, int n, int k, const double *dTheta, const double *dA0, const double *dB, double *dA,
+                        jacobi_stream_t stream);
+int jws_canonical_targets(int count, int n, const double *dQ, const double *dQref, float *dCoords, int *dKeep,
+                          double maxabs, jacobi_stream_t stream);
+size_t jws_column_stats_work(int rows, int cols);
+int jws_column_stats(int rows, int cols, const float *dX, const int *dKeep, int kept, float eps, float *dMean,
+                     float *dStd, double *dWork, jacobi_stream_t stream);
+int jws_gather_standardize(int kept, const int *dIdx, int xcols, const float *dX, int tcols, const float *dT,
+                           const float *dMean, const float *dStd, float *dXo, float *dTo, jacobi_stream_t stream);
 
 /* Text of the last error of the calling thread ("" if none). */
 const char *jacobi_last_error(void);
@@ -294,6 +365,36 @@ int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const in
 int jacobi_block_step32(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
                         const double *dV, const double *dD, jacobi_stream_t stream);
 
+/*
+ * The reduced QR factorization that precedes the one-sided SVD (§6,
+ * "Preprocessing with QR"), by the kernels jacobi_svd uses: G (m x n,
+ * m >= n >= 1, ldg >= m) = Q R with Q (m x n, ldq >= m) orthonormal columns and
+ * R (n x n, ldr >= n) upper triangular with a positive diagonal (zero below).
+ * CholeskyQR2 on FP64 MFMA: R_1 = chol(G^T G), Q_1 = G R_1^{-1}, then again on
+ * Q_1, R = R_2 R_1; when the first Cholesky meets a non-positive pivot, the
+ * first pass is shifted by 11 (m n + n (n + 1)) u ||G||_F^2 and CholeskyQR2
+ * follows.  Allocates its own temporaries.  Returns 0, 1 (the factorization
+ * failed: G is numerically rank deficient or not finite), -i for argument i,
+ * or 3.
+ */
+int jacobi_qr(int m, int n, const double *dG, int ldg, double *dQ, int ldq, double *dR, int ldr,
+              jacobi_stream_t stream);
+
+/*
+ * Gram blocks of the one-sided SVD (eq. SVD_subproblem, §6) by the kernels a
+ * jacobi_svd sweep uses: for each of the npairs column-block pairs (I, J)
+ * (0-based, I != J, block size b = 32 or 64), dAhat[p] (2b x 2b FP64,
+ * column-major, contiguous per pair) = [G_I G_J]^T [G_I G_J], where G_I =
+ * dG(:, I b .. I b + b - 1).  m >= n, n a multiple of b, ldg >= m.  The rows
+ * are summed in the row chunks a solve of this m uses (MFMA partial sums per
+ * chunk, then a fixed-order FP64 sum over chunks).  fp32 != 0: G is rounded to
+ * FP32 and the partial sums run on FP32 MFMA with FP32 accumulation (the
+ * precision ladder's FP32 phase).  Allocates its own temporaries; returns 0,
+ * -i for argument i, or 3.
+ */
+int jacobi_gram_blocks(int m, int n, int b, const double *dG, int ldg, int npairs, const int *hPairs, int fp32,
+                       double *dAhat, jacobi_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Kernel profiling (benchmarks)                                             */
 /* ------------------------------------------------------------------------ */
@@ -315,9 +416,10 @@ enum jacobi_prof_kind {
  * on != 0: from now on every launch of the kernels above records a HIP event
  * pair on its launch stream plus its algorithmic work (flops and HBM bytes
  * the method needs for that launch; skipped pairs and rotation tiles whose
- * both sides were skipped count zero; a rotated 2b x 2b subproblem counts one
- * scalar round-robin sweep: (2b - 1) rounds of b(b - 1)/2 pair-block updates
- * at 24 flops plus 2b x b rotated pairs of V at 6 flops).  Clears earlier
+ * both sides were skipped count zero; a rotated 2b x 2b subproblem counts, per
+ * inner sweep, 2b (2b - 1) / 2 scalar rotations of two rows and two columns
+ * of the full 2b x 2b matrix and two columns of V_hat, 18 * 2b flops each, and
+ * its three blocks read and written plus V_hat written).  Clears earlier
  * records.  Synchronises the device.
  * Not thread-safe against concurrent solver calls.  Returns 0 or 3.
  */

@@ -48,20 +48,33 @@ int jacobi_opts_default(jacobi_opts *o) {
     o->tol = 0.0;
     o->max_sweeps = 60;
     o->block = 0;
-    o->ordering = JACOBI_ORDER_ROUND_ROBIN;
+    o->ordering = JACOBI_ORDER_ROUND_ROBIN_SORTED;
     o->precision = JACOBI_PREC_FP64;
     o->inner_max_sweeps = 1;
     o->refine = -1;
     o->sort = 1;
     o->want_vectors = 1;
+    o->threshold = 0;
+    o->precondition = -1;
     return 0;
 }
 
 const char *jacobi_last_error(void) { return jx::last_error(); }
 
+int jacobi_init(void) {
+    g_last_error.clear();
+    try {
+        (void)device_ctx();
+        return 0;
+    } catch (const HipFail &) {
+        return 3;
+    }
+}
+
 size_t jacobi_eig_workspace(int n, const jacobi_opts *o) {
     if (n <= 1) return 256;
     jacobi_opts r = resolve(o);
+    if (r.block == 1) return n <= 1024 ? scalar_workspace(n) : 0;
     if (r.block != 0 && r.block != 32 && r.block != 64) return 0;
     return plan_eig(n, r).total;
 }
@@ -85,15 +98,30 @@ int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *
     if (o.want_vectors && n > 0 && !dQ) return fail(-6, "dQ is NULL but vectors were requested");
     if (o.want_vectors && ldq < (n > 1 ? n : 1)) return fail(-7, "ldq < n");
     if (dQ0 && ldq0 < (n > 1 ? n : 1)) return fail(-9, "ldq0 < n");
-    if (o.block != 0 && o.block != 32 && o.block != 64) return fail(-12, "opts->block must be 0, 32 or 64");
-    if (o.ordering != JACOBI_ORDER_ROUND_ROBIN && o.ordering != JACOBI_ORDER_ANTIDIAG)
+    if (o.block != 0 && o.block != 1 && o.block != 32 && o.block != 64)
+        return fail(-12, "opts->block must be 0, 1, 32 or 64");
+    if (o.ordering != JACOBI_ORDER_ROUND_ROBIN && o.ordering != JACOBI_ORDER_ANTIDIAG &&
+        o.ordering != JACOBI_ORDER_ROUND_ROBIN_SORTED)
         return fail(-12, "opts->ordering invalid");
-    if (o.precision < 0 || o.precision > 2) return fail(-12, "opts->precision invalid");
+    if (o.precision != JACOBI_PREC_FP64 && o.precision != JACOBI_PREC_MIXED_FP32)
+        return fail(-12, "opts->precision must be JACOBI_PREC_FP64 or JACOBI_PREC_MIXED_FP32");
+    if (o.block == 1 && (n > 1024 || o.precision != JACOBI_PREC_FP64))
+        return fail(-12, "opts->block = 1 (scalar Jacobi) takes n <= 1024 and JACOBI_PREC_FP64");
+    if (o.block == 1 && dQ0) return fail(-8, "no warm start with opts->block = 1");
+    if (o.threshold != 0 && (o.threshold != 1 || o.block != 1))
+        return fail(-12, "opts->threshold = 1 (relative) needs opts->block = 1");
     if (n == 0) {
         if (info) info->status = 0;
         return 0;
     }
     return guarded(info, [&]() -> int {
+        if (n > 1 && o.block == 1) {
+            const int rc = run_eig_scalar(n, dA, lda, uplo, dW, o.want_vectors ? dQ : nullptr, ldq, dWork, workBytes,
+                                          o, info, s);
+            if (rc == -100) set_error("workspace too small");
+            if (info) info->status = rc;
+            return rc;
+        }
         if (n == 1) {  // W = A, Q = 1
             JX_HIP(hipMemcpyAsync(dW, dA, sizeof(double), hipMemcpyDeviceToDevice, s));
             if (o.want_vectors) {
@@ -108,8 +136,8 @@ int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *
             if (info) info->status = st;
             return st;
         }
-        const int rc = run_eig(n, dA, lda, uplo, dW, o.want_vectors ? dQ : nullptr, ldq, o.want_vectors ? dQ0 : nullptr,
-                               ldq0, dWork, workBytes, o, info, s);
+        const int rc = run_eig(n, dA, lda, uplo, dW, o.want_vectors ? dQ : nullptr, ldq, dQ0, ldq0, dWork, workBytes,
+                               o, info, s);
         if (rc == -100) set_error("workspace too small");
         if (info) info->status = rc;
         return rc;
@@ -142,9 +170,12 @@ int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, 
     if (o.want_vectors && ldu < (m > 1 ? m : 1)) return fail(-7, "ldu < m");
     if (o.want_vectors && ldv < (n > 1 ? n : 1)) return fail(-9, "ldv < n");
     if (o.block != 0 && o.block != 32 && o.block != 64) return fail(-12, "opts->block must be 0, 32 or 64");
-    if (o.ordering != JACOBI_ORDER_ROUND_ROBIN && o.ordering != JACOBI_ORDER_ANTIDIAG)
+    if (o.ordering != JACOBI_ORDER_ROUND_ROBIN && o.ordering != JACOBI_ORDER_ANTIDIAG &&
+        o.ordering != JACOBI_ORDER_ROUND_ROBIN_SORTED)
         return fail(-12, "opts->ordering invalid");
-    if (o.precision < 0 || o.precision > 2) return fail(-12, "opts->precision invalid");
+    if (o.precision != JACOBI_PREC_FP64 && o.precision != JACOBI_PREC_MIXED_FP32)
+        return fail(-12, "opts->precision must be JACOBI_PREC_FP64 or JACOBI_PREC_MIXED_FP32");
+    if (o.threshold != 0) return fail(-12, "opts->threshold must be 0 for the SVD");
     if (n == 0) {
         if (info) info->status = 0;
         return 0;
@@ -195,6 +226,42 @@ static int block_step(int n, int b, double *dA, double *dQ, int npairs, const in
     }
     return guarded(nullptr, [&]() -> int {
         return run_block_step(n, b, dA, dQ, npairs, hPairs, dV, dD, f32, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+int jacobi_qr(int m, int n, const double *dG, int ldg, double *dQ, int ldq, double *dR, int ldr,
+              jacobi_stream_t stream) {
+    if (n < 1) return -2;
+    if (m < n) return -1;
+    if (!dG) return -3;
+    if (ldg < m) return -4;
+    if (!dQ) return -5;
+    if (ldq < m) return -6;
+    if (!dR) return -7;
+    if (ldr < n) return -8;
+    return guarded(nullptr, [&]() -> int {
+        return run_qr(m, n, dG, ldg, dQ, ldq, dR, ldr, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+int jacobi_gram_blocks(int m, int n, int b, const double *dG, int ldg, int npairs, const int *hPairs, int fp32,
+                       double *dAhat, jacobi_stream_t stream) {
+    if (b != 32 && b != 64) return -3;
+    if (n <= 0 || n % b) return -2;
+    if (m < n) return -1;
+    if (!dG) return -4;
+    if (ldg < m) return -5;
+    if (npairs < 0) return -6;
+    if (npairs > 0 && !hPairs) return -7;
+    for (int k = 0; k < npairs; ++k) {
+        const int I = hPairs[2 * k], J = hPairs[2 * k + 1];
+        if (I < 0 || J < 0 || I >= n / b || J >= n / b || I == J) return -7;
+    }
+    if (npairs > 0 && !dAhat) return -9;
+    if (npairs == 0) return 0;
+    return guarded(nullptr, [&]() -> int {
+        return run_gram_blocks(m, n, b, dG, ldg, npairs, hPairs, fp32 != 0, dAhat,
+                               reinterpret_cast<hipStream_t>(stream));
     });
 }
 

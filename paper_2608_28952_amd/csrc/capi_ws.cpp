@@ -95,4 +95,46 @@ int jws_cayley_batched(int batch, int n, const double *dS, const double *dQref, 
     return ws_guard("jws_cayley_batched", bad, [&] { cayley_batched(batch, n, dS, dQref, dQ0, (hipStream_t)stream); });
 }
 
+int jws_family_matrices(int count, int n, int k, const double *dTheta, const double *dA0, const double *dB, double *dA,
+                        jacobi_stream_t stream) {
+    const int bad = count < 0 ? -1 : n < 1 ? -2 : k < 0 ? -3 : (count > 0 && k > 0 && !dTheta) ? -4
+                  : (count > 0 && !dA0) ? -5 : (count > 0 && k > 0 && !dB) ? -6 : (count > 0 && !dA) ? -7 : 0;
+    return ws_guard("jws_family_matrices", bad,
+                    [&] { family_matrices(count, n, k, dTheta, dA0, dB, dA, (hipStream_t)stream); });
+}
+
+int jws_canonical_targets(int count, int n, const double *dQ, const double *dQref, float *dCoords, int *dKeep,
+                          double maxabs, jacobi_stream_t stream) {
+    const int bad = count < 0 ? -1 : (n < 2 || n > 64) ? -2 : (count > 0 && !dQ) ? -3 : (count > 0 && !dQref) ? -4
+                  : (count > 0 && !dCoords) ? -5 : (count > 0 && !dKeep) ? -6 : !(maxabs > 0.0) ? -7 : 0;
+    return ws_guard("jws_canonical_targets", bad,
+                    [&] { canonical_targets(count, n, dQ, dQref, dCoords, dKeep, maxabs, (hipStream_t)stream); });
+}
+
+size_t jws_column_stats_work(int rows, int cols) {
+    if (rows <= 0 || cols <= 0) return 0;
+    return sizeof(double) * 2 * (size_t)cols * (size_t)((rows + STATS_CHUNK - 1) / STATS_CHUNK);
+}
+
+int jws_column_stats(int rows, int cols, const float *dX, const int *dKeep, int kept, float eps, float *dMean,
+                     float *dStd, double *dWork, jacobi_stream_t stream) {
+    const int bad = rows < 0 ? -1 : cols < 0 ? -2 : (rows > 0 && !dX) ? -3 : (rows > 0 && !dKeep) ? -4
+                  : (kept < 0 || kept > rows) ? -5 : !(eps >= 0.f) ? -6 : (cols > 0 && !dMean) ? -7
+                  : (cols > 0 && !dStd) ? -8 : (rows > 0 && cols > 0 && !dWork) ? -9 : 0;
+    return ws_guard("jws_column_stats", bad, [&] {
+        column_stats(rows, cols, dX, dKeep, kept, eps, dMean, dStd, dWork, STATS_CHUNK, (hipStream_t)stream);
+    });
+}
+
+int jws_gather_standardize(int kept, const int *dIdx, int xcols, const float *dX, int tcols, const float *dT,
+                           const float *dMean, const float *dStd, float *dXo, float *dTo, jacobi_stream_t stream) {
+    const int bad = kept < 0 ? -1 : (kept > 0 && !dIdx) ? -2 : xcols < 0 ? -3 : (kept > 0 && xcols > 0 && !dX) ? -4
+                  : tcols < 0 ? -5 : (kept > 0 && tcols > 0 && !dT) ? -6 : (tcols > 0 && !dMean) ? -7
+                  : (tcols > 0 && !dStd) ? -8 : (kept > 0 && xcols > 0 && !dXo) ? -9
+                  : (kept > 0 && tcols > 0 && !dTo) ? -10 : 0;
+    return ws_guard("jws_gather_standardize", bad, [&] {
+        gather_standardize(kept, xcols, tcols, dIdx, dX, dT, dMean, dStd, dXo, dTo, (hipStream_t)stream);
+    });
+}
+
 }  // extern "C"

@@ -133,6 +133,10 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     // original matrix, which needs Q even for eigenvalues only
     p.refine = p.mixed || (p.vectors && (o.refine == 1 || (o.refine < 0 && n >= 256)));
     p.need_q = p.vectors || p.mixed;
+    // three npad x npad FP64 temporaries: the original matrix and two GEMM
+    // results for the refinement, and for a warm start's Q0^T A Q0 (a start
+    // is used whenever Q is kept), so no call allocates beside its workspace
+    p.temps = p.refine || p.need_q;
     const size_t npad = p.npad, nb = (size_t)p.N * (p.N + 1) / 2;
     const size_t m2sq = (size_t)(2 * p.b) * (2 * p.b);
     WorkspaceBuilder wb;
@@ -153,11 +157,16 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     p.off_smap = wb.add(sizeof(int) * 4 * ((size_t)p.R * p.H * (p.H - 1) / 2 + 1));  // where a tile's blocks are copied
     p.off_xcopy = wb.add(sizeof(int) * 8 * (size_t)p.R * p.H);          // other copies per round
     p.off_copy0 = wb.add(sizeof(int) * 8 * (size_t)p.H);                // copies before a sweep's round 0
+    p.sorted = o.ordering == JACOBI_ORDER_ROUND_ROBIN_SORTED;
+    if (p.sorted) {  // re-sorting between sweeps: a second block storage and the inverse permutation
+        p.off_ablk2 = wb.add(sizeof(double) * nb * p.b * p.b);
+        p.off_inv = wb.add(sizeof(int) * npad);
+    }
     p.off_partial = wb.add(sizeof(double) * 2 * nb);
     p.off_scal = wb.add(sizeof(double) * 8);
     p.off_w = wb.add(sizeof(double) * npad);
     p.off_rank = wb.add(sizeof(int) * npad);
-    if (p.refine) {
+    if (p.temps) {
         p.off_a0 = wb.add(sizeof(double) * npad * npad);
         p.off_t1 = wb.add(sizeof(double) * npad * npad);
         p.off_t2 = wb.add(sizeof(double) * npad * npad);
@@ -215,6 +224,41 @@ struct EigState {
     float *Vbuf32(int r) const { return V32 + (size_t)(r % NVBUF) * p.H * (2 * p.b) * (2 * p.b); }
     int *Fbuf(int r) const { return flags + (size_t)(r % NVBUF) * p.H; }
 
+    // Re-sorting (ordering JACOBI_ORDER_ROUND_ROBIN_SORTED): the indices are
+    // permuted so that the diagonal is ascending, A <- P^T A P and Q <- Q P
+    // (an exact permutation), before a sweep.  Block (I, J) then holds
+    // indices whose current diagonal values are close together, so nearly
+    // equal eigenvalues meet inside one subproblem, which the inner solve
+    // separates, instead of only in the pair of their two blocks once a
+    // sweep.  Padding indices keep their places.
+    double *ablk2 = nullptr, *qspare = nullptr, *wdiag = nullptr;
+    int *rank = nullptr, *inv = nullptr;
+    void resort() {
+        const size_t nab = (size_t)p.N * (p.N + 1) / 2 * p.b * p.b;
+        if (f32) launch_extract_diag32(p.npad, p.b, ablk32, wdiag, s);
+        else launch_extract_diag(p.npad, p.b, ablk, wdiag, s);
+        launch_rank(p.n, wdiag, +1, rank, s);
+        launch_inverse_perm(p.n, p.npad, rank, inv, s);
+        if (f32) {
+            launch_permute_sym32(p.npad, p.b, inv, ablk32, reinterpret_cast<float *>(ablk2), s);
+            JX_HIP(hipMemcpyAsync(ablk32, ablk2, sizeof(float) * nab, hipMemcpyDeviceToDevice, s));
+        } else {
+            launch_permute_sym(p.npad, p.b, inv, ablk, ablk2, s);
+            JX_HIP(hipMemcpyAsync(ablk, ablk2, sizeof(double) * nab, hipMemcpyDeviceToDevice, s));
+        }
+        if (p.need_q) {
+            const size_t nq = (size_t)p.npad * p.npad;
+            if (f32) {
+                float *sp = reinterpret_cast<float *>(qspare);
+                launch_permute_cols32(p.npad, p.npad, inv, Q32, p.npad, sp, p.npad, s);
+                JX_HIP(hipMemcpyAsync(Q32, sp, sizeof(float) * nq, hipMemcpyDeviceToDevice, s));
+            } else {
+                launch_permute_cols(p.npad, p.npad, inv, Q, p.npad, qspare, p.npad, s);
+                JX_HIP(hipMemcpyAsync(Q, qspare, sizeof(double) * nq, hipMemcpyDeviceToDevice, s));
+            }
+        }
+    }
+
     // {Xi(A)^2, sum of squared diagonal}
     void norms(double &off2, double &dia2) {
         if (f32) launch_block_norms32(p.npad, p.b, ablk32, partial, scal, s);
@@ -228,12 +272,13 @@ struct EigState {
     void sweep(double skip_thr) {
         const int m2 = 2 * p.b;
         const int ntiles = p.H * (p.H - 1) / 2;
-        // subproblem work per pair and inner sweep: 2x2 pair-block updates
-        // (24 flops off the diagonal) and the V_hat rotations (6 flops per entry pair)
-        const double hi = m2 / 2;  // inner pairs per inner round
-        const double k1_flops = (double)p.H * std::max(1, inner) * (m2 - 1) *
-                                (24.0 * hi * (hi - 1) / 2 + 6.0 * m2 * hi);
-        const double k1_bytes = (double)p.H * 6.0 * p.b * p.b * sizeof(double);
+        // algorithmic work of a rotated subproblem per inner sweep: m2 (m2 - 1) / 2
+        // scalar rotations, each applied to two rows and two columns of the
+        // full m2 x m2 A_hat and to two columns of V_hat, 6 flops per entry
+        // pair: 18 m2 flops per rotation (18.7 MFLOP at m2 = 128).  Bytes:
+        // the three blocks of the pair read and written, V_hat written.
+        const double k1_flops = (double)p.H * std::max(1, inner) * (m2 * (m2 - 1) / 2.0) * 18.0 * m2;
+        const double k1_bytes = (double)p.H * (6.0 * p.b * p.b + (double)m2 * m2) * sizeof(double);
         // round 0's critical blocks as they stand (later rounds' copies are
         // written by the round before, as it produces those blocks)
         if (f32) launch_copy_blocks32(p.b, ablk32, copy0, ncopy0, sidebuf(0), s);
@@ -347,22 +392,17 @@ struct EigState {
         }
     }
 
-    void make_streams() {
-        JX_HIP(hipStreamCreateWithFlags(&sq, hipStreamNonBlocking));
-        // ordering between the two streams of one device only: the kernels'
-        // own completion makes their writes visible device-wide, so the
-        // events need no system-scope fence (cache write-back) of their own
-        const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
-        JX_HIP(hipEventCreateWithFlags(&ev_v, fl));
-        JX_HIP(hipEventCreateWithFlags(&ev_q, fl));
-        JX_HIP(hipEventCreateWithFlags(&ev_rest, fl));
+    // the device context's second stream and events (ordering between the
+    // two streams of one device only: the kernels' own completion makes
+    // their writes visible device-wide, so no system-scope fence)
+    void use_streams(DeviceCtx &c) {
+        sq = c.side;
+        ev_v = c.ev[0];
+        ev_q = c.ev[1];
+        ev_rest = c.ev[2];
     }
     ~EigState() {
         if (sq) (void)hipStreamSynchronize(sq);
-        if (ev_v) (void)hipEventDestroy(ev_v);
-        if (ev_q) (void)hipEventDestroy(ev_q);
-        if (ev_rest) (void)hipEventDestroy(ev_rest);
-        if (sq) (void)hipStreamDestroy(sq);
     }
 };
 
@@ -390,7 +430,8 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     } else if (workBytes < p.total) {
         return -100;
     }
-    PinnedScalars pin(8);
+    DeviceCtx &ctx = device_ctx();
+    std::lock_guard<std::mutex> lk(ctx.mu);
 
     EigState st{p, ws, s};
     st.ablk = reinterpret_cast<double *>(ws + p.off_ablk);
@@ -412,10 +453,17 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     st.copy0 = reinterpret_cast<int *>(ws + p.off_copy0);
     st.partial = reinterpret_cast<double *>(ws + p.off_partial);
     st.scal = reinterpret_cast<double *>(ws + p.off_scal);
-    st.h_scal = pin.ptr;
+    st.h_scal = reinterpret_cast<double *>(ctx.pinned);
     st.inner = o.inner_max_sweeps;
     st.tol = o.tol > 0.0 ? o.tol : 1e-14;
-    st.make_streams();
+    st.use_streams(ctx);
+    if (p.sorted) {
+        st.ablk2 = reinterpret_cast<double *>(ws + p.off_ablk2);
+        st.inv = reinterpret_cast<int *>(ws + p.off_inv);
+        st.wdiag = reinterpret_cast<double *>(ws + p.off_w);
+        st.rank = reinterpret_cast<int *>(ws + p.off_rank);
+        st.qspare = p.temps ? reinterpret_cast<double *>(ws + p.off_t1) : nullptr;
+    }
     struct PinnedInts {
         int *ptr = nullptr;
         ~PinnedInts() { if (ptr) (void)hipHostFree(ptr); }
@@ -430,7 +478,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
 
     // schedule and tile list (host -> device once per call)
     std::vector<int> hp, hf;
-    padded_rounds(p.N, o.ordering, hp, hf);
+    padded_rounds(p.N, o.ordering == JACOBI_ORDER_ANTIDIAG ? JACOBI_ORDER_ANTIDIAG : JACOBI_ORDER_ROUND_ROBIN, hp, hf);
     st.any_force = std::any_of(hf.begin(), hf.end(), [](int v) { return v != 0; }) ? 1 : 0;
     // tile lists: per round, the critical tiles first (tile (p, q) of round r
     // holds block (I', J') of a pair of round r + 1 (cyclically) when I' is in
@@ -538,25 +586,15 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     }
 
     // A -> upper block storage; Q = I or Q0 (then A <- Q0^T A Q0)
-    double *A0 = p.refine ? reinterpret_cast<double *>(ws + p.off_a0) : nullptr;
-    double *T1 = p.refine ? reinterpret_cast<double *>(ws + p.off_t1) : nullptr;
-    double *T2 = p.refine ? reinterpret_cast<double *>(ws + p.off_t2) : nullptr;
-    if (p.refine) launch_full_from_triangle(n, p.npad, dA, lda, uplo, A0, s);
-    if (dQ0 && p.need_q) {
+    double *A0 = p.temps ? reinterpret_cast<double *>(ws + p.off_a0) : nullptr;
+    double *T1 = p.temps ? reinterpret_cast<double *>(ws + p.off_t1) : nullptr;
+    double *T2 = p.temps ? reinterpret_cast<double *>(ws + p.off_t2) : nullptr;
+    if (p.refine || (dQ0 && p.need_q)) launch_full_from_triangle(n, p.npad, dA, lda, uplo, A0, s);
+    if (dQ0 && p.need_q) {  // A <- Q0^T A Q0 (FP64 MFMA GEMMs), Q = Q0
         launch_copy_pad(n, p.npad, dQ0, ldq0, st.Q, p.npad, s);
-        double *F = A0, *T = T1, *A1 = T2;
-        DeviceBuffer tmp;
-        if (!p.refine) {
-            tmp.alloc(sizeof(double) * 3 * (size_t)p.npad * p.npad);
-            F = reinterpret_cast<double *>(tmp.ptr);
-            T = F + (size_t)p.npad * p.npad;
-            A1 = T + (size_t)p.npad * p.npad;
-            launch_full_from_triangle(n, p.npad, dA, lda, uplo, F, s);
-        }
-        gemm_p('N', 'N', p.npad, p.npad, p.npad, 1.0, F, p.npad, st.Q, p.npad, 0.0, T, p.npad, s);
-        gemm_p('T', 'N', p.npad, p.npad, p.npad, 1.0, st.Q, p.npad, T, p.npad, 0.0, A1, p.npad, s);
-        launch_pack_sym(p.npad, p.npad, p.b, A1, p.npad, 'U', st.ablk, s);
-        JX_HIP(hipStreamSynchronize(s));
+        gemm_p('N', 'N', p.npad, p.npad, p.npad, 1.0, A0, p.npad, st.Q, p.npad, 0.0, T1, p.npad, s);
+        gemm_p('T', 'N', p.npad, p.npad, p.npad, 1.0, st.Q, p.npad, T1, p.npad, 0.0, T2, p.npad, s);
+        launch_pack_sym(p.npad, p.npad, p.b, T2, p.npad, 'U', st.ablk, s);
     } else {
         launch_pack_sym(n, p.npad, p.b, dA, lda, uplo, st.ablk, s);
         if (p.need_q) launch_set_identity(p.npad, p.npad, st.Q, p.npad, s);
@@ -592,6 +630,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             if (st.f32 && prev >= 0.0 && rel < 1e-3 && rel > 0.5 * prev) return 4;
             if (sweeps >= cap) return 1;
             prev = rel;
+            if (p.sorted) st.resort();
             st.sweep(skip_thr);
             ++sweeps;
             if (st.f32) ++sweeps32;
@@ -631,8 +670,23 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             status = phase(tol, o.max_sweeps);
         }
         // final orthogonality refinement: the sweeps after it rotate by angles of
-        // the size of Q's orthogonality error and mostly skip
-        if (status == 0 && p.refine) {
+        // the size of Q's orthogonality error and mostly skip.  Below order
+        // 256 with the automatic setting, Q's orthogonality is measured first
+        // (||Q^T Q - I||_F from one GEMM) and refined only above 2e-13.
+        bool refine_now = status == 0 && p.refine;
+        if (status == 0 && !p.refine && p.vectors && o.refine < 0 && p.temps) {
+            const int np = p.npad;
+            gemm_p('T', 'N', np, np, np, 1.0, st.Q, np, st.Q, np, 0.0, T1, np, s);
+            launch_dev_identity(n, T1, np, T2, T2 + np, s);
+            double dev2 = 0.0;
+            JX_HIP(hipMemcpyAsync(&dev2, T2 + np, sizeof(double), hipMemcpyDeviceToHost, s));
+            JX_HIP(hipStreamSynchronize(s));
+            if (!(dev2 <= 4e-26)) {
+                launch_full_from_triangle(n, p.npad, dA, lda, uplo, A0, s);
+                refine_now = true;
+            }
+        }
+        if (refine_now) {
             recompute();
             status = phase(tol, o.max_sweeps + 12);
         }
@@ -663,6 +717,80 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     inf.sweeps_by_prec[1] = sweeps32;
     inf.sweeps_by_prec[2] = sweeps - sweeps32;
     inf.off_rel = fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// b = 1: scalar two-sided Jacobi (Alg. 1 with b = 1) in round-robin order
+// ---------------------------------------------------------------------------
+
+size_t scalar_workspace(int n) {
+    const int ne = n + (n & 1);
+    WorkspaceBuilder wb;
+    wb.add(sizeof(double) * (size_t)n * n);        // A
+    wb.add(sizeof(double) * (size_t)n * n);        // Q
+    wb.add(sizeof(int) * (size_t)ne * (ne - 1));   // pairs
+    wb.add(sizeof(double) * 4);                    // sweeps, off-norm, ||A||_F
+    wb.add(sizeof(double) * n);                    // diagonal
+    wb.add(sizeof(int) * n);                       // ranks
+    return wb.total();
+}
+
+int run_eig_scalar(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq, void *dWork,
+                   size_t workBytes, const jacobi_opts &o, jacobi_info *info, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int ne = n + (n & 1);
+    const size_t total = scalar_workspace(n);
+    DeviceBuffer own;
+    char *ws = static_cast<char *>(dWork);
+    if (!ws) {
+        own.alloc(total);
+        ws = own.ptr;
+    } else if (workBytes < total) {
+        return -100;
+    }
+    WorkspaceBuilder wb;
+    double *A = reinterpret_cast<double *>(ws + wb.add(sizeof(double) * (size_t)n * n));
+    double *Q = reinterpret_cast<double *>(ws + wb.add(sizeof(double) * (size_t)n * n));
+    int *pairs = reinterpret_cast<int *>(ws + wb.add(sizeof(int) * (size_t)ne * (ne - 1)));
+    double *out = reinterpret_cast<double *>(ws + wb.add(sizeof(double) * 4));
+    double *w = reinterpret_cast<double *>(ws + wb.add(sizeof(double) * n));
+    int *rank = reinterpret_cast<int *>(ws + wb.add(sizeof(int) * n));
+    std::vector<int> hp, hs;
+    make_schedule(ne, JACOBI_ORDER_ROUND_ROBIN, hp, hs);
+    JX_HIP(hipMemcpyAsync(pairs, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, s));
+    launch_sym_full(n, dA, lda, uplo, A, s);
+    const bool vec = o.want_vectors && dQ;
+    if (vec) launch_set_identity(n, n, Q, n, s);
+    const bool rel = o.threshold == 1;
+    const double tol = o.tol > 0.0 ? o.tol : (rel ? 2.220446049250313e-16 : 1e-14);
+    launch_scalar_rr(n, ne, pairs, A, vec ? Q : nullptr, tol, o.max_sweeps, rel ? 1 : 0, out, s);
+    double h[4] = {0.0, 0.0, 0.0, 0.0};
+    JX_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    JX_HIP(hipStreamSynchronize(s));
+    const int sweeps = (int)h[0];
+    const bool done = rel ? h[3] == 0.0 : h[1] <= tol * h[2];
+    int status = (std::isfinite(h[1]) && std::isfinite(h[2])) ? (done ? 0 : 1) : 2;
+    if (status != 2) {
+        launch_diag_of(n, A, n, w, s);
+        if (o.sort) {
+            launch_rank(n, w, +1, rank, s);
+        } else {
+            std::vector<int> id(n);
+            for (int i = 0; i < n; ++i) id[i] = i;
+            JX_HIP(hipMemcpyAsync(rank, id.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+        }
+        launch_scatter_values(n, w, rank, dW, s);
+        if (vec) launch_scatter_columns(n, n, Q, n, rank, dQ, ldq, s);
+        JX_HIP(hipStreamSynchronize(s));
+    }
+    jacobi_info inf{};
+    inf.status = status;
+    inf.sweeps = sweeps;
+    inf.sweeps_by_prec[2] = sweeps;
+    inf.off_rel = h[2] > 0.0 ? h[1] / h[2] : 0.0;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
     return status;

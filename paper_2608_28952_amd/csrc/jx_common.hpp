@@ -243,6 +243,28 @@ void launch_scatter_values(int n, const double *w, const int *rank, double *out,
 void launch_scatter_columns(int rows, int n, const double *src, int lds_, const int *rank,
                             double *out, int ldo, hipStream_t s);
 
+// Scalar round-robin Jacobi (b = 1) in one persistent workgroup (k_scalar.hip):
+// A (n x n full, ld n) and Q (may be NULL) in place, ne = n rounded up to even
+// (index n a placeholder), pairs: (ne - 1) rounds of ne / 2.  relative: rotate
+// only when |a_pq| > tol sqrt(|a_pp a_qq|), stop after a sweep without
+// rotations.  out[0] = sweeps, out[1] = Xi(A), out[2] = ||A||_F, out[3] =
+// rotations of the last sweep.
+void launch_scalar_rr(int n, int ne, const int *pairs, double *A, double *Q, double tol, int max_sweeps, int relative,
+                      double *out, hipStream_t s);
+void launch_sym_full(int n, const double *src, int lds_, char uplo, double *dst, hipStream_t s);
+
+// Re-sorting between sweeps: inv from the ranks of the diagonal (identity on
+// the padding), then dst(i', j') = src(inv[i'], inv[j']) (upper block storage)
+// and dst(:, j') = src(:, inv[j']).
+void launch_inverse_perm(int n, int npad, const int *rank, int *inv, hipStream_t s);
+void launch_permute_sym(int npad, int b, const int *inv, const double *src, double *dst, hipStream_t s);
+void launch_permute_sym32(int npad, int b, const int *inv, const float *src, float *dst, hipStream_t s);
+void launch_permute_cols(int rows, int cols, const int *inv, const double *src, int lds_, double *dst, int ldd,
+                         hipStream_t s);
+void launch_permute_cols32(int rows, int cols, const int *inv, const float *src, int lds_, float *dst, int ldd,
+                           hipStream_t s);
+void launch_extract_diag32(int npad, int b, const float *ablk, double *w, hipStream_t s);
+
 // Precision ladder helpers.
 void launch_cast_to_f32(size_t count, const double *src, float *dst, hipStream_t s);
 void launch_cast_to_f64(size_t count, const float *src, double *dst, hipStream_t s);
@@ -254,6 +276,28 @@ void launch_vperm_from_colmajor(int count, int m2, const double *src, double *ds
 void launch_vperm32_from_colmajor(int count, int m2, const double *src, float *dst, hipStream_t s);
 void launch_write_pair_blocks(int count, int b, const int *pairs, const double *D, double *ablk,
                               hipStream_t s);
+
+// Reduced QR of the one-sided SVD's preprocessing (k_qr.hip).  Diagonal block
+// k0 .. k0+127 of the SPD matrix W: Cholesky W_kk = R_kk^T R_kk in place (upper
+// triangle, zero below) and R_kk^{-1} (128 x 128) to Rinv; a pivot that is not
+// positive and finite sets *flag = 1.
+void launch_chol_diag(double *W, int ldw, int k0, double *Rinv, int *flag, hipStream_t s);
+void launch_unit_pad_diag(int n, int npad, double *W, int ldw, hipStream_t s);
+void launch_shift_diag(int n, double shift, double *W, int ldw, hipStream_t s);
+void launch_zero_lower(int npad, double *W, int ldw, hipStream_t s);
+void launch_diag_of(int n, const double *X, int ldx, double *out, hipStream_t s);
+// X (npad x cols, ld npad): fixed pseudo-random values in [-1, 1) on the first n rows, zero below
+void launch_fill_probe(int n, int npad, int cols, double *X, hipStream_t s);
+// out[0] = ||Y - Z||_F^2 over m rows and `cols` columns (ld); partial: cols doubles
+void launch_diff_frob2(int m, int cols, const double *Y, const double *Z, int ld, double *partial, double *out,
+                       hipStream_t s);
+// out[0] = ||X(0:m, 0:n)||_F^2; partial: n doubles
+void launch_frob2(int m, int n, const double *X, int ldx, double *partial, double *out, hipStream_t s);
+// out[0] = ||X(0:n, 0:n) - I||_F^2; partial: n doubles
+void launch_dev_identity(int n, const double *X, int ldx, double *partial, double *out, hipStream_t s);
+// copy of the leading m x n part (destination padded with zeros to mpad x npad)
+void launch_copy_rect(int m, int n, const double *src, int lds_, double *dst, int ldd, int mpad, int npad,
+                      hipStream_t s);
 
 // General FP64 GEMM on column-major operands: C = alpha op(A) op(B) + beta C,
 // M x N result, K contraction, every dimension a multiple of 128 (16 for K).

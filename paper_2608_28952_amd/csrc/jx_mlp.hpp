@@ -38,5 +38,15 @@ void mlp_to_bf16(size_t count, const float *src, uint16_t *dst, hipStream_t s);
 void skew_from_coords(int batch, int n, const float *coords, const float *mean, const float *stdv, double *S,
                       hipStream_t s);
 void cayley_batched(int batch, int n, const double *S, const double *Qref, double *Q0, hipStream_t s);
+// k_canon.hip: training data
+void family_matrices(int count, int n, int k, const double *theta, const double *A0, const double *B, double *A,
+                     hipStream_t s);
+void canonical_targets(int count, int n, const double *Q, const double *Qref, float *coords, int *keep,
+                       double maxabs, hipStream_t s);
+constexpr int STATS_CHUNK = 1024;  // rows per partial sum of column_stats
+void column_stats(int rows, int cols, const float *X, const int *keep, int nkeep, float eps, float *mean,
+                  float *stdv, double *part, int chunk, hipStream_t s);
+void gather_standardize(int kept, int xcols, int tcols, const int *idx, const float *X, const float *T,
+                        const float *mean, const float *stdv, float *Xo, float *To, hipStream_t s);
 
 }  // namespace jx

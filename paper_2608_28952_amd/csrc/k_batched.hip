@@ -366,18 +366,24 @@ __global__ void __launch_bounds__((KCfg<BS, NPP>::NT)) k_batched_hp(BatchArgs a)
         double *Acur = A0;
         int fallback = 0;
         if (warm || sw32 > 0) {
-            // Newton-Schulz steps, then A_1 = Q^T A Q from the input.  Q from
-            // the FP32 phase is orthogonal to about FP32 accuracy: two steps.
-            // A warm start (an FP64 Cayley map) is orthogonal to working
-            // accuracy: one step (a start with orthogonality error e leaves
-            // it with about e^2).
-            const int ns = warm ? 1 : 2;
-            for (int it = 0; it < ns; ++it) {
+            // Newton-Schulz steps Q <- Q (3 I - Q^T Q) / 2, then A_1 = Q^T A Q
+            // from the input.  A step from ||Q^T Q - I||_F = e leaves about
+            // e^2, so the steps stop after the first one that starts from
+            // e <= 1e-8 (at most four: Q from the FP32 phase, e ~ 1e-6, takes
+            // two; an FP64 warm start usually one).
+            for (int it = 0; it < 4; ++it) {
                 gemm_wg<NT, M2>(T, 1.0, true, Q, Q, 0.0, nullptr);
+                double dev2 = 0.0;
+                for (int e = threadIdx.x; e < M2 * M2; e += NT) {
+                    const double d = T[e] - (e % M2 == e / M2 ? 1.0 : 0.0);
+                    dev2 += d * d;
+                }
+                dev2 = block_sum<NT>(dev2, red);
                 gemm_wg<NT, M2>(U, -0.5, false, Q, T, 1.5, Q);
                 double *tmp = Q;
                 Q = U;
                 U = tmp;
+                if (dev2 <= 1e-16) break;
             }
             gemm_wg<NT, M2>(T, 1.0, false, A0, Q, 0.0, nullptr);
             gemm_wg<NT, M2>(U, 1.0, true, Q, T, 0.0, nullptr);

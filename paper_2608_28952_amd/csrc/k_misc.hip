@@ -420,3 +420,99 @@ void launch_block_norms32(int npad, int b, const float *ablk, double *partial, d
     JX_LAUNCHED();
 }
 }  // namespace jx
+
+// ---------------------------------------------------------------------------
+// Re-sorting the indices by the current diagonal (between sweeps)
+// ---------------------------------------------------------------------------
+namespace jx {
+namespace {
+
+// inv[rank[i]] = i for i < n (rank: a permutation of 0 .. n-1); inv[i] = i
+// on the padding n .. npad-1.
+__global__ void k_inverse_perm(int n, int npad, const int *__restrict__ rank, int *__restrict__ inv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[rank[i]] = i;
+    else if (i < npad) inv[i] = i;
+}
+
+// dst(i', j') = src(inv[i'], inv[j']) in the upper block storage (block
+// order b, diagonal blocks held whole); one workgroup per stored block of dst.
+template <class T>
+__global__ void __launch_bounds__(256) k_permute_sym(int b, const int *__restrict__ inv, const T *__restrict__ src,
+                                                     T *__restrict__ dst) {
+    int I, J;
+    slot_to_block(blockIdx.x, I, J);
+    T *out = dst + ublk(I, J) * (size_t)(b * b);
+    for (int e = threadIdx.x; e < b * b; e += 256) {
+        const int r = e % b, c = e / b;
+        const int i = inv[I * b + r], j = inv[J * b + c];
+        const int bi = i / b, bj = j / b;
+        T v;
+        if (bi <= bj) v = src[ublk(bi, bj) * (size_t)(b * b) + (size_t)(j % b) * b + i % b];
+        else v = src[ublk(bj, bi) * (size_t)(b * b) + (size_t)(i % b) * b + j % b];
+        out[e] = v;
+    }
+}
+
+// dst(:, j') = src(:, inv[j']) for `rows` rows of `cols` columns.
+template <class T>
+__global__ void k_permute_cols(int rows, const int *__restrict__ inv, const T *__restrict__ src, int lds_,
+                               T *__restrict__ dst, int ldd) {
+    const int j = blockIdx.y;
+    const T *s = src + (size_t)inv[j] * lds_;
+    T *d = dst + (size_t)j * ldd;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+}  // namespace
+
+void launch_inverse_perm(int n, int npad, const int *rank, int *inv, hipStream_t s) {
+    hipLaunchKernelGGL(k_inverse_perm, dim3((npad + 255) / 256), dim3(256), 0, s, n, npad, rank, inv);
+    JX_LAUNCHED();
+}
+
+template <class T>
+static void permute_sym_t(int npad, int b, const int *inv, const T *src, T *dst, hipStream_t s) {
+    const int N = npad / b;
+    hipLaunchKernelGGL((k_permute_sym<T>), dim3(N * (N + 1) / 2), dim3(256), 0, s, b, inv, src, dst);
+    JX_LAUNCHED();
+}
+void launch_permute_sym(int npad, int b, const int *inv, const double *src, double *dst, hipStream_t s) {
+    permute_sym_t<double>(npad, b, inv, src, dst, s);
+}
+void launch_permute_sym32(int npad, int b, const int *inv, const float *src, float *dst, hipStream_t s) {
+    permute_sym_t<float>(npad, b, inv, src, dst, s);
+}
+
+template <class T>
+static void permute_cols_t(int rows, int cols, const int *inv, const T *src, int lds_, T *dst, int ldd,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_permute_cols<T>), dim3((rows + 255) / 256, cols), dim3(256), 0, s, rows, inv, src, lds_,
+                       dst, ldd);
+    JX_LAUNCHED();
+}
+void launch_permute_cols(int rows, int cols, const int *inv, const double *src, int lds_, double *dst, int ldd,
+                         hipStream_t s) {
+    permute_cols_t<double>(rows, cols, inv, src, lds_, dst, ldd, s);
+}
+void launch_permute_cols32(int rows, int cols, const int *inv, const float *src, int lds_, float *dst, int ldd,
+                           hipStream_t s) {
+    permute_cols_t<float>(rows, cols, inv, src, lds_, dst, ldd, s);
+}
+
+}  // namespace jx
+
+namespace jx {
+namespace {
+__global__ void k_extract_diag32(int npad, int b, const float *__restrict__ ablk, double *__restrict__ w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    const int I = i / b, r = i % b;
+    w[i] = (double)ablk[ublk(I, I) * (size_t)(b * b) + (size_t)r * b + r];
+}
+}  // namespace
+void launch_extract_diag32(int npad, int b, const float *ablk, double *w, hipStream_t s) {
+    hipLaunchKernelGGL(k_extract_diag32, dim3((npad + 255) / 256), dim3(256), 0, s, npad, b, ablk, w);
+    JX_LAUNCHED();
+}
+}  // namespace jx

@@ -19,6 +19,7 @@ _lib = None
 
 ORDER_ROUND_ROBIN = 0
 ORDER_ANTIDIAG = 1
+ORDER_ROUND_ROBIN_SORTED = 2
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1
 PREC_MIXED_BF16 = 2
@@ -30,7 +31,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("block", ctypes.c_int),
                 ("ordering", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_max_sweeps", ctypes.c_int), ("refine", ctypes.c_int), ("sort", ctypes.c_int),
-                ("want_vectors", ctypes.c_int)]
+                ("want_vectors", ctypes.c_int), ("threshold", ctypes.c_int), ("precondition", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -74,6 +75,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libjacobi.so not built ({LIB_PATH}); run python -m paper_2608_28952_amd.build")
+        # PyTorch first: its HIP runtime is then the one the library binds to
+        # (loaded the other way round, the process holds two HIP runtimes and
+        # the library's sees no device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.jacobi_opts_default.argtypes = [ctypes.POINTER(Opts)]
         L.jacobi_last_error.restype = ctypes.c_char_p
@@ -106,7 +111,20 @@ def lib():
         L.jws_to_bf16.argtypes = [ctypes.c_size_t, _vp, _vp, _vp]
         L.jws_skew_from_coords.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
         L.jws_cayley_batched.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
+        L.jws_family_matrices.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+        L.jws_canonical_targets.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double, _vp]
+        L.jws_column_stats_work.restype = ctypes.c_size_t
+        L.jws_column_stats_work.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.jws_column_stats.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp,
+                                       _vp, _vp]
+        L.jws_gather_standardize.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                             _vp, _vp]
+        L.jacobi_init.argtypes = []
         L.jacobi_subproblem_solve.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
+        L.jacobi_qr.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int,
+                                _vp]
+        L.jacobi_gram_blocks.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
+                                         _ip, ctypes.c_int, _vp, _vp]
         L.jacobi_block_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         L.jacobi_block_step32.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         _lib = L
@@ -177,6 +195,8 @@ def jacobi_eig(A, uplo="U", Q0=None, opts=None, work=None, check=True):
     Qt = torch.empty((n, n), dtype=torch.float64, device=A.device) if o.want_vectors else None
     q0b, ldq0 = None, max(n, 1)
     if Q0 is not None:
+        if Q0.shape != (n, n) or not Q0.is_cuda:
+            raise ValueError("Q0 must be an n x n CUDA tensor")
         q0b, ldq0 = _colmajor_view(Q0.to(torch.float64))
     info = Info()
     rc = lib().jacobi_eig(n, _ptr(Ab), lda, ul, _ptr(W), _ptr(Qt), max(n, 1), _ptr(q0b), ldq0,
@@ -238,13 +258,12 @@ def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, ch
     ho_a[:batch] = np.asarray(offsets, dtype=np.int64)[:batch]
     hn = hn_a.ctypes.data_as(_ip)
     ho = ho_a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-    dtype = F32 if packed.dtype == torch.float32 else F64
     total_w = int(hn_a[:batch].astype(np.int64).sum())
     total_q = int((ho_a[:batch] + hn_a[:batch].astype(np.int64) ** 2).max()) if batch else 0
+    check_batched_args(packed, Q0, out, total_w, total_q)
+    dtype = F32 if packed.dtype == torch.float32 else F64
     if out is not None:
         W, Q = out
-        if W.numel() < total_w or (Q is not None and Q.numel() < total_q):
-            raise ValueError("output tensors too small")
     else:
         W = torch.empty(total_w, dtype=torch.float64, device=packed.device)
         Q = torch.empty(total_q, dtype=torch.float64, device=packed.device)
@@ -257,6 +276,35 @@ def jacobi_eig_batched(sizes, offsets, packed, Q0=None, opts=None, work=None, ch
     if check:
         _check(rc)
     return W, Q, (infos[:batch] if info == "array" else _info_dicts(infos, batch))
+
+
+def check_batched_args(packed, Q0, out, total_w, total_q):
+    """Raise ValueError unless the batched call's tensors match what the
+    library will read and write: `packed` float32/float64 with at least
+    total_q elements, Q0 (optional) float64 with total_q, out W/Q float64
+    with total_w / total_q; all contiguous CUDA tensors.  (The library takes
+    raw pointers: a wrong type or a short buffer would be read or written out
+    of bounds.)"""
+    import torch
+
+    todo = [(packed, "packed", (torch.float32, torch.float64), total_q)]
+    if Q0 is not None:
+        todo.append((Q0, "Q0", (torch.float64,), total_q))
+    if out is not None:
+        W, Q = out
+        todo.append((W, "out W", (torch.float64,), total_w))
+        if Q is not None:
+            todo.append((Q, "out Q", (torch.float64,), total_q))
+    for t, name, dtypes, count in todo:
+        if t.dtype not in dtypes:
+            raise ValueError(f"{name} must be {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() < count:
+            raise ValueError(f"{name} holds {t.numel()} elements, the batch needs {count}")
+    for t, name, _, _ in todo:
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
 
 
 def batched_workspace(sizes, dtype_f64=False, opts=None):
@@ -338,3 +386,32 @@ def jacobi_block_step(A, Q, b, pairs, V, D, fp32=False):
     _check(fn(n, b, _ptr(Ac), _ptr(Qc), len(pairs), hp, _ptr(Vc), _ptr(Dc), _stream()))
     torch.cuda.synchronize()
     return Ac.t(), (Qc.t() if Qc is not None else None)
+
+
+def jacobi_gram_blocks(G, b, pairs, fp32=False):
+    """Gram blocks [G_I G_J]^T [G_I G_J] of the listed column-block pairs by the
+    SVD's kernels (float64 CUDA tensor G, m x n).  Returns a len(pairs) x 2b x 2b
+    tensor."""
+    import torch
+    m, n = G.shape
+    Gb, ldg = _colmajor_view(G)
+    out = torch.empty((len(pairs), 2 * b, 2 * b), dtype=torch.float64, device=G.device)
+    flat = [int(v) for pr in pairs for v in pr]
+    hp = (ctypes.c_int * max(len(flat), 1))(*flat)
+    _check(lib().jacobi_gram_blocks(m, n, b, _ptr(Gb), ldg, len(pairs), hp, 1 if fp32 else 0, _ptr(out), _stream()))
+    return out.transpose(1, 2)
+
+
+def jacobi_qr(G, check=True):
+    """Reduced QR G = Q R (float64 CUDA tensor G, m x n, m >= n) by the SVD's
+    preprocessing kernels.  Returns (Q, R, status): R upper triangular with a
+    positive diagonal; status 1 when the factorization failed."""
+    import torch
+    m, n = G.shape
+    Gb, ldg = _colmajor_view(G)
+    Qt = torch.empty((n, m), dtype=torch.float64, device=G.device)   # column-major m x n
+    Rt = torch.empty((n, n), dtype=torch.float64, device=G.device)
+    rc = lib().jacobi_qr(m, n, _ptr(Gb), ldg, _ptr(Qt), max(m, 1), _ptr(Rt), max(n, 1), _stream())
+    if check:
+        _check(rc, allow=(0, 1))
+    return Qt.t(), Rt.t(), rc

@@ -6,12 +6,14 @@ network proposes Q0 = Qref cay(S(theta)) and the batched Jacobi solver
 finishes from Q0^T A Q0; a proposal that does not lower the off-norm falls
 back to the cold start inside the solver.
 
-Every numerical step runs in the library's kernels (through the C-ABI):
-the batched FP64 solver generates the training solutions, the network is
-trained with jws_mlp_forward / jws_mlp_backward / jws_mse / jws_adam_step,
-and proposals use jws_skew_from_coords and jws_cayley_batched.  PyTorch holds
-device memory; the canonical training targets are prepared on the host with
-numpy (one pass over the generated solutions, not on the solve path).
+Every numerical step runs in the library's kernels (through the C-ABI): the
+family's matrices (jws_family_matrices), the batched FP64 solver that
+generates the training solutions, their canonical targets
+(jws_canonical_targets), the target statistics and standardisation
+(jws_column_stats, jws_gather_standardize), the network's training
+(jws_mlp_forward / jws_mlp_backward / jws_mse / jws_adam_step) and the
+proposals (jws_skew_from_coords, jws_cayley_batched).  PyTorch holds device
+memory; the host only draws the seeded parameters and keeps index lists.
 
     python -m paper_2608_28952_amd.warmstart [--train 262144] [--epochs 40]
 """
@@ -30,7 +32,6 @@ NIN, K1, HID = 8, 16, 256
 OFF_W1, OFF_W2, OFF_W3 = 0, K1 * HID, K1 * HID + HID * HID
 OFF_B1 = OFF_W3 + HID * NC
 NPARAM = OFF_B1 + 2 * HID + NC
-IU = np.triu_indices(N, 1)
 
 
 def _p(t):
@@ -66,10 +67,15 @@ class Family:
 
     def matrices(self, theta):
         """theta: m x 8 (numpy or CUDA tensor) -> m x n x n FP64 CUDA tensor
-        (symmetric, so row- and column-major storage coincide)."""
+        A0 + sum_k theta_k B_k (symmetric, so row- and column-major storage
+        coincide), formed by jws_family_matrices."""
         import torch
-        th = torch.as_tensor(theta, dtype=torch.float64, device="cuda")
-        return self.A0t.unsqueeze(0) + torch.tensordot(th, self.Bt, dims=([1], [0]))
+        th = torch.as_tensor(theta, dtype=torch.float64, device="cuda").contiguous()
+        m = th.shape[0]
+        A = torch.empty(m, N, N, dtype=torch.float64, device="cuda")
+        _chk(jx.lib().jws_family_matrices(m, N, NIN, _p(th), _p(self.A0t), _p(self.Bt), _p(A), _s()),
+             "jws_family_matrices")
+        return A
 
 
 def solve(A, Q0=None, precision=None, max_sweeps=60):
@@ -87,95 +93,46 @@ def solve(A, Q0=None, precision=None, max_sweeps=60):
     return W.view(m, N), Q.view(m, N, N).transpose(1, 2), infos
 
 
-def _greedy_columns(W, top=384):
-    """For each matrix of the batch W (m x n x n): the column paired with row i,
-    taking the largest remaining |W_ij| first (m x n int).  The `top` largest
-    entries of every matrix are sorted once and walked in step for the whole
-    batch; matrices left incomplete rerun the plain loop."""
-    m = W.shape[0]
-    A = np.abs(W).reshape(m, -1)
-    ar = np.arange(m)
-    c = np.full((m, N), -1, dtype=np.int64)
-    rowfree = np.ones((m, N), dtype=bool)
-    colfree = np.ones((m, N), dtype=bool)
-    k = min(top, N * N - 1)
-    idx = np.argpartition(-A, k, axis=1)[:, :k]
-    idx = np.take_along_axis(idx, np.argsort(-np.take_along_axis(A, idx, axis=1), axis=1, kind="stable"), axis=1)
-    for p in range(k):
-        i, j = idx[:, p] // N, idx[:, p] % N
-        ok = rowfree[ar, i] & colfree[ar, j]
-        a, ii, jj = ar[ok], i[ok], j[ok]
-        c[a, ii] = jj
-        rowfree[a, ii] = False
-        colfree[a, jj] = False
-    rest = np.nonzero(rowfree.any(axis=1))[0]
-    if len(rest):
-        B = A[rest].reshape(len(rest), N, N).copy()
-        r = len(rest)
-        cc = np.full((r, N), -1, dtype=np.int64)
-        br = np.arange(r)
-        for _ in range(N):
-            flat = B.reshape(r, -1).argmax(axis=1)
-            i, j = flat // N, flat % N
-            cc[br, i] = j
-            B[br, i, :] = -1.0
-            B[br, :, j] = -1.0
-        c[rest] = cc
-    return c
-
-
-def _targets_chunk(Qref, Qc):
-    """canonical_targets for one chunk (see there)."""
-    I = np.eye(N)
-    Qc = np.asarray(Qc, dtype=np.float64)
-    mc = Qc.shape[0]
-    Wm = (Qref.T @ Qc.transpose(1, 0, 2).reshape(N, -1)).reshape(N, mc, N).transpose(1, 0, 2)
-    cols = _greedy_columns(Wm)
-    Wm = np.take_along_axis(Wm, cols[:, None, :], axis=2)
-    d = np.diagonal(Wm, axis1=1, axis2=2)
-    Wm = Wm * np.where(d < 0.0, -1.0, 1.0)[:, None, :]
-    neg = np.linalg.det(Wm) < 0.0
-    if np.any(neg):
-        j = np.argmin(np.abs(np.diagonal(Wm, axis1=1, axis2=2)), axis=1)
-        idx = np.nonzero(neg)[0]
-        Wm[idx, :, j[idx]] *= -1.0
-    # S (W + I) = W - I  <=>  (W + I)^T S^T = (W - I)^T
-    lhs, rhs = np.swapaxes(Wm + I, 1, 2), np.swapaxes(Wm - I, 1, 2)
-    try:
-        St = np.linalg.solve(lhs, rhs)
-    except np.linalg.LinAlgError:  # some W + I singular: those samples are dropped
-        St = np.full_like(lhs, np.nan)
-        for q in range(mc):
-            try:
-                St[q] = np.linalg.solve(lhs[q], rhs[q])
-            except np.linalg.LinAlgError:
-                pass
-    S = np.swapaxes(St, 1, 2)
-    S = 0.5 * (S - np.swapaxes(S, 1, 2))
-    ok = np.all(np.isfinite(S), axis=(1, 2)) & (np.max(np.abs(S), axis=(1, 2)) <= 10.0)
-    return np.where(ok[:, None], S[:, IU[0], IU[1]], 0.0).astype(np.float32), ok
-
-
-def canonical_targets(Qref, Q, chunk=1024, threads=None):
-    """Generator coordinates of the solutions: W = Qref^T Q with its columns
-    matched to Qref's columns (largest remaining overlap first), column signs
-    with diag(W) >= 0, the column of smallest |W_jj| flipped when det W < 0,
-    S = (W - I)(W + I)^{-1} made exactly skew.  Matching by overlap instead of
-    eigenvalue order keeps W near I when eigenvalues cross.  Returns
-    (coords m x 2016 float32, kept mask: finite and max |S_ij| <= 10).
-    Chunks run on a thread pool (numpy releases the GIL in its kernels)."""
-    import os
-    from concurrent.futures import ThreadPoolExecutor
-    Qref = np.asarray(Qref, dtype=np.float64)
+def canonical_targets(fam, Q, maxabs=10.0):
+    """Generator coordinates of solved matrices (m x n x n CUDA tensor, Q[k] the
+    eigenvector matrix, eigenvalues ascending): jws_canonical_targets (overlap
+    matching to Qref, signs, determinant, inverse Cayley).  Returns (coords
+    m x 2016 FP32 CUDA, keep m int32 CUDA: finite and max |S_ij| <= maxabs)."""
+    import torch
     m = Q.shape[0]
-    out = np.zeros((m, NC), dtype=np.float32)
-    keep = np.zeros(m, dtype=bool)
-    starts = list(range(0, m, chunk))
-    threads = threads or min(16, os.cpu_count() or 1)
-    with ThreadPoolExecutor(max(1, threads)) as ex:
-        for a, (c, k) in zip(starts, ex.map(lambda a: _targets_chunk(Qref, Q[a:a + chunk]), starts)):
-            out[a:a + chunk], keep[a:a + chunk] = c, k
-    return out, keep
+    Qcm = Q.transpose(1, 2).contiguous()   # column-major storage of each matrix
+    coords = torch.empty(m, NC, dtype=torch.float32, device="cuda")
+    keep = torch.empty(m, dtype=torch.int32, device="cuda")
+    _chk(jx.lib().jws_canonical_targets(m, N, _p(Qcm), _p(fam.Qref_cm), _p(coords), _p(keep), maxabs, _s()),
+         "jws_canonical_targets")
+    return coords, keep
+
+
+def standardized(theta, coords, keep, stats=None, eps=1e-6):
+    """Kept rows of (theta, coords) with the coordinates standardised by the
+    kept rows' column means and standard deviations (jws_column_stats, or the
+    given `stats`), gathered in order by jws_gather_standardize.  Returns
+    (X kept x 8, T kept x 2016, (mean, std))."""
+    import torch
+    rows = coords.shape[0]
+    idx_h = np.nonzero(keep.cpu().numpy())[0].astype(np.int32)
+    kept = len(idx_h)
+    if stats is None:
+        mean = torch.empty(NC, dtype=torch.float32, device="cuda")
+        std = torch.empty(NC, dtype=torch.float32, device="cuda")
+        work = torch.empty(int(jx.lib().jws_column_stats_work(rows, NC)) // 8 + 1, dtype=torch.float64,
+                           device="cuda")
+        _chk(jx.lib().jws_column_stats(rows, NC, _p(coords), _p(keep), kept, eps, _p(mean), _p(std), _p(work),
+                                       _s()), "jws_column_stats")
+    else:
+        mean, std = stats
+    idx = torch.from_numpy(idx_h).cuda()
+    th = torch.as_tensor(theta, dtype=torch.float32, device="cuda").contiguous()
+    X = torch.empty(kept, NIN, dtype=torch.float32, device="cuda")
+    T = torch.empty(kept, NC, dtype=torch.float32, device="cuda")
+    _chk(jx.lib().jws_gather_standardize(kept, _p(idx), NIN, _p(th), NC, _p(coords), _p(mean), _p(std), _p(X),
+                                         _p(T), _s()), "jws_gather_standardize")
+    return X, T, (mean, std)
 
 
 # ---------------------------------------------------------------------------
@@ -294,77 +251,105 @@ def propose(net, fam, theta):
 
 
 def generate(fam, count, seed, chunk=32768, log=None):
-    """Thetas (count x 8, N(0, 0.1^2)), standardisable targets and the kept mask."""
+    """Thetas (count x 8, N(0, 0.1^2)), the solutions' canonical targets
+    (count x 2016 FP32, CUDA) and the kept mask (int32, CUDA)."""
+    import torch
     th = inputs.warmstart_thetas(count, seed)
-    coords = np.zeros((count, NC), dtype=np.float32)
-    keep = np.zeros(count, dtype=bool)
-    Qref = fam.Qref.cpu().numpy()
+    coords = torch.empty(count, NC, dtype=torch.float32, device="cuda")
+    keep = torch.empty(count, dtype=torch.int32, device="cuda")
     for a in range(0, count, chunk):
         A = fam.matrices(th[a:a + chunk])
         _, Q, infos = solve(A)
         if (infos["status"] != 0).any():
             raise RuntimeError("training solve did not converge")
-        c, k = canonical_targets(Qref, Q.cpu().numpy())
+        c, k = canonical_targets(fam, Q)
         coords[a:a + chunk], keep[a:a + chunk] = c, k
         if log:
             log(f"generated {min(a + chunk, count)}/{count}")
-    return th.astype(np.float32), coords, keep
+    return th, coords, keep
 
 
-def evaluate(net, fam, test_theta, reps=3):
-    """Cold vs warm batched FP64 solves of the test batch: sweeps, fallback
-    rate and solves/s (warm includes the network and the Cayley map)."""
+def fixed_start(fam, m, mean=None, std=None):
+    """Starts that use no network: Q0 = Qref for every matrix (mean None), or
+    Q0 = Qref cay(S_mean) with S_mean the generator of the mean standardised
+    target (coordinates 0 * std + mean, through the same kernels as the
+    network's proposals)."""
+    import torch
+    if mean is None:
+        return fam.Qref.unsqueeze(0).expand(m, N, N).contiguous()
+    zero = torch.zeros(m, NC, dtype=torch.float32, device="cuda")
+    S = torch.empty(m, N, N, dtype=torch.float64, device="cuda")
+    _chk(jx.lib().jws_skew_from_coords(m, N, _p(zero), _p(mean), _p(std), _p(S), _s()), "jws_skew_from_coords")
+    Q0cm = torch.empty(m, N, N, dtype=torch.float64, device="cuda")
+    _chk(jx.lib().jws_cayley_batched(m, N, _p(S), _p(fam.Qref_cm), _p(Q0cm), _s()), "jws_cayley_batched")
+    return Q0cm.transpose(1, 2)
+
+
+def evaluate(net, fam, test_theta, reps=5):
+    """Batched FP64 solves of the test batch from four starts: cold (Q0 = I),
+    Qref for all, Qref cay(S_mean) (no network), and the network's proposal.
+    Sweeps, their histograms, fallback rate and solves/s (median of `reps`
+    timed calls; a start's own cost -- network, skew assembly, Cayley map --
+    is inside its timed region)."""
     import torch
     A = fam.matrices(test_theta)
     th = torch.from_numpy(np.ascontiguousarray(test_theta, dtype=np.float32)).cuda()
     m = A.shape[0]
 
     def timed(fn):
-        best = np.inf
-        for _ in range(reps):
+        ts, r = [], None
+        for _ in range(reps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = fn()
             torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
-        return r, best
+            ts.append(time.perf_counter() - t0)
+        return r, float(np.median(ts[1:]))
 
-    (_, _, ic), tc = timed(lambda: solve(A))
-    (_, _, iw), tw = timed(lambda: solve(A, Q0=propose(net, fam, th)))
-    sc = ic["sweeps"].astype(np.int64)
-    sw = iw["sweeps"].astype(np.int64)
-    fb = iw["fallback_used"]
-    return {
-        "matrices": m,
-        "cold_sweeps_mean": float(sc.mean()), "warm_sweeps_mean": float(sw.mean()),
-        "sweeps_saved_mean": float((sc - sw).mean()),
-        "sweeps_saved_hist": {int(k): int(v) for k, v in zip(*np.unique(sc - sw, return_counts=True))},
-        "fallback_rate": float(fb.mean()),
-        "cold_solves_per_s": m / tc, "warm_solves_per_s": m / tw, "speedup": tc / tw,
-        "status_ok": bool((ic["status"] == 0).all() and (iw["status"] == 0).all()),
+    starts = {
+        "cold": lambda: solve(A),
+        "qref": lambda: solve(A, Q0=fixed_start(fam, m)),
+        "mean_generator": lambda: solve(A, Q0=fixed_start(fam, m, net.mean, net.std)),
+        "network": lambda: solve(A, Q0=propose(net, fam, th)),
     }
+    out = {"matrices": m}
+    ok = True
+    cold_sweeps = None
+    for name, fn in starts.items():
+        (_, _, inf), t = timed(fn)
+        sw = inf["sweeps"].astype(np.int64)
+        if cold_sweeps is None:
+            cold_sweeps = sw
+        ok = ok and bool((inf["status"] == 0).all())
+        out[name] = {"sweeps_mean": float(sw.mean()),
+                     "sweeps_hist": {int(k): int(v) for k, v in zip(*np.unique(sw, return_counts=True))},
+                     "sweeps_saved_mean": float((cold_sweeps - sw).mean()),
+                     "fallback_rate": float(inf["fallback_used"].mean()), "solves_per_s": m / t, "seconds": t}
+    out["status_ok"] = ok
+    out["cold_sweeps_mean"] = out["cold"]["sweeps_mean"]
+    out["warm_sweeps_mean"] = out["network"]["sweeps_mean"]
+    out["speedup"] = out["network"]["solves_per_s"] / out["cold"]["solves_per_s"]
+    out["speedup_vs_best_fixed_start"] = out["network"]["solves_per_s"] / max(
+        out["qref"]["solves_per_s"], out["mean_generator"]["solves_per_s"])
+    return out
 
 
 def run(train_count=1 << 18, epochs=40, val_count=4096, test_count=4096, seed=5, log=print):
-    import torch
     fam = Family(seed)
     t0 = time.perf_counter()
     th, coords, keep = generate(fam, train_count, 50, log=log)
     gen_s = time.perf_counter() - t0
     vth, vco, vkeep = generate(fam, val_count, 51)
-    mean = coords[keep].mean(axis=0)
-    std = coords[keep].std(axis=0) + 1e-6
+    X, T, stats = standardized(th, coords, keep)
+    VX, VT, _ = standardized(vth, vco, vkeep, stats=stats)
     net = Net(seed=0)
-    net.mean = torch.from_numpy(mean).cuda()
-    net.std = torch.from_numpy(std).cuda()
-    T = torch.from_numpy((coords[keep] - mean) / std).cuda()
-    X = torch.from_numpy(th[keep]).cuda()
-    VT = torch.from_numpy((vco[vkeep] - mean) / std).cuda()
-    VX = torch.from_numpy(vth[vkeep]).cuda()
+    net.mean, net.std = stats
+    dropped = 1.0 - X.shape[0] / train_count
+    del coords
     tr = train(net, X, T, VX, VT, epochs=epochs, log=log)
     test_theta = inputs.warmstart_thetas(test_count, 52)
     ev = evaluate(net, fam, test_theta)
-    return {"train_samples": int(train_count), "dropped_fraction": float(1.0 - keep.mean()),
+    return {"train_samples": int(train_count), "dropped_fraction": float(dropped),
             "generation_seconds": gen_s, "training": {k: v for k, v in tr.items() if k != "history"},
             "val_history": tr["history"], "test": ev}
 

@@ -78,8 +78,15 @@ def test_opts_defaults_and_workspace():
     ublk = 64 * 65 // 2 * 64 * 64 * 8
     vhat = 3 * 32 * 128 * 128 * 8
     side = 2 * 4 * 32 * 64 * 64 * 8
-    w = jx.jacobi_eig_workspace(4096, jx.opts_default(want_vectors=0, refine=0))
+    w = jx.jacobi_eig_workspace(4096, jx.opts_default(want_vectors=0, refine=0, ordering=jx.ORDER_ROUND_ROBIN))
     assert ublk + vhat + side <= w < ublk + vhat + side + 2 * 2 ** 20
+    # the sorted ordering adds a second block triangle (the permuted copy)
+    ws = jx.jacobi_eig_workspace(4096, jx.opts_default(want_vectors=0, refine=0))
+    assert o.ordering == jx.ORDER_ROUND_ROBIN_SORTED
+    assert 2 * ublk + vhat + side <= ws < 2 * ublk + vhat + side + 2 * 2 ** 20
+    # b = 1 (scalar): A, Q, the schedule and a few vectors
+    assert 2 * 256 * 256 * 8 <= jx.jacobi_eig_workspace(256, jx.opts_default(block=1)) < 2 * 256 * 256 * 8 + 2 ** 20
+    assert jx.jacobi_eig_workspace(2048, jx.opts_default(block=1)) == 0  # beyond the scalar kernel's orders
     assert jx.jacobi_eig_workspace(100) > 0
     assert jx.jacobi_eig_workspace(64, jx.opts_default(block=48)) == 0  # unsupported block
 
@@ -152,3 +159,47 @@ def test_batched_info_array_matches_the_c_struct():
     arr = np.frombuffer(bytes(infos), dtype=dt)
     assert jx._info_dicts(arr, 5) == [infos[k].as_dict() for k in range(5)]
     assert jx._info_dicts(arr, 0) == []
+
+
+def test_batched_binding_rejects_mismatched_tensors():
+    """The batched binding hands raw pointers to the library: a wrong element
+    type, a non-contiguous tensor or a short buffer must be refused before
+    any call (here with CPU tensors, which it refuses last)."""
+    import torch
+    jx = _jx()
+    tw, tq = 10, 50  # elements the batch writes to W and reads from A / Q0 / Q
+    ok32 = torch.zeros(tq, dtype=torch.float32)
+    f64 = lambda k: torch.zeros(k, dtype=torch.float64)
+    cases = [
+        (dict(packed=torch.zeros(tq, dtype=torch.float16)), "packed must be"),
+        (dict(packed=torch.zeros(tq, dtype=torch.bfloat16)), "packed must be"),
+        (dict(packed=torch.zeros(2 * tq, dtype=torch.float32)[::2]), "packed must be contiguous"),
+        (dict(packed=torch.zeros(tq - 1, dtype=torch.float32)), "the batch needs"),
+        (dict(packed=ok32, Q0=torch.zeros(tq, dtype=torch.float32)), "Q0 must be"),
+        (dict(packed=ok32, Q0=f64(tq - 1)), "Q0 holds"),
+        (dict(packed=ok32, Q0=torch.zeros(tq, 2, dtype=torch.float64).t()[0]), "Q0 must be contiguous"),
+        (dict(packed=ok32, out=(torch.zeros(tw, dtype=torch.float32), f64(tq))), "out W must be"),
+        (dict(packed=ok32, out=(f64(tw - 1), f64(tq))), "out W holds"),
+        (dict(packed=ok32, out=(f64(tw), f64(tq - 1))), "out Q holds"),
+        (dict(packed=ok32), "must be a CUDA tensor"),
+    ]
+    for kw, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            jx.check_batched_args(kw["packed"], kw.get("Q0"), kw.get("out"), tw, tq)
+    # the entry point itself validates before calling the library
+    with pytest.raises(ValueError, match="packed must be"):
+        jx.jacobi_eig_batched([5, 5], [0, 25], torch.zeros(tq, dtype=torch.float16))
+
+
+def test_bf16_precision_is_refused():
+    """JACOBI_PREC_MIXED_BF16 has no implementation: the opts argument's error
+    code (checked before any device work)."""
+    jx = _jx()
+    L = jx.lib()
+    o = jx.opts_default(precision=jx.PREC_MIXED_BF16)
+    info = jx.Info()
+    fake = ctypes.c_void_p(16)  # never dereferenced: the call fails in the argument checks
+    rc = L.jacobi_eig(4, fake, 4, b"U", fake, fake, 4, None, 4, None, 0, ctypes.byref(o), ctypes.byref(info), None)
+    assert rc == -12 and info.status == -12 and "precision" in jx.last_error()
+    rc = L.jacobi_svd(8, 4, fake, 8, fake, fake, 8, fake, 4, None, 0, ctypes.byref(o), ctypes.byref(info), None)
+    assert rc == -12

@@ -196,6 +196,28 @@ def test_batched_warm_start_and_fallback(jx):
     assert sum(i["fallback_used"] for i in ib) >= 1
 
 
+def test_batched_fp32_quality_warm_start_values_only(jx):
+    """A warm start orthogonal only to FP32 accuracy (exact eigenvectors
+    rotated slightly, then rounded to FP32) with eigenvalues only: the
+    Newton-Schulz steps must restore FP64 orthogonality before Q0^T A Q0,
+    or the eigenvalues miss the 1e-12 bar."""
+    rng = np.random.default_rng(19)
+    mats, starts = [], []
+    for n in (40, 96, 200, 256):
+        A = inputs.sym_with_spectrum(rng.standard_normal(n), inputs.haar(n, rng))
+        mats.append(A)
+        S = rng.standard_normal((n, n)) * 1e-4
+        q = O.eig(A).Q @ O.cayley(S - S.T)
+        starts.append(q.astype(np.float32).astype(np.float64))
+        assert np.linalg.norm(starts[-1].T @ starts[-1] - np.eye(n)) > 1e-7  # not FP64-orthogonal
+    sizes, offs, packed = pack(mats, np.float64)
+    q0 = np.concatenate([q.reshape(-1, order="F") for q in starts])
+    (Ws, _), infos = run(jx, sizes, offs, packed, Q0=q0, precision=jx.PREC_FP64, want_vectors=0)
+    for k in range(len(mats)):
+        assert infos[k]["status"] == 0 and infos[k]["fallback_used"] == 0, infos[k]
+        check_against_oracle(mats[k], Ws[k], None)
+
+
 def test_batched_library_workspace(jx):
     sizes, offs, packed = inputs.batched_case(10, 5)
     (Ws, Qs), infos = run(jx, sizes, offs, packed, work=False, precision=jx.PREC_MIXED_FP32)
