@@ -153,6 +153,29 @@ int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *
                const jacobi_opts *opts, jacobi_info *info, jacobi_stream_t stream);
 
 /*
+ * jacobi_eig without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, outputs and
+ * status codes as jacobi_eig, minus dWork/workBytes: the workspace is a
+ * static device array of this library, jacobi_eig_noalloc_max_bytes()
+ * bytes (64 MiB) on every GPU the library runs on, held until the process
+ * ends.  Its device address is looked up once per device, by jacobi_init
+ * or by the first call on that device.
+ *   - Orders whose workspace (jacobi_eig_workspace(n, opts)) exceeds the
+ *     array are rejected with -1 before any device work (with the default
+ *     options: n <= 1152 with eigenvectors, n <= 2432 eigenvalues only).
+ *   - The call allocates nothing: no hipMalloc/hipFree, no allocating
+ *     library routine; the caller passes inputs and outputs.
+ *   - Every call on a GPU shares that GPU's array, which keeps the last
+ *     call's contents (each call initialises what it reads).  Calls that
+ *     overlap on one GPU (from several threads or streams) race on it.
+ */
+int jacobi_eig_noalloc(int n, const double *dA, int lda, char uplo, double *dW, double *dQ, int ldq,
+                       const double *dQ0, int ldq0, const jacobi_opts *opts, jacobi_info *info,
+                       jacobi_stream_t stream);
+size_t jacobi_eig_noalloc_max_bytes(void);
+
+/*
  * Thin SVD G = U diag(S) V^T by one-sided block Jacobi (Alg. 6, §6).
  *   m >= n >= 0 (m < n returns -1); dG, ldg: m x n input
  *   dS: n singular values (descending when opts->sort)

@@ -65,6 +65,7 @@ int jacobi_init(void) {
     g_last_error.clear();
     try {
         (void)device_ctx();
+        (void)noalloc_setup();
         return 0;
     } catch (const HipFail &) {
         return 3;

@@ -49,6 +49,9 @@ struct DeviceCtx {
     char *pinned = nullptr;
 };
 DeviceCtx &device_ctx();  // the current device's context (created on first use)
+// Device address of the current device's static scratch array of the
+// no-allocation entry point (looked up once per device).
+void *noalloc_setup();
 
 struct EigPlan {
     int n, npad, b, N, H, R;
