@@ -27,6 +27,11 @@
  *                      ||Q^T Q - I||_F, SVD residuals.
  *   ora_cayley         Cayley map W = (I - S)^{-1} (I + S) by Gaussian
  *                      elimination with partial pivoting, long double.
+ *   ora_lupp_cols      the pivoting step of block Jacobi (§2.1, the
+ *                      convergence conditions after eq. (sweep cost)): LU with
+ *                      partial pivoting applied to the leading rows of the
+ *                      subproblem's rotation, giving the column permutation
+ *                      P of the update V_hat <- V_hat P.
  *
  * The 2x2 rotation used by ora_eig / ora_svd is the textbook symmetric Schur
  * decomposition (Golub & Van Loan, Matrix Computations, §8.5.2; Rutishauser
@@ -684,6 +689,55 @@ int ora_block_step(int n, int b, double *A, double *Q, int npairs, const int *pa
     free(L);
     free(R);
     free(inpair);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pivoting step                                                             */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Column selection by LU with partial pivoting (§2.1, the pivoting step of the
+ * convergence conditions): M is rows x cols (rows <= cols), here the leading
+ * b rows of the 2b x 2b rotation V_hat.  Gaussian elimination with partial
+ * pivoting runs on X = M^T (cols x rows): at step k the row i >= k of X with
+ * the largest |X(i, k)| (the first such i on ties) is swapped into place k,
+ * then X(i, j) -= l_i X(k, j) for i > k, j > k, with l_i = X(i, k) / X(k, k)
+ * (skipped when the whole column is zero).  The row swaps of X are column
+ * swaps of M; perm receives them applied to the identity: column j of M P is
+ * column perm[j] of M, the first `rows` entries being the selected columns.
+ * The update is written as fma(-l, x_kj, x_ij) (one rounding), the form a
+ * fused multiply-add unit evaluates.  Returns 0, or -1 on bad sizes.
+ */
+int ora_lupp_cols(int rows, int cols, const double *M, int ldm, int *perm)
+{
+    if (rows < 0 || cols < rows || ldm < (rows > 1 ? rows : 1)) return -1;
+    double *X = (double *)malloc(sizeof(double) * ((size_t)cols * rows + 1));
+    for (int i = 0; i < cols; ++i) {
+        perm[i] = i;
+        for (int k = 0; k < rows; ++k) X[IDX(i, k, cols)] = M[IDX(k, i, ldm)];
+    }
+    for (int k = 0; k < rows; ++k) {
+        int piv = k;
+        double best = fabs(X[IDX(k, k, cols)]);
+        for (int i = k + 1; i < cols; ++i)
+            if (fabs(X[IDX(i, k, cols)]) > best) { best = fabs(X[IDX(i, k, cols)]); piv = i; }
+        if (piv != k) {
+            for (int j = 0; j < rows; ++j) {
+                double t = X[IDX(k, j, cols)];
+                X[IDX(k, j, cols)] = X[IDX(piv, j, cols)];
+                X[IDX(piv, j, cols)] = t;
+            }
+            int t = perm[k]; perm[k] = perm[piv]; perm[piv] = t;
+        }
+        double d = X[IDX(k, k, cols)];
+        if (d == 0.0) continue;
+        for (int i = k + 1; i < cols; ++i) {
+            double l = X[IDX(i, k, cols)] / d;
+            for (int j = k + 1; j < rows; ++j) X[IDX(i, j, cols)] = fma(-l, X[IDX(k, j, cols)], X[IDX(i, j, cols)]);
+        }
+    }
+    free(X);
     return 0;
 }
 

@@ -54,6 +54,7 @@ def lib():
         L.ora_check_svd.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp, _dp,
                                     ctypes.c_int, _dp, ctypes.c_int, _dp]
         L.ora_cayley.restype = ctypes.c_int
+        L.ora_lupp_cols.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _ip]
         L.ora_cayley.argtypes = [ctypes.c_int, _dp, _dp]
         L.ora_cayley_inverse.restype = ctypes.c_int
         L.ora_cayley_inverse.argtypes = [ctypes.c_int, _dp, _dp]
@@ -223,6 +224,19 @@ def check_svd(G, S, U, V):
     out = np.zeros(3)
     lib().ora_check_svd(m, n, _p(G), m, _p(S), _p(U), m, _p(V), n, _p(out))
     return out
+
+
+def lupp_cols(M):
+    """Column permutation of the pivoting step (§2.1): LU with partial
+    pivoting on M^T for M rows x cols (rows <= cols).  Returns perm (cols
+    ints): column j of M P is column perm[j] of M."""
+    M = _f64(M)
+    rows, cols = M.shape
+    perm = np.zeros(cols, dtype=np.int32)
+    rc = lib().ora_lupp_cols(rows, cols, _p(M), max(rows, 1), perm.ctypes.data_as(_ip))
+    if rc != 0:
+        raise ValueError(f"ora_lupp_cols: {rc}")
+    return perm
 
 
 def cayley(S):

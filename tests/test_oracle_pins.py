@@ -719,3 +719,70 @@ def test_relative_threshold_reaches_what_the_absolute_test_misses():
     r = O.eig(A, relative=True, tol=EPS)
     assert r.status == 0 and r.sweeps >= 2
     assert np.max(np.abs(r.W - ref) / np.abs(ref)) <= 50 * n * EPS
+
+
+# --------------------------------------------------------------------------
+# Pivoting step (§2.1, convergence conditions): LU with partial pivoting on
+# the leading rows of V_hat selects the column permutation P
+# --------------------------------------------------------------------------
+
+def _perm_from_getrf(piv, cols):
+    perm = np.arange(cols)
+    for k, p in enumerate(piv):
+        perm[[k, p]] = perm[[p, k]]
+    return perm
+
+
+@pytest.mark.parametrize("rows,seed", [(1, 0), (3, 1), (8, 2), (32, 3), (64, 4), (64, 5)])
+def test_lupp_cols_matches_lapack_getrf(rows, seed):
+    # LAPACK's dgetrf on M^T: the same pivot rows (Gaussian entries: no near ties)
+    import scipy.linalg as sl
+    M = np.random.default_rng(seed).standard_normal((rows, 2 * rows))
+    perm = O.lupp_cols(M)
+    _, piv = sl.lu_factor(M.T)
+    np.testing.assert_array_equal(perm, _perm_from_getrf(piv, 2 * rows))
+    assert sorted(perm) == list(range(2 * rows))
+
+
+def test_lupp_cols_pivots_are_final():
+    # partial pivoting on the already permuted matrix swaps nothing, and every
+    # multiplier of its LU factor is at most 1 in magnitude
+    import scipy.linalg as sl
+    M = np.random.default_rng(9).standard_normal((16, 32))
+    perm = O.lupp_cols(M)
+    Pm, L, U = sl.lu(M[:, perm].T)
+    np.testing.assert_array_equal(Pm, np.eye(32))
+    assert np.max(np.abs(L)) <= 1.0
+    np.testing.assert_array_equal(O.lupp_cols(M[:, perm]), np.arange(32))
+
+
+def test_lupp_cols_special_cases():
+    b = 6
+    Z, I = np.zeros((b, b)), np.eye(b)
+    # [0 | I]: the identity half is selected, in order; the rest follows in
+    # the order of the swaps
+    np.testing.assert_array_equal(O.lupp_cols(np.hstack([Z, I])), list(range(b, 2 * b)) + list(range(b)))
+    np.testing.assert_array_equal(O.lupp_cols(np.hstack([I, Z])), np.arange(2 * b))  # nothing to do
+    np.testing.assert_array_equal(O.lupp_cols(np.zeros((b, 2 * b))), np.arange(2 * b))  # ties: first index
+    # a rotation whose leading block is singular: the block swap [[0, I], [I, 0]]
+    # gives V_11 = 0; the selected columns make (V P)_11 = I
+    V = np.block([[Z, I], [I, Z]])
+    perm = O.lupp_cols(V[:b])
+    np.testing.assert_array_equal((V[:, perm])[:b, :b], I)
+
+
+def test_lupp_cols_well_conditioned_leading_block():
+    # rotation V_hat = blockdiag(H1, H2) [[C, -S], [S, C]] with cos/sin
+    # diagonal C, S (angles near pi/2): V_11 = H1 C is nearly singular,
+    # the selected columns give a leading block with sigma_min bounded away
+    # from zero (here at least 1/4)
+    b = 16
+    rng = np.random.default_rng(11)
+    H1, H2 = inputs.haar(b, rng), inputs.haar(b, rng)
+    th = np.pi / 2 - 1e-9 * rng.random(b)
+    C, S = np.diag(np.cos(th)), np.diag(np.sin(th))
+    V = np.block([[H1 @ C, -H1 @ S], [H2 @ S, H2 @ C]])
+    assert np.linalg.norm(V.T @ V - np.eye(2 * b)) < 1e-13
+    assert np.linalg.svd(V[:b, :b], compute_uv=False)[-1] < 1e-8
+    perm = O.lupp_cols(V[:b])
+    assert np.linalg.svd(V[:b][:, perm[:b]], compute_uv=False)[-1] >= 0.25
