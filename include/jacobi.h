@@ -111,6 +111,14 @@ typedef struct {
                              (one-sided Jacobi on G itself).  Falls back to the
                              plain solve when the factorization fails or a
                              singular value is zero.  eig: unused */
+    int pivot;            /* eig, b = 32 or 64: 1 = the pivoting step of the
+                             convergence conditions (§2.1, after eq. (sweep
+                             cost)) after every subproblem solve of the FP64
+                             sweeps: LU with partial pivoting on the leading b
+                             rows of V_hat selects a column permutation P, and
+                             V_hat <- V_hat P, D_hat <- P^T D_hat P.  Default 0
+                             (the paper's algorithms omit it).  svd, batched
+                             and b = 1: must be 0 */
 } jacobi_opts;
 
 typedef struct {
@@ -377,6 +385,22 @@ int jacobi_subproblem_solve(int count, int m2, const double *dAhat, double *dV, 
  */
 int jacobi_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
                       const double *dV, const double *dD, jacobi_stream_t stream);
+
+/*
+ * The pivoting step (§2.1, the convergence conditions after eq. (sweep cost))
+ * by the kernel the solver runs with opts->pivot = 1, on explicit data in the
+ * solver's storage: A (n x n symmetric, full column-major, lda = n) holds the
+ * diagonalised subproblems D_hat in its pair blocks A([I,J],[I,J]); dV holds
+ * npairs rotations V_hat of order 2b (column-major).  For each pair, LU with
+ * partial pivoting on V_hat(0:b, :)^T (the first maximal |entry| on ties;
+ * multipliers l = x_ik / x_kk, updates fma(-l, x_kj, x_ij)) gives the
+ * permutation P; then V_hat <- V_hat P and A([I,J],[I,J]) <- P^T A([I,J],[I,J]) P
+ * in place, other blocks untouched.  dPerm (may be NULL): npairs x 2b ints,
+ * column j of V_hat P is column dPerm[j] of V_hat.  n, b, hPairs as for
+ * jacobi_block_step.  Returns 0 or an error code.
+ */
+int jacobi_pivot_step(int n, int b, double *dA, int npairs, const int *hPairs, double *dV, int *dPerm,
+                      jacobi_stream_t stream);
 
 /*
  * The same step of Alg. 2 (§3) by the FP32 kernels of the precision ladder's

@@ -56,6 +56,7 @@ int jacobi_opts_default(jacobi_opts *o) {
     o->want_vectors = 1;
     o->threshold = 0;
     o->precondition = -1;
+    o->pivot = 0;
     return 0;
 }
 
@@ -111,6 +112,8 @@ int jacobi_eig(int n, const double *dA, int lda, char uplo, double *dW, double *
     if (o.block == 1 && dQ0) return fail(-8, "no warm start with opts->block = 1");
     if (o.threshold != 0 && (o.threshold != 1 || o.block != 1))
         return fail(-12, "opts->threshold = 1 (relative) needs opts->block = 1");
+    if (o.pivot != 0 && (o.pivot != 1 || o.block == 1))
+        return fail(-12, "opts->pivot = 1 needs a blocked solve (opts->block 0, 32 or 64)");
     if (n == 0) {
         if (info) info->status = 0;
         return 0;
@@ -177,6 +180,7 @@ int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, 
     if (o.precision != JACOBI_PREC_FP64 && o.precision != JACOBI_PREC_MIXED_FP32)
         return fail(-12, "opts->precision must be JACOBI_PREC_FP64 or JACOBI_PREC_MIXED_FP32");
     if (o.threshold != 0) return fail(-12, "opts->threshold must be 0 for the SVD");
+    if (o.pivot != 0) return fail(-12, "opts->pivot must be 0 for the SVD");
     if (n == 0) {
         if (info) info->status = 0;
         return 0;
@@ -227,6 +231,25 @@ static int block_step(int n, int b, double *dA, double *dQ, int npairs, const in
     }
     return guarded(nullptr, [&]() -> int {
         return run_block_step(n, b, dA, dQ, npairs, hPairs, dV, dD, f32, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+int jacobi_pivot_step(int n, int b, double *dA, int npairs, const int *hPairs, double *dV, int *dPerm,
+                      jacobi_stream_t stream) {
+    if (b != 32 && b != 64) return -2;
+    if (n <= 0 || n % (2 * b) || n % 128) return -1;
+    if (!dA) return -3;
+    if (npairs != n / (2 * b)) return -4;
+    if (!hPairs) return -5;
+    std::vector<char> seen(n / b, 0);
+    for (int k = 0; k < npairs; ++k) {
+        const int I = hPairs[2 * k], J = hPairs[2 * k + 1];
+        if (I < 0 || J >= n / b || I >= J || seen[I] || seen[J]) return -5;
+        seen[I] = seen[J] = 1;
+    }
+    if (!dV) return -6;
+    return guarded(nullptr, [&]() -> int {
+        return run_pivot_step(n, b, dA, npairs, hPairs, dV, dPerm, reinterpret_cast<hipStream_t>(stream));
     });
 }
 

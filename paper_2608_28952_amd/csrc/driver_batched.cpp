@@ -501,6 +501,7 @@ int jacobi_eig_batched(int batch, const int *h_n, const int64_t *h_offA, int dty
     if (rc == 0 && batch > 0 && o.want_vectors && !dQ) rc = -7;
     if (rc == 0 && opts && opts->block != 0 && opts->block != 8 && opts->block != 16) rc = -11;
     if (rc == 0 && o.precision != JACOBI_PREC_FP64 && o.precision != JACOBI_PREC_MIXED_FP32) rc = -11;
+    if (rc == 0 && (o.threshold != 0 || o.pivot != 0)) rc = -11;
     if (rc != 0) {
         set_error("jacobi_eig_batched: invalid argument " + std::to_string(-rc));
         if (info)

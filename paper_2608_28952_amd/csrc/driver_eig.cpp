@@ -158,6 +158,7 @@ EigPlan plan_eig(int n, const jacobi_opts &o) {
     p.off_xcopy = wb.add(sizeof(int) * 8 * (size_t)p.R * p.H);          // other copies per round
     p.off_copy0 = wb.add(sizeof(int) * 8 * (size_t)p.H);                // copies before a sweep's round 0
     p.sorted = o.ordering == JACOBI_ORDER_ROUND_ROBIN_SORTED;
+    p.pivot = o.pivot == 1;
     if (p.sorted) {  // re-sorting between sweeps: a second block storage and the inverse permutation
         p.off_ablk2 = wb.add(sizeof(double) * nb * p.b * p.b);
         p.off_inv = wb.add(sizeof(int) * npad);
@@ -242,9 +243,9 @@ struct EigState {
         if (f32) {
             launch_permute_sym32(p.npad, p.b, inv, ablk32, reinterpret_cast<float *>(ablk2), s);
             JX_HIP(hipMemcpyAsync(ablk32, ablk2, sizeof(float) * nab, hipMemcpyDeviceToDevice, s));
-        } else {
+        } else {  // the permuted copy becomes A's storage (the two buffers trade places)
             launch_permute_sym(p.npad, p.b, inv, ablk, ablk2, s);
-            JX_HIP(hipMemcpyAsync(ablk, ablk2, sizeof(double) * nab, hipMemcpyDeviceToDevice, s));
+            std::swap(ablk, ablk2);
         }
         if (p.need_q) {
             const size_t nq = (size_t)p.npad * p.npad;
@@ -305,6 +306,16 @@ struct EigState {
             {
                 ProfScope ps(PROF_SUBPROBLEM, s, k1_flops / p.H, k1_bytes / p.H, slot_next, p.H, m2);
                 launch_subproblem(a, s);
+            }
+            if (p.pivot && !f32) {  // V_hat <- V_hat P, D_hat <- P^T D_hat P before any tile reads them
+                PivotArgs pa{};
+                pa.count = p.H;
+                pa.m2 = m2;
+                pa.pairs = pr;
+                pa.ablk = ablk;
+                pa.V = Vbuf(r);
+                pa.flags = Fbuf(r);
+                launch_pivot(pa, s);
             }
             int slot = -1;
             if (h_flaglog && flog_count < flog_cap) {
@@ -811,6 +822,36 @@ int run_subproblem(int count, int m2, const double *dAhat, double *dV, double *d
     a.dout = dD;
     a.inner_sweeps = inner;
     launch_subproblem(a, s);
+    JX_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+int run_pivot_step(int n, int b, double *dA, int npairs, const int *hPairs, double *dV, int *dPerm,
+                   hipStream_t s) {
+    const int N = n / b, m2 = 2 * b;
+    const size_t nb = (size_t)N * (N + 1) / 2;
+    DeviceBuffer buf;
+    WorkspaceBuilder wb;
+    const size_t o_ab = wb.add(sizeof(double) * nb * b * b);
+    const size_t o_v = wb.add(sizeof(double) * (size_t)npairs * m2 * m2);
+    const size_t o_p = wb.add(sizeof(int) * 2 * (size_t)npairs);
+    buf.alloc(wb.total());
+    double *ablk = reinterpret_cast<double *>(buf.ptr + o_ab);
+    double *V = reinterpret_cast<double *>(buf.ptr + o_v);
+    int *pairs = reinterpret_cast<int *>(buf.ptr + o_p);
+    JX_HIP(hipMemcpyAsync(pairs, hPairs, sizeof(int) * 2 * npairs, hipMemcpyHostToDevice, s));
+    launch_pack_sym(n, n, b, dA, n, 'U', ablk, s);
+    launch_vperm_from_colmajor(npairs, m2, dV, V, s);
+    PivotArgs pa{};
+    pa.count = npairs;
+    pa.m2 = m2;
+    pa.pairs = pairs;
+    pa.ablk = ablk;
+    pa.V = V;
+    pa.perm_out = dPerm;
+    launch_pivot(pa, s);
+    launch_colmajor_from_vperm(npairs, m2, V, dV, s);
+    launch_unpack_sym(n, b, ablk, dA, n, s);
     JX_HIP(hipStreamSynchronize(s));
     return 0;
 }

@@ -135,6 +135,24 @@ struct SubArgs {
 };
 void launch_subproblem(const SubArgs &a, hipStream_t s);
 
+// Pivoting step (k_pivot.hip): per pair, LU with partial pivoting on the
+// leading m2/2 rows of V_hat gives P; V_hat <- V_hat P, D_hat <- P^T D_hat P.
+// Solver storage (ablk != nullptr: V in vperm order, D_hat in the pair's
+// blocks of the upper block storage, pairs I < J) or plain column-major
+// (V and, if non-null, D per pair).  m2 = 64 or 128.
+struct PivotArgs {
+    int count;          // pairs
+    int m2;
+    const int *pairs;   // solver storage: 2 ints per pair
+    double *ablk;       // solver storage: upper block storage of A (else nullptr)
+    double *V;          // per pair m2 x m2
+    double *D;          // plain storage: per pair m2 x m2 symmetric (may be nullptr)
+    const int *flags;   // optional: 1 = skipped pair (left alone)
+    int *perm_out;      // optional: per pair m2 ints, column j of V P = column perm[j] of V
+};
+void launch_pivot(const PivotArgs &a, hipStream_t s);
+void launch_colmajor_from_vperm(int count, int m2, const double *src, double *dst, hipStream_t s);
+
 // Batched solver (k_batched.hip): one persistent launch per size class.  A
 // class holds the matrices whose order pads to M2 = 2 * bs * npp (npp pair
 // problems of order 2 bs per middle round); every matrix has its own padded

@@ -55,7 +55,7 @@ void *noalloc_setup();
 
 struct EigPlan {
     int n, npad, b, N, H, R;
-    bool vectors, refine, mixed, need_q, temps, sorted;
+    bool vectors, refine, mixed, need_q, temps, sorted, pivot;
     size_t off_ablk, off_q, off_v, off_flags, off_pairs, off_force, off_tiles, off_qmask, off_side, off_smap, off_xcopy, off_copy0, off_partial,
         off_scal, off_w, off_rank, off_a0, off_t1, off_t2, off_ablk32, off_q32, off_v32, off_ablk2, off_inv;
     size_t total;
@@ -89,6 +89,7 @@ int run_qr(int m, int n, const double *dG, int ldg, double *dQ, int ldq, double 
 int run_gram_blocks(int m, int n, int b, const double *dG, int ldg, int npairs, const int *hPairs, bool f32,
                     double *dAhat, hipStream_t s);
 // f32: the same step by the FP32 kernels (inputs rounded, results widened)
+int run_pivot_step(int n, int b, double *dA, int npairs, const int *hPairs, double *dV, int *dPerm, hipStream_t s);
 int run_block_step(int n, int b, double *dA, double *dQ, int npairs, const int *hPairs,
                    const double *dV, const double *dD, bool f32, hipStream_t s);
 

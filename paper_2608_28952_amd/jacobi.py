@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("block", ctypes.c_int),
                 ("ordering", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_max_sweeps", ctypes.c_int), ("refine", ctypes.c_int), ("sort", ctypes.c_int),
-                ("want_vectors", ctypes.c_int), ("threshold", ctypes.c_int), ("precondition", ctypes.c_int)]
+                ("want_vectors", ctypes.c_int), ("threshold", ctypes.c_int), ("precondition", ctypes.c_int),
+                ("pivot", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -127,6 +128,7 @@ def lib():
                                          _ip, ctypes.c_int, _vp, _vp]
         L.jacobi_block_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         L.jacobi_block_step32.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
+        L.jacobi_pivot_step.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _ip, _vp, _vp, _vp]
         _lib = L
     return _lib
 
@@ -386,6 +388,24 @@ def jacobi_block_step(A, Q, b, pairs, V, D, fp32=False):
     _check(fn(n, b, _ptr(Ac), _ptr(Qc), len(pairs), hp, _ptr(Vc), _ptr(Dc), _stream()))
     torch.cuda.synchronize()
     return Ac.t(), (Qc.t() if Qc is not None else None)
+
+
+def jacobi_pivot_step(A, b, pairs, V):
+    """The pivoting step on explicit data (jacobi_pivot_step): A (n x n
+    float64 CUDA tensor, symmetric) holds D_hat in its pair blocks, V is a
+    len(pairs) x 2b x 2b float64 tensor of rotations.  Returns (A_new, V_new,
+    perm) with V_new = V P, A_new's pair blocks P^T D_hat P, and perm
+    (len(pairs) x 2b int32): column j of V P is column perm[j] of V."""
+    import torch
+    n = A.shape[0]
+    Ac = A.t().contiguous()   # column-major A
+    Vc = V.transpose(1, 2).contiguous()
+    perm = torch.empty((len(pairs), 2 * b), dtype=torch.int32, device=A.device)
+    flat = [int(v) for pr in pairs for v in pr]
+    hp = (ctypes.c_int * len(flat))(*flat)
+    _check(lib().jacobi_pivot_step(n, b, _ptr(Ac), len(pairs), hp, _ptr(Vc), _ptr(perm), _stream()))
+    torch.cuda.synchronize()
+    return Ac.t(), Vc.transpose(1, 2), perm
 
 
 def jacobi_gram_blocks(G, b, pairs, fp32=False):

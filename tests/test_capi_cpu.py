@@ -203,3 +203,35 @@ def test_bf16_precision_is_refused():
     assert rc == -12 and info.status == -12 and "precision" in jx.last_error()
     rc = L.jacobi_svd(8, 4, fake, 8, fake, fake, 8, fake, 4, None, 0, ctypes.byref(o), ctypes.byref(info), None)
     assert rc == -12
+
+
+def test_pivot_option_defaults_and_checks():
+    """opts.pivot: off by default; refused for b = 1, the SVD and the batched
+    solver (argument checks, before any device work)."""
+    jx = _jx()
+    L = jx.lib()
+    o = jx.opts_default()
+    assert o.pivot == 0
+    fake = ctypes.c_void_p(16)  # never dereferenced: the calls fail in the argument checks
+    info = jx.Info()
+    bad = jx.opts_default(pivot=1, block=1)
+    rc = L.jacobi_eig(4, fake, 4, b"U", fake, fake, 4, None, 4, None, 0, ctypes.byref(bad), ctypes.byref(info), None)
+    assert rc == -12 and "pivot" in jx.last_error()
+    bad = jx.opts_default(pivot=2)
+    rc = L.jacobi_eig(4, fake, 4, b"U", fake, fake, 4, None, 4, None, 0, ctypes.byref(bad), ctypes.byref(info), None)
+    assert rc == -12
+    rc = L.jacobi_svd(8, 4, fake, 8, fake, fake, 8, fake, 4, None, 0, ctypes.byref(jx.opts_default(pivot=1)),
+                      ctypes.byref(info), None)
+    assert rc == -12 and "pivot" in jx.last_error()
+    n = (ctypes.c_int * 2)(16, 20)
+    off = (ctypes.c_int64 * 2)(0, 256)
+    infos = (jx.Info * 2)()
+    rc = L.jacobi_eig_batched(2, n, off, jx.F32, fake, fake, fake, None, None, 0,
+                              ctypes.byref(jx.opts_default(pivot=1)), infos, None)
+    assert rc == -11
+    # the test hook's own checks
+    hp = (ctypes.c_int * 4)(0, 1, 2, 3)
+    assert L.jacobi_pivot_step(256, 48, fake, 2, hp, fake, None, None) == -2
+    assert L.jacobi_pivot_step(256, 64, fake, 1, hp, fake, None, None) == -4
+    hp2 = (ctypes.c_int * 4)(1, 0, 2, 3)
+    assert L.jacobi_pivot_step(256, 64, fake, 2, hp2, fake, None, None) == -5

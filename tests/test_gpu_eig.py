@@ -134,6 +134,59 @@ def test_block_step_matches_oracle(jx, n, b, rnd):
     assert np.array_equal(Ag, Ag.T)
 
 
+def _rotation_near_singular_lead(b, rng):
+    """V = blockdiag(H1, H2) [[C, -S], [S, C]] with angles near pi/2: an
+    orthogonal 2b x 2b matrix whose leading b x b block is nearly singular."""
+    H1, H2 = inputs.haar(b, rng), inputs.haar(b, rng)
+    th = np.pi / 2 - 1e-3 * rng.random(b)
+    C, S = np.diag(np.cos(th)), np.diag(np.sin(th))
+    return np.block([[H1 @ C, -H1 @ S], [H2 @ S, H2 @ C]])
+
+
+@pytest.mark.parametrize("n,b,rnd", [(256, 64, 0), (384, 64, 2), (256, 32, 3), (512, 32, 5)])
+def test_pivot_step_matches_oracle(jx, n, b, rnd):
+    """The pivoting step (LU with partial pivoting on V_hat's leading rows) in
+    the solver's storage: the permutation equals the oracle's bit for bit,
+    V_hat P and P^T D_hat P are exact permutations, other blocks untouched."""
+    rng = np.random.default_rng(7 * n + b)
+    A, _ = inputs.eig_uniform(n, 60 + rnd)
+    A = np.triu(A) + np.triu(A, 1).T  # exactly symmetric
+    N = n // b
+    pairs = O.rr_list(N)[rnd]
+    # half Haar rotations, half with a nearly singular leading block
+    Vh = np.stack([inputs.haar(2 * b, rng) if k % 2 else _rotation_near_singular_lead(b, rng)
+                   for k in range(len(pairs))])
+    print(f"pivot step n={n} b={b}", flush=True)
+    Ag, Vg, perm = jx.jacobi_pivot_step(dev(A), b, pairs, dev(Vh))
+    Ag, Vg, perm = host(Ag), host(Vg), host(perm)
+    Ar = A.copy()
+    for k, (I, J) in enumerate(pairs):
+        pk = O.lupp_cols(Vh[k][:b])
+        np.testing.assert_array_equal(perm[k], pk)
+        np.testing.assert_array_equal(Vg[k], Vh[k][:, pk])
+        idx = np.r_[I * b:(I + 1) * b, J * b:(J + 1) * b]
+        Ar[np.ix_(idx, idx)] = A[np.ix_(idx, idx)][np.ix_(pk, pk)]
+        # the selected columns give a leading block far from singular
+        assert np.linalg.svd(Vg[k][:b, :b], compute_uv=False)[-1] >= 1e-2
+    np.testing.assert_array_equal(Ag, Ar)
+
+
+@pytest.mark.parametrize("n,b,graded", [(512, 32, False), (1024, 64, False), (1024, 64, True)])
+def test_eig_pivot_matches_oracle(jx, n, b, graded):
+    """Blocked solve with the pivoting step after every subproblem: the same
+    eigen-decomposition as the oracle, eigenvalues within 1e-12 ||A||_2."""
+    A, _ = (inputs.eig_graded if graded else inputs.eig_uniform)(n, 90 + n)
+    W, Q, info = eig_gpu(jx, A, block=b, pivot=1)
+    W0, _, info0 = eig_gpu(jx, A, block=b, want_vectors=0)
+    print(f"pivot n={n} b={b} graded={graded}: sweeps {info['sweeps']} (without pivoting {info0['sweeps']})",
+          flush=True)
+    assert info["status"] == 0, info
+    _check_against_oracle(A, W, Q)
+    Wv, _, infov = eig_gpu(jx, A, block=b, pivot=1, want_vectors=0)
+    assert infov["status"] == 0
+    assert np.max(np.abs(Wv - W)) <= 1e-12 * np.max(np.abs(W))
+
+
 @pytest.mark.parametrize("n,b,rnd", [(256, 64, 0), (384, 64, 2), (256, 32, 3), (512, 32, 5)])
 def test_block_step_fp32_matches_oracle(jx, n, b, rnd):
     """The FP32 kernels of the precision ladder's FP32 phase (single-block
