@@ -164,25 +164,28 @@ __global__ void k_extract_diag(int npad, int b, const double *__restrict__ ablk,
 }
 
 // rank[i] = #{ j : w_j strictly before w_i, or equal with j < i } (stable).
-__global__ void __launch_bounds__(256) k_rank(int n, const double *__restrict__ w, int dir,
-                                              int *__restrict__ rank) {
-    __shared__ double tile[1024];
-    const int i = blockIdx.x * 256 + threadIdx.x;
+// A workgroup ranks 64 values (one per lane); its 16 waves split the j range
+// and their counts are added at the end.
+__global__ void __launch_bounds__(1024) k_rank(int n, const double *__restrict__ w, int dir,
+                                               int *__restrict__ rank) {
+    __shared__ int part[16][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
     const double wi = (i < n) ? w[i] : 0.0;
+    const int chunk = (n + 15) / 16, j0 = wv * chunk, j1 = min(n, j0 + chunk);
     int cnt = 0;
-    for (int j0 = 0; j0 < n; j0 += 1024) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < 1024; t += 256) tile[t] = (j0 + t < n) ? w[j0 + t] : 0.0;
-        __syncthreads();
-        const int jn = min(1024, n - j0);
-        for (int t = 0; t < jn; ++t) {
-            const double wj = tile[t];
-            const int j = j0 + t;
-            const bool before = dir > 0 ? (wj < wi || (wj == wi && j < i)) : (wj > wi || (wj == wi && j < i));
-            cnt += before ? 1 : 0;
-        }
+    for (int j = j0; j < j1; ++j) {
+        const double wj = w[j];
+        const bool before = dir > 0 ? (wj < wi || (wj == wi && j < i)) : (wj > wi || (wj == wi && j < i));
+        cnt += before ? 1 : 0;
     }
-    if (i < n) rank[i] = cnt;
+    part[wv][lane] = cnt;
+    __syncthreads();
+    if (wv == 0 && i < n) {
+        int s = 0;
+        for (int k = 0; k < 16; ++k) s += part[k][lane];
+        rank[i] = s;
+    }
 }
 
 __global__ void k_scatter_values(int n, const double *__restrict__ w, const int *__restrict__ rank,
@@ -254,7 +257,7 @@ void launch_extract_diag(int npad, int b, const double *ablk, double *w, hipStre
 
 void launch_rank(int n, const double *w, int dir, int *rank, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_rank, dim3((n + 255) / 256), dim3(256), 0, s, n, w, dir, rank);
+    hipLaunchKernelGGL(k_rank, dim3((n + 63) / 64), dim3(1024), 0, s, n, w, dir, rank);
     JX_LAUNCHED();
 }
 

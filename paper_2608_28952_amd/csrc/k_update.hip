@@ -528,7 +528,15 @@ k_update_a_crit(const int *__restrict__ pairs, T *__restrict__ ablk, const T *__
                 const T *__restrict__ side) {
     extern __shared__ double lds_raw[];
     constexpr int NS = B == 64 ? CRIT_SPLIT : 1;
-    const int i = blockIdx.x / NS, part = blockIdx.x % NS;
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its
+    // own L2): workgroup w runs on XCD w mod 8.  Numbering the (tile, part)
+    // units XCD by XCD puts the NS parts of a tile on one XCD, so the tile is
+    // fetched from HBM into one L2 instead of NS of them (a bijection on the
+    // first 8 floor(G / 8) workgroups, identity on the rest).
+    const int per = gridDim.x / 8;
+    int u = blockIdx.x;
+    if (u < 8 * per) u = (u % 8) * per + u / 8;
+    const int i = u / NS, part = u % NS;
     const int p = tiles[2 * i], q = tiles[2 * i + 1];
     const bool idp = flags[p] != 0, idq = flags[q] != 0;
     if (idp && idq) return;  // the tile does not change (and its rest is skipped the same way)
