@@ -212,7 +212,7 @@ def extras(jx):
     log("extras: batched autotune")
     tune = os.path.join(tempfile.mkdtemp(), "tune.json")
     t0 = time.perf_counter()
-    jx.batched_autotune(tune, dtype_f64=False, per_bucket=32, seed=0)
+    jx.batched_autotune(tune, dtype_f64=False, per_bucket=1024, seed=0)
     tune_s = time.perf_counter() - t0
     os.environ["JACOBI_TUNE_FILE"] = tune
     try:

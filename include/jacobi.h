@@ -240,14 +240,19 @@ int jacobi_eig_batched(int batch, const int *h_n, const int64_t *h_offA, int dty
 /*
  * Tuning table of jacobi_eig_batched: per element type and size bucket
  * (0: n <= 32, 1: <= 64, 2: <= 128, 3: <= 192, 4: <= 256) the block size bs
- * (8 or 16) and whether the FP32 phase runs (mixed).  The active table is the
+ * (8 or 16) and the FP32 phase (mixed: 0 none, 1 until off(A) <= 1e-5
+ * ||A||_F, 2 until 1e-3 ||A||_F; either ends early when the decrease
+ * stalls).  The active table is the
  * JSON file named by the environment variable JACOBI_TUNE_FILE when it parses
  * and was written for the current device, else built-in defaults.
  *   jacobi_batched_tuning: returns 1 (from the file), 0 (defaults) or -1.
  *   jacobi_batched_autotune: times every (bs, mixed) candidate on a seeded
  *     calibration batch of `per_bucket` random symmetric matrices per bucket
- *     (fastest candidate whose every matrix converges), writes the table and
- *     the timings as JSON to `path`, and makes it active for this process.
+ *     (a batch that fills the GPU, e.g. 1024, times throughput); the active
+ *     entry is timed first and kept unless a candidate whose every matrix
+ *     converges is at least 3 % faster.  Writes the table and the timings
+ *     (per bucket, the active entry's first) as JSON to `path` and makes it
+ *     active for this process.
  *     Returns 0, -1 (arguments), -4 (file not written) or 3 (HIP error).
  *   jacobi_batched_graph_stats: cached-graph hits and graphs built so far.
  */

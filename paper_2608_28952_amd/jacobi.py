@@ -336,9 +336,11 @@ def batched_graph_stats():
     return h.value, b.value
 
 
-def batched_autotune(path, dtype_f64=False, per_bucket=32, seed=0):
+def batched_autotune(path, dtype_f64=False, per_bucket=1024, seed=0):
     """Time the candidate class parameters on a seeded calibration batch per
-    size bucket, write the JSON cache to `path` and make it active."""
+    size bucket, write the JSON cache to `path` and make it active.  The
+    batch should fill the GPU (a few matrices per CU) so that the timings are
+    throughput, as in a large call, not one matrix's latency."""
     _check(lib().jacobi_batched_autotune(F64 if dtype_f64 else F32, per_bucket, seed, str(path).encode()))
 
 

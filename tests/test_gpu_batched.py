@@ -233,7 +233,8 @@ def test_batched_autotune_cache(jx, tmp_path):
     jx.batched_autotune(path, dtype_f64=False, per_bucket=6, seed=2)
     doc = json.loads(path.read_text())
     assert len(doc["f32_bs"]) == 5 and all(b in (8, 16) for b in doc["f32_bs"])
-    assert all(t > 0 for t in doc["calibration_ms"])
+    assert all(m in (0, 1, 2) for m in doc["f32_mixed"])
+    assert len(doc["calibration_ms"]) == 5 * 6 and all(t > 0 for t in doc["calibration_ms"])
     assert jx.batched_tuning(False, 4)[2] is True
     # a corrupt cache file gives the defaults
     bad = tmp_path / "bad.json"
@@ -248,6 +249,34 @@ def test_batched_autotune_cache(jx, tmp_path):
         assert jx.batched_tuning(False, 4)[2] is True
     finally:
         del os.environ["JACOBI_TUNE_FILE"]
+
+
+def test_batched_early_switch_level_matches_oracle(jx, tmp_path):
+    """A table whose every bucket ends the FP32 phase at 1e-3 ||A||_F (mixed
+    level 2): fewer FP32 sweeps, and the same results to the 1e-12 bar."""
+    path = tmp_path / "tune.json"
+    jx.batched_autotune(path, dtype_f64=False, per_bucket=4, seed=3)
+    doc = json.loads(path.read_text())
+    doc["f32_mixed"] = [2] * 5
+    lvl2 = tmp_path / "level2.json"
+    lvl2.write_text(json.dumps(doc))
+    sizes, offs, packed = inputs.batched_case(40, 9)
+    os.environ["JACOBI_TUNE_FILE"] = str(lvl2)
+    try:
+        assert jx.batched_tuning(False, 2)[1] == 2
+        (Ws, Qs), infos = run(jx, sizes, offs, packed, precision=jx.PREC_MIXED_FP32)
+    finally:
+        del os.environ["JACOBI_TUNE_FILE"]
+    (_, _), infos1 = run(jx, sizes, offs, packed, precision=jx.PREC_MIXED_FP32)
+    f32_2 = sum(i["sweeps_by_prec"][1] for i in infos)
+    f32_1 = sum(i["sweeps_by_prec"][1] for i in infos1)
+    print(f"FP32 sweeps: level 2 {f32_2}, level 1 {f32_1}", flush=True)
+    assert f32_2 < f32_1
+    for k, n in enumerate(sizes):
+        n = int(n)
+        assert infos[k]["status"] == 0
+        A = packed[offs[k]:offs[k + 1]].astype(np.float64).reshape((n, n), order="F")
+        check_against_oracle(A, Ws[k], Qs[k])
 
 
 def test_batched_full_workload_sampled(jx):
