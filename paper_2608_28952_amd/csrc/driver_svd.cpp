@@ -33,11 +33,14 @@ SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
     p.b = o.block > 0 ? o.block : svd_block(n);
     const int unit = std::max(2 * p.b, 128);
     p.npad = std::max(unit, (n + unit - 1) / unit * unit);
-    p.nchunks = std::max(1, std::min(32, (m + 1023) / 1024));
-    const int rows = std::max(128, ((m + p.nchunks - 1) / p.nchunks + 127) / 128 * 128);
-    p.mpad = rows * p.nchunks;
     p.N = p.npad / p.b;
     p.H = p.N / 2;
+    // Gram row chunks: chunks of up to 1024 rows, more (down to 128 rows) when
+    // the pairs alone give too few workgroups (about 256 fill the chip)
+    const int fill = std::min((256 + p.H - 1) / p.H, (m + 127) / 128);
+    p.nchunks = std::max(1, std::min(32, std::max((m + 1023) / 1024, fill)));
+    const int rows = std::max(128, ((m + p.nchunks - 1) / p.nchunks + 127) / 128 * 128);
+    p.mpad = rows * p.nchunks;
     p.R = (o.ordering == JACOBI_ORDER_ANTIDIAG) ? p.N : p.N - 1;
     p.vectors = o.want_vectors != 0;
     p.mixed = o.precision != JACOBI_PREC_FP64;

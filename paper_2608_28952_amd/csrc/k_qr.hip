@@ -21,13 +21,15 @@ constexpr int QLD = QB + 1;    // LDS stride
 // and is replaced by 1 so that the kernel completes.
 constexpr size_t CHOL_LDS = sizeof(double) * (QB * QLD + QB);
 
-__global__ void __launch_bounds__(256) k_chol_diag(double *__restrict__ W, int ldw, int k0,
+constexpr int CNT = 1024;  // threads of k_chol_diag
+
+__global__ void __launch_bounds__(CNT) k_chol_diag(double *__restrict__ W, int ldw, int k0,
                                                    double *__restrict__ Rinv, int *__restrict__ flag) {
     extern __shared__ double lds[];
     double *T = lds;               // T[i * QLD + j] = element (i, j)
     double *rd = lds + QB * QLD;   // R's diagonal
     const int tid = threadIdx.x;
-    for (int e = tid; e < QB * QB; e += 256) {
+    for (int e = tid; e < QB * QB; e += CNT) {
         const int i = e % QB, j = e / QB;
         T[i * QLD + j] = i <= j ? W[(size_t)(k0 + j) * ldw + k0 + i] : 0.0;  // upper triangle
     }
@@ -43,25 +45,27 @@ __global__ void __launch_bounds__(256) k_chol_diag(double *__restrict__ W, int l
         }
         const double r = sqrt(d), ir = 1.0 / r;
         __syncthreads();  // every lane has read the pivot
-        for (int c = j + 1 + tid; c < QB; c += 256) T[j * QLD + c] *= ir;
+        for (int c = j + 1 + tid; c < QB; c += CNT) T[j * QLD + c] *= ir;
         if (tid == 0) {
             T[j * QLD + j] = r;
             rd[j] = r;
         }
         __syncthreads();
-        const int m = QB - j - 1;  // trailing order
-        for (int e = tid; e < m * m; e += 256) {
-            const int ii = e % m, cc = e / m;
-            if (ii <= cc) {
-                const int i = j + 1 + ii, c = j + 1 + cc;
-                T[i * QLD + c] -= T[j * QLD + i] * T[j * QLD + c];
+        // trailing upper triangle: thread (rg, cc) takes column c = j + 1 + cc,
+        // rows j + 1 + rg, + CNT / QB, ... up to c
+        {
+            constexpr int RG = CNT / QB;
+            const int c = j + 1 + (tid % QB), rg = tid / QB;
+            if (c < QB) {
+                const double tjc = T[j * QLD + c];
+                for (int i = j + 1 + rg; i <= c; i += RG) T[i * QLD + c] -= T[j * QLD + i] * tjc;
             }
         }
         __syncthreads();
     }
     if (bad && tid == 0) flag[0] = 1;  // one workgroup per launch: a plain store
     // R_kk back to W (upper), zero below
-    for (int e = tid; e < QB * QB; e += 256) {
+    for (int e = tid; e < QB * QB; e += CNT) {
         const int i = e % QB, j = e / QB;
         W[(size_t)(k0 + j) * ldw + k0 + i] = i <= j ? T[i * QLD + j] : 0.0;
     }
@@ -73,9 +77,17 @@ __global__ void __launch_bounds__(256) k_chol_diag(double *__restrict__ W, int l
         const int c = tid;
         const double xcc = 1.0 / rd[c];
         for (int i = c - 1; i >= 0; --i) {
-            double s = T[i * QLD + c] * xcc;  // l = c
-            for (int l = i + 1; l < c; ++l) s += T[i * QLD + l] * T[c * QLD + l];
-            T[c * QLD + i] = -s / rd[i];
+            // four partial sums (independent FMA chains), added at the end
+            double s0 = T[i * QLD + c] * xcc, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // l = c
+            int l = i + 1;
+            for (; l + 3 < c; l += 4) {
+                s0 += T[i * QLD + l] * T[c * QLD + l];
+                s1 += T[i * QLD + l + 1] * T[c * QLD + l + 1];
+                s2 += T[i * QLD + l + 2] * T[c * QLD + l + 2];
+                s3 += T[i * QLD + l + 3] * T[c * QLD + l + 3];
+            }
+            for (; l < c; ++l) s0 += T[i * QLD + l] * T[c * QLD + l];
+            T[c * QLD + i] = -((s0 + s1) + (s2 + s3)) / rd[i];
         }
         for (int i = 0; i < QB; ++i)
             Rinv[(size_t)c * QB + i] = i < c ? T[c * QLD + i] : (i == c ? xcc : 0.0);
@@ -216,7 +228,7 @@ void launch_chol_diag(double *W, int ldw, int k0, double *Rinv, int *flag, hipSt
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)CHOL_LDS));
         attr = true;
     }
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), CHOL_LDS, s, W, ldw, k0, Rinv, flag);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(CNT), CHOL_LDS, s, W, ldw, k0, Rinv, flag);
     JX_LAUNCHED();
 }
 
