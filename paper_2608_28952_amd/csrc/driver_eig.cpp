@@ -737,6 +737,10 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
 // b = 1: scalar two-sided Jacobi (Alg. 1 with b = 1) in round-robin order
 // ---------------------------------------------------------------------------
 
+// Orders from which a round runs over n/2 workgroups (one launch per round);
+// below, every sweep runs in one persistent workgroup.
+constexpr int SCALAR_MULTI_MIN = 128;
+
 size_t scalar_workspace(int n) {
     const int ne = n + (n & 1);
     WorkspaceBuilder wb;
@@ -746,6 +750,10 @@ size_t scalar_workspace(int n) {
     wb.add(sizeof(double) * 4);                    // sweeps, off-norm, ||A||_F
     wb.add(sizeof(double) * n);                    // diagonal
     wb.add(sizeof(int) * n);                       // ranks
+    if (n >= SCALAR_MULTI_MIN) {
+        wb.add(sizeof(double) * (size_t)n * n);    // the second copy of A (rounds alternate)
+        wb.add(sizeof(int) * 4);                   // rotations of a sweep
+    }
     return wb.total();
 }
 
@@ -769,6 +777,9 @@ int run_eig_scalar(int n, const double *dA, int lda, char uplo, double *dW, doub
     double *out = reinterpret_cast<double *>(ws + wb.add(sizeof(double) * 4));
     double *w = reinterpret_cast<double *>(ws + wb.add(sizeof(double) * n));
     int *rank = reinterpret_cast<int *>(ws + wb.add(sizeof(int) * n));
+    const bool multi = n >= SCALAR_MULTI_MIN;
+    double *A2 = multi ? reinterpret_cast<double *>(ws + wb.add(sizeof(double) * (size_t)n * n)) : nullptr;
+    int *rot = multi ? reinterpret_cast<int *>(ws + wb.add(sizeof(int) * 4)) : nullptr;
     std::vector<int> hp, hs;
     make_schedule(ne, JACOBI_ORDER_ROUND_ROBIN, hp, hs);
     JX_HIP(hipMemcpyAsync(pairs, hp.data(), sizeof(int) * hp.size(), hipMemcpyHostToDevice, s));
@@ -777,10 +788,45 @@ int run_eig_scalar(int n, const double *dA, int lda, char uplo, double *dW, doub
     if (vec) launch_set_identity(n, n, Q, n, s);
     const bool rel = o.threshold == 1;
     const double tol = o.tol > 0.0 ? o.tol : (rel ? 2.220446049250313e-16 : 1e-14);
-    launch_scalar_rr(n, ne, pairs, A, vec ? Q : nullptr, tol, o.max_sweeps, rel ? 1 : 0, out, s);
-    double h[4] = {0.0, 0.0, 0.0, 0.0};
-    JX_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
-    JX_HIP(hipStreamSynchronize(s));
+    double h[4] = {0.0, 0.0, 0.0, 0.0};  // sweeps, Xi(A), ||A||_F, rotations of the last sweep
+    if (!multi) {
+        launch_scalar_rr(n, ne, pairs, A, vec ? Q : nullptr, tol, o.max_sweeps, rel ? 1 : 0, out, s);
+        JX_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+        JX_HIP(hipStreamSynchronize(s));
+    } else {
+        // one launch per round; the rounds alternate between A and A2
+        DeviceCtx &ctx = device_ctx();
+        std::lock_guard<std::mutex> lk(ctx.mu);  // its pinned scalars
+        double *hs2 = reinterpret_cast<double *>(ctx.pinned);
+        launch_scalar_norms(n, A, out, s);
+        JX_HIP(hipMemcpyAsync(hs2, out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        JX_HIP(hipStreamSynchronize(s));
+        double off2 = hs2[0];
+        const double fro = std::sqrt(hs2[1]);
+        int sw = 0, rotated = 1;
+        double *cur = A, *nxt = A2;
+        const int H = ne / 2;
+        while (sw < o.max_sweeps && off2 == off2 && (rel ? rotated > 0 : std::sqrt(off2) > tol * fro)) {
+            launch_fill_int(rot, 1, 0, s);
+            for (int r = 0; r < ne - 1; ++r) {
+                launch_scalar_round(n, ne, pairs + (size_t)2 * r * H, cur, nxt, vec ? Q : nullptr, tol, rel ? 1 : 0,
+                                    rot, s);
+                std::swap(cur, nxt);
+            }
+            ++sw;
+            launch_scalar_norms(n, cur, out, s);
+            JX_HIP(hipMemcpyAsync(hs2, out, sizeof(double), hipMemcpyDeviceToHost, s));
+            JX_HIP(hipMemcpyAsync(hs2 + 2, rot, sizeof(int), hipMemcpyDeviceToHost, s));
+            JX_HIP(hipStreamSynchronize(s));
+            off2 = hs2[0];
+            rotated = *reinterpret_cast<int *>(hs2 + 2);
+        }
+        if (cur != A) JX_HIP(hipMemcpyAsync(A, cur, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+        h[0] = sw;
+        h[1] = std::sqrt(off2);
+        h[2] = fro;
+        h[3] = rotated;
+    }
     const int sweeps = (int)h[0];
     const bool done = rel ? h[3] == 0.0 : h[1] <= tol * h[2];
     int status = (std::isfinite(h[1]) && std::isfinite(h[2])) ? (done ? 0 : 1) : 2;

@@ -270,6 +270,12 @@ void launch_scatter_columns(int rows, int n, const double *src, int lds_, const 
 void launch_scalar_rr(int n, int ne, const int *pairs, double *A, double *Q, double tol, int max_sweeps, int relative,
                       double *out, hipStream_t s);
 void launch_sym_full(int n, const double *src, int lds_, char uplo, double *dst, hipStream_t s);
+// one round of scalar Jacobi over n/2 workgroups (reads Acur, writes Anext,
+// updates Q's columns in place); rot (optional) += rotations of the round
+void launch_scalar_round(int n, int ne, const int *pairs_round, const double *Acur, double *Anext, double *Q,
+                         double tol, int relative, int *rot, hipStream_t s);
+// out[0] = Xi(A)^2, out[1] = ||A||_F^2 (full n x n A, fixed order)
+void launch_scalar_norms(int n, const double *A, double *out, hipStream_t s);
 
 // Re-sorting between sweeps: inv from the ranks of the diagonal (identity on
 // the padding), then dst(i', j') = src(inv[i'], inv[j']) (upper block storage)

@@ -10,6 +10,10 @@
 // memory (L2-resident at these orders); workgroup barriers order the rounds.
 // After each sweep the off-norm Xi(A) of eq. (Omega_A) is summed directly;
 // with the relative threshold the sweeps end once a sweep rotates nothing.
+//
+// Two forms: k_scalar_rr runs every sweep in one persistent workgroup (small
+// orders); k_scalar_round runs one round over n/2 workgroups, workgroup k
+// owning the two columns of pair k (larger orders, one launch per round).
 #include "jx_common.hpp"
 #include "jx_sweep.hpp"
 
@@ -128,7 +132,116 @@ __global__ void k_sym_full(int n, const double *__restrict__ src, int lds_, int 
     }
 }
 
+// One round of the multi-workgroup form.  A is full, column-major (n x n);
+// this round reads Acur only and writes Anext, so every workgroup sees the
+// matrix as the round found it.  Workgroup k1 computes the rotations of all
+// H pairs (each workgroup the same values), loads its columns p1, q1, and for
+// every pair k2 writes the 2 x 2 block (rows p2, q2; columns p1, q1) of
+// J^T A J: rows rotated by pair k2, columns by pair k1 (its own block by the
+// closed form).  Q(:, [p1, q1]) <- Q(:, [p1, q1]) J_k1 in place (only this
+// workgroup touches those columns).  rot (optional): workgroup 0 adds the
+// number of rotations of the round.
+__global__ void __launch_bounds__(256) k_scalar_round(int n, int H, const int *__restrict__ pr,
+                                                      const double *__restrict__ Acur, double *__restrict__ Anext,
+                                                      double *__restrict__ Q, double tol, int relative,
+                                                      int *__restrict__ rot) {
+    extern __shared__ double sm[];
+    double *cs = sm, *sn = sm + H, *ta = sm + 2 * H, *cp = sm + 3 * H, *cq = cp + n;
+    const int tid = threadIdx.x, k1 = blockIdx.x;
+    const int p1 = pr[2 * k1], q1 = pr[2 * k1 + 1];
+    const bool hq1 = q1 < n;  // index n is the placeholder of an odd order
+    int mine = 0;
+    for (int k = tid; k < H; k += 256) {
+        const int p = pr[2 * k], q = pr[2 * k + 1];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (q < n) {
+            const double apq = Acur[(size_t)q * n + p], app = Acur[(size_t)p * n + p], aqq = Acur[(size_t)q * n + q];
+            if (!relative || fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+                rot_cst(app, aqq, apq, c, s, t);
+                t *= apq;
+                mine += (s != 0.0) ? 1 : 0;
+            }
+        }
+        cs[k] = c;
+        sn[k] = s;
+        ta[k] = t;
+    }
+    if (rot && k1 == 0 && mine) atomicAdd(rot, mine);
+    for (int i = tid; i < n; i += 256) {
+        cp[i] = Acur[(size_t)p1 * n + i];
+        cq[i] = hq1 ? Acur[(size_t)q1 * n + i] : 0.0;
+    }
+    __syncthreads();
+    const double c1 = cs[k1], s1 = sn[k1];
+    double *op = Anext + (size_t)p1 * n, *oq = Anext + (size_t)q1 * n;
+    for (int k2 = tid; k2 < H; k2 += 256) {
+        const int p2 = pr[2 * k2], q2 = pr[2 * k2 + 1];
+        if (k2 == k1) {  // the pair's own block: a_pp - t a_pq, a_qq + t a_pq, 0
+            const bool r = hq1 && s1 != 0.0;
+            op[p1] = r ? cp[p1] - ta[k1] : cp[p1];
+            if (hq1) {
+                oq[q1] = r ? cq[q1] + ta[k1] : cq[q1];
+                op[q1] = r ? 0.0 : cp[q1];
+                oq[p1] = r ? 0.0 : cq[p1];
+            }
+            continue;
+        }
+        const bool hq2 = q2 < n;
+        const double c2 = cs[k2], s2 = sn[k2];
+        const double a11 = cp[p2], a12 = cq[p2];
+        const double a21 = hq2 ? cp[q2] : 0.0, a22 = hq2 ? cq[q2] : 0.0;
+        // rows by pair k2: p' = c p - s q, q' = s p + c q; then columns by pair k1
+        const double b11 = c2 * a11 - s2 * a21, b21 = s2 * a11 + c2 * a21;
+        const double b12 = c2 * a12 - s2 * a22, b22 = s2 * a12 + c2 * a22;
+        op[p2] = c1 * b11 - s1 * b12;
+        if (hq1) oq[p2] = s1 * b11 + c1 * b12;
+        if (hq2) {
+            op[q2] = c1 * b21 - s1 * b22;
+            if (hq1) oq[q2] = s1 * b21 + c1 * b22;
+        }
+    }
+    if (Q && hq1 && s1 != 0.0)
+        for (int i = tid; i < n; i += 256) {
+            const double qp = Q[(size_t)p1 * n + i], qq = Q[(size_t)q1 * n + i];
+            Q[(size_t)p1 * n + i] = c1 * qp - s1 * qq;
+            Q[(size_t)q1 * n + i] = s1 * qp + c1 * qq;
+        }
+}
+
+// out[0] = Xi(A)^2 (off-diagonal sum of squares), out[1] = ||A||_F^2 of the
+// full n x n matrix, in one workgroup (a fixed order).
+__global__ void __launch_bounds__(1024) k_scalar_norms(int n, const double *__restrict__ A, double *__restrict__ out) {
+    __shared__ double red[32];
+    double off2 = 0.0, fro2 = 0.0;
+    for (size_t e = threadIdx.x; e < (size_t)n * n; e += 1024) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        const double v = A[e];
+        fro2 += v * v;
+        if (i != j) off2 += v * v;
+    }
+    off2 = block_sum<1024>(off2, red);
+    fro2 = block_sum<1024>(fro2, red);
+    if (threadIdx.x == 0) {
+        out[0] = off2;
+        out[1] = fro2;
+    }
+}
+
 }  // namespace
+
+void launch_scalar_round(int n, int ne, const int *pairs_round, const double *Acur, double *Anext, double *Q,
+                         double tol, int relative, int *rot, hipStream_t s) {
+    const int H = ne / 2;
+    const size_t lds = sizeof(double) * (3 * (size_t)H + 2 * (size_t)n);
+    hipLaunchKernelGGL(k_scalar_round, dim3(H), dim3(256), lds, s, n, H, pairs_round, Acur, Anext, Q, tol, relative,
+                       rot);
+    JX_LAUNCHED();
+}
+
+void launch_scalar_norms(int n, const double *A, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_norms, dim3(1), dim3(1024), 0, s, n, A, out);
+    JX_LAUNCHED();
+}
 
 void launch_sym_full(int n, const double *src, int lds_, char uplo, double *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_sym_full, dim3((n + 255) / 256, n), dim3(256), 0, s, n, src, lds_,

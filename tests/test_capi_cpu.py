@@ -84,8 +84,10 @@ def test_opts_defaults_and_workspace():
     ws = jx.jacobi_eig_workspace(4096, jx.opts_default(want_vectors=0, refine=0))
     assert o.ordering == jx.ORDER_ROUND_ROBIN_SORTED
     assert 2 * ublk + vhat + side <= ws < 2 * ublk + vhat + side + 2 * 2 ** 20
-    # b = 1 (scalar): A, Q, the schedule and a few vectors
-    assert 2 * 256 * 256 * 8 <= jx.jacobi_eig_workspace(256, jx.opts_default(block=1)) < 2 * 256 * 256 * 8 + 2 ** 20
+    # b = 1 (scalar): A, Q, the schedule and a few vectors; from n = 128 a
+    # second copy of A (one launch per round, alternating)
+    assert 2 * 64 * 64 * 8 <= jx.jacobi_eig_workspace(64, jx.opts_default(block=1)) < 2 * 64 * 64 * 8 + 2 ** 20
+    assert 3 * 256 * 256 * 8 <= jx.jacobi_eig_workspace(256, jx.opts_default(block=1)) < 3 * 256 * 256 * 8 + 2 ** 20
     assert jx.jacobi_eig_workspace(2048, jx.opts_default(block=1)) == 0  # beyond the scalar kernel's orders
     assert jx.jacobi_eig_workspace(100) > 0
     assert jx.jacobi_eig_workspace(64, jx.opts_default(block=48)) == 0  # unsupported block
