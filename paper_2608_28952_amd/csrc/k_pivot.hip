@@ -11,6 +11,7 @@
 // X(i, j)) for i, j > k with l_i = X(i, k) / X(k, k).  The permuted V_hat and
 // D_hat are then written back through an LDS copy of each.
 #include "jx_common.hpp"
+#include "jx_sweep.hpp"
 
 namespace jx {
 
@@ -23,7 +24,9 @@ struct PivLds {
     static constexpr int B = M2 / 2;
     static constexpr int LDX = B + 1;                                   // X row stride (doubles)
     static constexpr size_t STAGE = sizeof(double) * (size_t)M2 * M2;  // >= X (M2 x LDX)
-    static constexpr size_t BYTES = STAGE + sizeof(double) * M2 + sizeof(int) * (M2 + 8);
+    // stage | multipliers (M2) | next-pivot candidates (PNT / B values and
+    // rows) | perm (M2)
+    static constexpr size_t BYTES = STAGE + sizeof(double) * (M2 + PNT / B) + sizeof(int) * (PNT / B + M2);
 };
 
 // Element (r, c) of the pair's rotation and (r <= c) of its D_hat, and the
@@ -77,9 +80,7 @@ __global__ void __launch_bounds__(PNT) k_pivot(PivotArgs a) {
     extern __shared__ double smem[];
     double *X = smem;                                         // M2 x LDX, later the M2 x M2 stage
     double *lmul = smem + (size_t)M2 * M2;                    // multipliers l_i
-    int *perm = reinterpret_cast<int *>(lmul + M2);           // M2
-    int *piv = perm + M2;  // pivot row of step k in piv[k & 1] (a step's slot is
-                           // rewritten two steps later, after every thread read it)
+    int *perm = reinterpret_cast<int *>(lmul + M2 + PNT / B) + PNT / B;  // M2 (after the candidates)
     const int tid = threadIdx.x, lane = tid & 63;
     const int pr = blockIdx.x;
     int *pout = a.perm_out ? a.perm_out + (size_t)pr * M2 : nullptr;
@@ -118,50 +119,96 @@ __global__ void __launch_bounds__(PNT) k_pivot(PivotArgs a) {
     for (int i = tid; i < M2; i += PNT) perm[i] = i;
     __syncthreads();
 
+    // Step k: wave 0 takes the pivot (from the column maxima the previous
+    // step's update left; step 0 searches itself), swaps the rows and forms
+    // the multipliers, its lanes ordered among themselves by wave-level LDS
+    // syncs; then every wave updates the trailing block, and the threads of
+    // column k + 1 record that column's maxima for the next step.  Two
+    // workgroup barriers per step.
+    constexpr int RS = PNT / B;  // threads per column in the update
+    double *candv = lmul + M2;   // RS candidates (|x|, row) for the next pivot
+    int *candi = reinterpret_cast<int *>(candv + RS);
+    if (tid < RS) {  // step 0's candidates: rows tid, tid + RS, ... of column 0
+        double best = -1.0;
+        int bi = M2;
+        for (int i = tid; i < M2; i += RS) {
+            const double m = fabs(X[i * LDX]);
+            if (m > best) { best = m; bi = i; }
+        }
+        candv[tid] = best;
+        candi[tid] = bi;
+    }
+    __syncthreads();
     for (int k = 0; k < B; ++k) {
-        if (tid < 64) {  // pivot search by wave 0: (|x|, -i) maximal
-            double best = -1.0;
-            int bi = M2;
-            for (int i = k + lane; i < M2; i += 64) {
-                const double m = fabs(X[i * LDX + k]);
-                if (m > best) { best = m; bi = i; }  // rows ascending per lane: first max kept
+        if (tid < 64) {
+            // the first maximal row: largest |x|, the smaller row on ties
+            double best = candv[0];
+            int p = candi[0];
+#pragma unroll
+            for (int r = 1; r < RS; ++r) {
+                const double v = candv[r];
+                const int i = candi[r];
+                if (v > best || (v == best && i < p)) { best = v; p = i; }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            if (p != k) {  // swap rows k and p of X (lane j: column j), entries k and p of perm
+                for (int j = lane; j < B; j += 64) {
+                    const double t = X[k * LDX + j];
+                    X[k * LDX + j] = X[p * LDX + j];
+                    X[p * LDX + j] = t;
+                }
+                if (lane == 0) {
+                    const int t = perm[k];
+                    perm[k] = perm[p];
+                    perm[p] = t;
+                }
             }
-            if (lane == 0) piv[k & 1] = bi;
+            wave_lds_sync();
+            const double dk = X[k * LDX + k];
+            for (int i = k + 1 + lane; i < M2; i += 64) lmul[i] = dk != 0.0 ? X[i * LDX + k] / dk : 0.0;
         }
         __syncthreads();
-        const int p = piv[k & 1];
-        if (p != k) {  // swap rows k and p of X, entries k and p of perm
-            for (int j = tid; j < B; j += PNT) {
-                const double t = X[k * LDX + j];
-                X[k * LDX + j] = X[p * LDX + j];
-                X[p * LDX + j] = t;
-            }
-            if (tid == 0) {
-                const int t = perm[k];
-                perm[k] = perm[p];
-                perm[p] = t;
-            }
-            __syncthreads();
-        }
-        const double dk = X[k * LDX + k];
-        if (dk != 0.0 && k + 1 < B) {
-            for (int i = k + 1 + tid; i < M2; i += PNT) lmul[i] = X[i * LDX + k] / dk;
-            __syncthreads();
-            // thread: column j = tid mod B, rows k + 1 + tid / B in steps of PNT / B
-            constexpr int RS = PNT / B;
-            const int j = tid % B;
+        if (k + 1 < B) {
+            // thread: column j = tid mod B, rows k + 1 + tid / B in steps of RS
+            // (a zero pivot leaves zero multipliers: the column is all zero)
+            const int j = tid % B, r = tid / B;
             if (j > k) {
-                const double xkj = X[k * LDX + j];
-#pragma unroll 4
-                for (int i = k + 1 + tid / B; i < M2; i += RS) X[i * LDX + j] = fma(-lmul[i], xkj, X[i * LDX + j]);
+                double *__restrict__ Xj = X + j;
+                const double *__restrict__ lm = lmul;
+                const double xkj = Xj[k * LDX];
+                // four rows per iteration, their loads issued before any
+                // store; every column tracks its maxima (only column k + 1's
+                // are kept: a branch here would split the waves)
+                double best = -1.0;
+                int bi = M2;
+                int i = k + 1 + r;
+                for (; i + 3 * RS < M2; i += 4 * RS) {
+                    const double l0 = lm[i], l1 = lm[i + RS], l2 = lm[i + 2 * RS], l3 = lm[i + 3 * RS];
+                    const double x0 = Xj[i * LDX], x1 = Xj[(i + RS) * LDX], x2 = Xj[(i + 2 * RS) * LDX],
+                                 x3 = Xj[(i + 3 * RS) * LDX];
+                    const double v0 = fma(-l0, xkj, x0), v1 = fma(-l1, xkj, x1), v2 = fma(-l2, xkj, x2),
+                                 v3 = fma(-l3, xkj, x3);
+                    Xj[i * LDX] = v0;
+                    Xj[(i + RS) * LDX] = v1;
+                    Xj[(i + 2 * RS) * LDX] = v2;
+                    Xj[(i + 3 * RS) * LDX] = v3;
+                    // rows ascending: the first maximum is kept
+                    if (fabs(v0) > best) { best = fabs(v0); bi = i; }
+                    if (fabs(v1) > best) { best = fabs(v1); bi = i + RS; }
+                    if (fabs(v2) > best) { best = fabs(v2); bi = i + 2 * RS; }
+                    if (fabs(v3) > best) { best = fabs(v3); bi = i + 3 * RS; }
+                }
+                for (; i < M2; i += RS) {
+                    const double v = fma(-lm[i], xkj, Xj[i * LDX]);
+                    Xj[i * LDX] = v;
+                    if (fabs(v) > best) { best = fabs(v); bi = i; }
+                }
+                if (j == k + 1) {
+                    candv[r] = best;
+                    candi[r] = bi;
+                }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
     if (pout)
         for (int i = tid; i < M2; i += PNT) pout[i] = perm[i];
