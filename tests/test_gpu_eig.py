@@ -171,12 +171,14 @@ def test_pivot_step_matches_oracle(jx, n, b, rnd):
     np.testing.assert_array_equal(Ag, Ar)
 
 
-@pytest.mark.parametrize("n,b,graded", [(512, 32, False), (1024, 64, False), (1024, 64, True)])
-def test_eig_pivot_matches_oracle(jx, n, b, graded):
-    """Blocked solve with the pivoting step after every subproblem: the same
+@pytest.mark.parametrize("n,b,graded,prec", [(512, 32, False, 0), (1024, 64, False, 0), (1024, 64, True, 0),
+                                             (1024, 64, True, 1)])
+def test_eig_pivot_matches_oracle(jx, n, b, graded, prec):
+    """Blocked solve with the pivoting step after every subproblem of the
+    FP64 sweeps (the FP32 phase of the ladder runs without it): the same
     eigen-decomposition as the oracle, eigenvalues within 1e-12 ||A||_2."""
     A, _ = (inputs.eig_graded if graded else inputs.eig_uniform)(n, 90 + n)
-    W, Q, info = eig_gpu(jx, A, block=b, pivot=1)
+    W, Q, info = eig_gpu(jx, A, block=b, pivot=1, precision=prec)
     W0, _, info0 = eig_gpu(jx, A, block=b, want_vectors=0)
     print(f"pivot n={n} b={b} graded={graded}: sweeps {info['sweeps']} (without pivoting {info0['sweeps']})",
           flush=True)
