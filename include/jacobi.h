@@ -220,8 +220,9 @@ int jacobi_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, 
  *              the block size of the two-level scheme), precision
  *              (JACOBI_PREC_FP64: FP64 sweeps only; otherwise an FP32 phase
  *              precedes the FP64 refinement where the tuning table says so),
- *              want_vectors, sort.  ordering, inner_max_sweeps and refine are
- *              not used.
+ *              want_vectors, sort.  ordering, inner_max_sweeps, refine and
+ *              precondition are not used; threshold and pivot must be 0
+ *              (-11 otherwise).
  *   dWork      workspace of jacobi_eig_batched_workspace() bytes, or NULL (the
  *              library allocates it; the graph is then not cached)
  *   info       NULL or an array of `batch` records: status, sweeps,
