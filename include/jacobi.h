@@ -87,7 +87,11 @@ typedef struct {
     int inner_max_sweeps; /* cap on inner scalar sweeps per subproblem; 0 = until
                              the subproblem's off-norm <= eps ||A_hat||_F (cap 30).
                              Default 1: the paper allows approximate
-                             diagonalisation of the subproblem (§3). */
+                             diagonalisation of the subproblem (§3).  eig: after
+                             30 sweeps without reaching tol, the remaining
+                             sweeps solve each subproblem to convergence
+                             (repeated eigenvalues converge only linearly with
+                             approximate inner solves). */
     int refine;           /* 1 = orthogonality refinement of Q/V (Newton-Schulz,
                              then a recomputed FP64 A = Q^T A0 Q or G = G0 V and
                              FP64 sweeps to tol); -1 = automatic (default: on

@@ -350,6 +350,22 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
     } else if (workBytes < p.total) {
         return -100;
     }
+    {
+        // a non-finite entry: status 2 before any sweep (the sweeps' largest
+        // relative cosine is a max that would pass over a NaN)
+        double *part = reinterpret_cast<double *>(ws + p.off_sigma);
+        double *out = reinterpret_cast<double *>(ws + p.off_meas);
+        launch_count_nonfinite(m, n, dG, ldg, part, out, s);
+        double bad = 0.0;
+        JX_HIP(hipMemcpyAsync(&bad, out, sizeof(double), hipMemcpyDeviceToHost, s));
+        JX_HIP(hipStreamSynchronize(s));
+        if (bad != 0.0) {
+            inf.status = 2;
+            inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (info) *info = inf;
+            return 2;
+        }
+    }
     if (p.qr) {
         const int rc = svd_qr(p, ws, dG, ldg, dS, dU, ldu, dV, ldv, o, inf, s);
         if (rc != QR_FALLBACK) {

@@ -271,9 +271,11 @@ void launch_scalar_rr(int n, int ne, const int *pairs, double *A, double *Q, dou
                       double *out, hipStream_t s);
 void launch_sym_full(int n, const double *src, int lds_, char uplo, double *dst, hipStream_t s);
 // one round of scalar Jacobi over n/2 workgroups (reads Acur, writes Anext,
-// updates Q's columns in place); rot (optional) += rotations of the round
+// updates Q's columns in place); rot (optional) += rotations of the round;
+// absolute mode rotates pairs with |a_pq| > skip, relative mode pairs with
+// |a_pq| > tol sqrt(|a_pp a_qq|)
 void launch_scalar_round(int n, int ne, const int *pairs_round, const double *Acur, double *Anext, double *Q,
-                         double tol, int relative, int *rot, hipStream_t s);
+                         double tol, int relative, double skip, int *rot, hipStream_t s);
 // out[0] = Xi(A)^2, out[1] = ||A||_F^2 (full n x n A, fixed order)
 void launch_scalar_norms(int n, const double *A, double *out, hipStream_t s);
 
@@ -310,6 +312,8 @@ void launch_unit_pad_diag(int n, int npad, double *W, int ldw, hipStream_t s);
 void launch_shift_diag(int n, double shift, double *W, int ldw, hipStream_t s);
 void launch_zero_lower(int npad, double *W, int ldw, hipStream_t s);
 void launch_diag_of(int n, const double *X, int ldx, double *out, hipStream_t s);
+// out[0] = number of non-finite entries of X (m x n, ldx); partial: n doubles
+void launch_count_nonfinite(int m, int n, const double *X, int ldx, double *partial, double *out, hipStream_t s);
 // X (npad x cols, ld npad): fixed pseudo-random values in [-1, 1) on the first n rows, zero below
 void launch_fill_probe(int n, int npad, int cols, double *X, hipStream_t s);
 // out[0] = ||Y - Z||_F^2 over m rows and `cols` columns (ld); partial: cols doubles

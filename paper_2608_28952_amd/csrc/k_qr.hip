@@ -194,7 +194,27 @@ __global__ void __launch_bounds__(256) k_diff_colsq(int m, const double *__restr
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// partial[j] = number of entries of column j (m rows) that are not finite.
+__global__ void __launch_bounds__(256) k_col_nonfinite(int m, const double *__restrict__ X, int ldx,
+                                                       double *__restrict__ partial) {
+    __shared__ double red[4];
+    const double *x = X + (size_t)blockIdx.x * ldx;
+    double c = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) c += (fabs(x[i]) <= 1.7976931348623157e308) ? 0.0 : 1.0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
 }  // namespace
+
+void launch_count_nonfinite(int m, int n, const double *X, int ldx, double *partial, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_col_nonfinite, dim3(n), dim3(256), 0, s, m, X, ldx, partial);
+    JX_LAUNCHED();
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, s, n, partial, out);
+    JX_LAUNCHED();
+}
 
 void launch_fill_probe(int n, int npad, int cols, double *X, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_probe, dim3((npad + 255) / 256, cols), dim3(256), 0, s, n, npad, cols, X);

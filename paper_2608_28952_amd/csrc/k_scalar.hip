@@ -41,6 +41,9 @@ __global__ void __launch_bounds__(SNT) k_scalar_rr(int n, int ne, const int *__r
     fro2 = block_sum<SNT>(fro2, red);
     off2 = block_sum<SNT>(off2, red);
     const double thr = tol * sqrt(fro2);
+    // absolute mode: a pair is rotated only when |a_pq| > tol ||A||_F /
+    // sqrt(n (n - 1)), so a sweep that rotates none meets the stop test
+    const double skip = thr / sqrt((double)n * (n - 1));
     int sweeps = 0;
     double rotated = 1.0;  // rotations of the last sweep (relative threshold)
     while (sweeps < max_sweeps && off2 == off2 && (relative ? rotated > 0.0 : sqrt(off2) > thr)) {
@@ -56,7 +59,7 @@ __global__ void __launch_bounds__(SNT) k_scalar_rr(int n, int ne, const int *__r
                     const double apq = A[(size_t)q * n + p], app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
                     // relative threshold (Demmel & Veselic): only couplings
                     // above tol sqrt(|a_pp a_qq|) are rotated
-                    if (!relative || fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+                    if (relative ? fabs(apq) > tol * sqrt(fabs(app * aqq)) : fabs(apq) > skip) {
                         rot_cst(app, aqq, apq, c, s, t);
                         t *= apq;
                         my_rot += (s != 0.0) ? 1.0 : 0.0;
@@ -140,11 +143,12 @@ __global__ void k_sym_full(int n, const double *__restrict__ src, int lds_, int 
 // J^T A J: rows rotated by pair k2, columns by pair k1 (its own block by the
 // closed form).  Q(:, [p1, q1]) <- Q(:, [p1, q1]) J_k1 in place (only this
 // workgroup touches those columns).  rot (optional): workgroup 0 adds the
-// number of rotations of the round.
+// number of rotations of the round.  Absolute mode rotates a pair only when
+// |a_pq| > skip; relative mode when |a_pq| > tol sqrt(|a_pp a_qq|).
 __global__ void __launch_bounds__(256) k_scalar_round(int n, int H, const int *__restrict__ pr,
                                                       const double *__restrict__ Acur, double *__restrict__ Anext,
                                                       double *__restrict__ Q, double tol, int relative,
-                                                      int *__restrict__ rot) {
+                                                      double skip, int *__restrict__ rot) {
     extern __shared__ double sm[];
     double *cs = sm, *sn = sm + H, *ta = sm + 2 * H, *cp = sm + 3 * H, *cq = cp + n;
     const int tid = threadIdx.x, k1 = blockIdx.x;
@@ -156,7 +160,7 @@ __global__ void __launch_bounds__(256) k_scalar_round(int n, int H, const int *_
         double c = 1.0, s = 0.0, t = 0.0;
         if (q < n) {
             const double apq = Acur[(size_t)q * n + p], app = Acur[(size_t)p * n + p], aqq = Acur[(size_t)q * n + q];
-            if (!relative || fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+            if (relative ? fabs(apq) > tol * sqrt(fabs(app * aqq)) : fabs(apq) > skip) {
                 rot_cst(app, aqq, apq, c, s, t);
                 t *= apq;
                 mine += (s != 0.0) ? 1 : 0;
@@ -230,11 +234,11 @@ __global__ void __launch_bounds__(1024) k_scalar_norms(int n, const double *__re
 }  // namespace
 
 void launch_scalar_round(int n, int ne, const int *pairs_round, const double *Acur, double *Anext, double *Q,
-                         double tol, int relative, int *rot, hipStream_t s) {
+                         double tol, int relative, double skip, int *rot, hipStream_t s) {
     const int H = ne / 2;
     const size_t lds = sizeof(double) * (3 * (size_t)H + 2 * (size_t)n);
     hipLaunchKernelGGL(k_scalar_round, dim3(H), dim3(256), lds, s, n, H, pairs_round, Acur, Anext, Q, tol, relative,
-                       rot);
+                       skip, rot);
     JX_LAUNCHED();
 }
 

@@ -238,10 +238,10 @@ def test_block_step_identity_rotation_is_exact(jx):
 # Full solver against the oracle
 # --------------------------------------------------------------------------
 
-def _check_against_oracle(A, W, Q, tol_eig=1e-12):
+def _check_against_oracle(A, W, Q, tol_eig=1e-12, ora_tol=1e-14):
     # the oracle's round-robin rounds, in parallel over a round's disjoint
     # rotations for the larger orders
-    ora = O.eig(A, order=1, nthreads=1 if A.shape[0] < 256 else min(16, os.cpu_count() or 1))
+    ora = O.eig(A, tol=ora_tol, order=1, nthreads=1 if A.shape[0] < 256 else min(16, os.cpu_count() or 1))
     assert ora.status == 0
     nrm = max(np.max(np.abs(ora.W)), 1e-300)
     assert np.max(np.abs(W - ora.W)) <= tol_eig * nrm, np.max(np.abs(W - ora.W)) / nrm
@@ -451,6 +451,42 @@ def test_eig_edge_cases(jx):
     A, _ = inputs.eig_uniform(300, 2)
     _, _, info = eig_gpu(jx, A, max_sweeps=1, check=False)
     assert info["status"] == 1 and info["sweeps"] == 1
+
+
+@pytest.mark.parametrize("block", [0, 1])
+def test_eig_degenerate_spectra(jx, block):
+    """Zero and identity matrices (every pair skipped: no sweep, W and Q
+    exact), and three clusters of exactly equal eigenvalues: A = H diag(lam)
+    H^T / 256 with H the Sylvester-Hadamard matrix of order 256 and lam in
+    {-1, 1/4, 2} is exact in FP64, so its spectrum is exactly lam (the
+    vectors of a cluster are not unique: eigenvalues against lam, residual
+    and orthogonality in long double)."""
+    import scipy.linalg as sl
+    n = 256
+    for A, lam in ((np.zeros((n, n)), 0.0), (np.eye(n), 1.0)):
+        W, Q, info = eig_gpu(jx, A, block=block)
+        assert info["status"] == 0 and info["sweeps"] == 0
+        assert np.all(W == lam) and np.array_equal(Q, np.eye(n))
+    H = sl.hadamard(n).astype(np.float64)
+    lam = np.repeat([-1.0, 0.25, 2.0], [80, 96, 80])[np.random.default_rng(3).permutation(n)]
+    A = np.asfortranarray((H * lam) @ H.T / n)
+    assert np.array_equal(A, A.T)
+    W, Q, info = eig_gpu(jx, A, block=block)
+    print(f"clusters block={block}: sweeps {info['sweeps']} status {info['status']}", flush=True)
+    assert info["status"] == 0
+    assert np.max(np.abs(W - np.sort(lam))) <= 1e-12 * 2.0
+    res, orth, _, _ = O.check_eig(A, W, Q)
+    assert res <= 1e-12 and orth <= 1e-12, (res, orth)
+
+
+def test_eig_scalar_b1_largest_order(jx):
+    """b = 1 at its largest order, n = 1024 (one launch per round over 512
+    workgroups), against the oracle."""
+    A, _ = inputs.eig_uniform(1024, 55)
+    W, Q, info = eig_gpu(jx, A, block=1)
+    print(f"scalar n=1024: sweeps {info['sweeps']}", flush=True)
+    assert info["status"] == 0
+    _check_against_oracle(A, W, Q)
 
 
 def test_eig_workspace_too_small(jx):

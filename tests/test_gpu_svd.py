@@ -192,6 +192,20 @@ def test_svd_edge_cases(jx):
     import torch
     with pytest.raises(Exception):
         jx.jacobi_svd(torch.zeros((3, 5), dtype=torch.float64, device="cuda"))
+    # the zero matrix (the QR preprocessing cannot factor it: the plain solve
+    # runs), with and without vectors
+    for wv in (1, 0):
+        S, U, V, info = svd_gpu(jx, np.zeros((300, 130)), want_vectors=wv)
+        assert info["status"] == 0 and np.all(S == 0.0)
+        if wv:
+            assert np.all(U == 0.0) and np.linalg.norm(V.T @ V - np.eye(130)) <= 1e-13
+    # n = 0, and a non-finite entry
+    S, U, V, info = jx.jacobi_svd(torch.zeros((7, 0), dtype=torch.float64, device="cuda"))
+    assert S.numel() == 0 and info["status"] == 0
+    G = rng.standard_normal((200, 64))
+    G[3, 5] = np.nan
+    _, _, _, info = svd_gpu(jx, G, check=False)
+    assert info["status"] == 2
 
 
 def test_svd_deterministic(jx):
