@@ -158,14 +158,20 @@ def test_batched_graph_cache_and_determinism(jx):
     jx.jacobi_eig_batched(sizes, offs, dA, opts=o, work=ws, out=(W, Q))
     W1, Q1 = W.clone(), Q.clone()
     h1, b1 = jx.batched_graph_stats()
-    W.fill_(0.0)
-    Q.fill_(0.0)
-    _, _, infos = jx.jacobi_eig_batched(sizes, offs, dA, opts=o, work=ws, out=(W, Q))
+    # three replays, with eager work on the same buffers and synchronisations
+    # between them: every replay equals the first call
+    for rep in range(3):
+        W.fill_(float(rep + 1))
+        Q.fill_(-float(rep + 1))
+        ws.fill_(0xA5)
+        torch.cuda.synchronize()
+        _, _, infos = jx.jacobi_eig_batched(sizes, offs, dA, opts=o, work=ws, out=(W, Q))
+        torch.cuda.synchronize()
+        assert all(i["status"] == 0 for i in infos)
+        assert torch.equal(W1, W) and torch.equal(Q1, Q), rep
     h2, b2 = jx.batched_graph_stats()
     assert b1 == b0 + 1 and b2 == b1            # built once
-    assert h2 == h1 + 1                          # then replayed
-    assert all(i["status"] == 0 for i in infos)
-    assert torch.equal(W1, W) and torch.equal(Q1, Q)
+    assert h2 == h1 + 3                          # then replayed
 
 
 def test_batched_warm_start_and_fallback(jx):
@@ -277,6 +283,35 @@ def test_batched_early_switch_level_matches_oracle(jx, tmp_path):
         assert infos[k]["status"] == 0
         A = packed[offs[k]:offs[k + 1]].astype(np.float64).reshape((n, n), order="F")
         check_against_oracle(A, Ws[k], Qs[k])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batched_degenerate_matrices(jx, precision):
+    """Zero and identity matrices (no sweep, exact results) and exactly
+    clustered spectra, A = H diag(lam) H^T / n with H Hadamard and lam in
+    {-1, 1/4, 2} (exact in FP64): every matrix converges, eigenvalues
+    within 1e-12 max|lam| of lam."""
+    import scipy.linalg as sl
+    mats = []
+    for n in (16, 64, 128):
+        H = sl.hadamard(n).astype(np.float64)
+        lam = np.repeat([-1.0, 0.25, 2.0], [n * 5 // 16, n * 6 // 16, n - n * 5 // 16 - n * 6 // 16])
+        lam = lam[np.random.default_rng(n).permutation(n)]
+        mats += [((H * lam) @ H.T / n, np.sort(lam)), (np.zeros((n, n)), np.zeros(n)), (np.eye(n), np.ones(n))]
+    sizes = np.array([A.shape[0] for A, _ in mats], dtype=np.int32)
+    offs = np.zeros(len(mats) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)
+    packed = np.concatenate([A.reshape(-1, order="F") for A, _ in mats])
+    prec = jx.PREC_MIXED_FP32 if precision == "mixed" else jx.PREC_FP64
+    (Ws, Qs), infos = run(jx, sizes, offs, packed, precision=prec)
+    for k, (A, lam) in enumerate(mats):
+        assert infos[k]["status"] == 0, (k, infos[k])
+        assert np.max(np.abs(Ws[k] - lam)) <= 1e-12 * 2.0
+        if k % 3:  # zero and identity: nothing to rotate
+            assert infos[k]["sweeps"] == 0 and np.array_equal(Qs[k], np.eye(A.shape[0]))
+        else:
+            res, orth, _, _ = O.check_eig(A, Ws[k], Qs[k])
+            assert res <= 1e-12 and orth <= 1e-12, (k, res, orth)
 
 
 def test_batched_full_workload_sampled(jx):
