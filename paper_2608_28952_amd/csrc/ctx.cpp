@@ -9,6 +9,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
+#include <utility>
 
 #include "jx_common.hpp"
 #include "jx_host.hpp"
@@ -39,6 +41,17 @@ DeviceCtx &device_ctx() {
     DeviceCtx &ref = *c;
     g_ctx[dev] = std::move(c);
     return ref;
+}
+
+void ensure_lds_limit(const void *func, int bytes) {
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    int dev = 0;
+    JX_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.count({dev, func})) return;
+    JX_HIP(hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    done.insert({dev, func});
 }
 
 }  // namespace jx

@@ -133,6 +133,10 @@ struct SubArgs {
     float *vout32;          // V_hat written in FP32, vperm32 order (instead of vout)
     int spin_limit;         // bound of the in-kernel hand-off waits (0: the default)
 };
+// Raises kernel `func`'s dynamic LDS limit to `bytes` on the current device,
+// once per (device, kernel); thread-safe (host code, ctx.cpp).
+void ensure_lds_limit(const void *func, int bytes);
+
 void launch_subproblem(const SubArgs &a, hipStream_t s);
 
 // Pivoting step (k_pivot.hip): per pair, LU with partial pivoting on the

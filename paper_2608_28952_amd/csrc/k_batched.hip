@@ -477,16 +477,11 @@ const void *class_kernel(bool lp) {
               : reinterpret_cast<const void *>(&k_batched_hp<BS, NPP>);
 }
 
-// Dynamic LDS above the default limit, set once per kernel (before any capture:
-// the occupancy query of the driver runs first).
+// Dynamic LDS above the default limit, set once per kernel and device (before
+// any capture: the occupancy query of the driver runs first).
 template <int BS, int NPP>
 void ensure_attr(bool lp) {
-    static bool done[2] = {false, false};
-    if (!done[lp]) {
-        JX_HIP(hipFuncSetAttribute(class_kernel<BS, NPP>(lp), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)KCfg<BS, NPP>::LDS));
-        done[lp] = true;
-    }
+    ensure_lds_limit(class_kernel<BS, NPP>(lp), (int)KCfg<BS, NPP>::LDS);
 }
 
 template <int BS, int NPP>

@@ -335,12 +335,7 @@ void family_matrices(int count, int n, int k, const double *theta, const double 
 void canonical_targets(int count, int n, const double *Q, const double *Qref, float *coords, int *keep,
                        double maxabs, hipStream_t s) {
     if (count <= 0) return;
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_canon),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)CANON_LDS));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_canon), (int)CANON_LDS);
     hipLaunchKernelGGL(k_canon, dim3(count), dim3(CNT), CANON_LDS, s, n, Q, Qref, coords, keep, maxabs);
     JX_LAUNCHED();
 }

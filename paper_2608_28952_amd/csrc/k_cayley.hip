@@ -140,12 +140,7 @@ void cayley_batched(int batch, int n, const double *S, const double *Qref, doubl
         return;
     }
     const size_t lds = sizeof(double) * ((size_t)n * 2 * n + (size_t)n * n);
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cayley), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(sizeof(double) * 3 * NMAX * NMAX)));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_cayley), (int)(sizeof(double) * 3 * NMAX * NMAX));
     hipLaunchKernelGGL(k_cayley, dim3(batch), dim3(NT), lds, s, n, S, Qref, Q0);
     JX_LAUNCHED();
 }

@@ -105,12 +105,7 @@ void launch_gemm_f64(char ta, char tb, int M, int N, int K, double alpha, const 
     }
     const int ita = (ta == 'T' || ta == 't'), itb = (tb == 'T' || tb == 't');
     constexpr size_t lds_bytes = sizeof(double) * 2 * GK * GLD;
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_gemm_f64),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_gemm_f64), (int)lds_bytes);
     hipLaunchKernelGGL(k_gemm_f64, dim3(M / GT, N / GT), dim3(256), lds_bytes, s, ita, itb, K, alpha, A, lda, B,
                        ldb, beta, C, ldc);
     JX_LAUNCHED();

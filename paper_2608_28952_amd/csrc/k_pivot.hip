@@ -259,12 +259,7 @@ __global__ void __launch_bounds__(PNT) k_pivot(PivotArgs a) {
 
 template <int M2>
 void launch_pivot_t(const PivotArgs &a, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pivot<M2>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)PivLds<M2>::BYTES));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_pivot<M2>), (int)PivLds<M2>::BYTES);
     hipLaunchKernelGGL(k_pivot<M2>, dim3(a.count), dim3(PNT), PivLds<M2>::BYTES, s, a);
     JX_LAUNCHED();
 }

@@ -242,12 +242,7 @@ void launch_dev_identity(int n, const double *X, int ldx, double *partial, doubl
 }
 
 void launch_chol_diag(double *W, int ldw, int k0, double *Rinv, int *flag, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol_diag),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)CHOL_LDS));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_chol_diag), (int)CHOL_LDS);
     hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(CNT), CHOL_LDS, s, W, ldw, k0, Rinv, flag);
     JX_LAUNCHED();
 }

@@ -715,12 +715,7 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
 template <int M2, int MODE>
 static void launch_sub_t(const SubArgs &a, hipStream_t s) {
     using C = SubCfg<M2>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_subproblem<M2, MODE>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS_BYTES));
-        attr_set = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_subproblem<M2, MODE>), (int)C::LDS_BYTES);
     hipLaunchKernelGGL((k_subproblem<M2, MODE>), dim3(a.count), dim3(C::NT), C::LDS_BYTES, s, a);
     JX_LAUNCHED();
 }
@@ -739,12 +734,7 @@ template <int MODE>
 static void launch_sub2_t(const SubArgs &a0, hipStream_t s) {
     SubArgs a = a0;
     if (a.spin_limit <= 0) a.spin_limit = handoff_spin();
-    static bool attr_set = false;
-    if (!attr_set) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_subproblem2<MODE>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tl::LDS_BYTES));
-        attr_set = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_subproblem2<MODE>), (int)tl::LDS_BYTES);
     hipLaunchKernelGGL((k_subproblem2<MODE>), dim3(a.count), dim3(tl::NT), tl::LDS_BYTES, s, a);
     JX_LAUNCHED();
 }

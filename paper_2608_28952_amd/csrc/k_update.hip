@@ -796,12 +796,7 @@ void launch_uaq(int b, int npairs, const int *pairs, T *ablk, const T *vhat, con
         throw HipFail{hipErrorInvalidValue};
     }
     const size_t lds = std::max<size_t>(UaCfg<64, 512>::LDS_BYTES, 81 * 1024);
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_aq_bounded<T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_update_aq_bounded<T>), (int)lds);
     const int nrb = n_rows / 128, nqw = Q ? nrb * npairs : 0;
     const int nwork = std::max(ntiles, 0) + nqw;
     if (nwork <= 0) return;
@@ -821,12 +816,7 @@ void launch_ua_bounded(const int *pairs, T *ablk, const T *vhat, const int *flag
     size_t need = 2 * UaCfg<B>::LDS_BYTES;
     if constexpr (B == 64) need = UaCfg<B, 512>::LDS_BYTES;
     const size_t lds = std::max<size_t>(need, 81 * 1024);
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a_bounded<B, T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_update_a_bounded<B, T>), (int)lds);
     const int grid = std::max(1, std::min(device_cus() - reserve, B == 64 ? ntiles : (ntiles + 1) / 2));
     hipLaunchKernelGGL((k_update_a_bounded<B, T>), dim3(grid), dim3(512), lds, s, pairs, ablk, vhat, flags, tiles,
                        ntiles, qmask, nq, side, snext, smap);
@@ -842,12 +832,7 @@ void launch_ua_crit(const int *pairs, T *ablk, const T *vhat, const int *flags, 
     size_t need = U::LDS_BYTES;
     if constexpr (B == 64) need = std::max(need, sizeof(T) * 128 * 129);
     const size_t lds = std::max<size_t>(need, 81 * 1024);
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_a_crit<B, T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_update_a_crit<B, T>), (int)lds);
     const int ns = B == 64 ? CRIT_SPLIT : 1;
     hipLaunchKernelGGL((k_update_a_crit<B, T>), dim3(ntiles * ns), dim3(512), lds, s, pairs, ablk, vhat, flags,
                        tiles, qmask, side);
@@ -899,12 +884,7 @@ int device_cus() {
 template <int B, class T>
 void launch_uq_bounded(int npairs, const int *pairs, T *Q, int ldq, int n_rows, const T *vhat, const int *flags,
                        int reserve, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        JX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_update_q_bounded<B, T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)UQ_BOUNDED_LDS));
-        attr = true;
-    }
+    ensure_lds_limit(reinterpret_cast<const void *>(&k_update_q_bounded<B, T>), (int)UQ_BOUNDED_LDS);
     const int nrb = n_rows / 128, nwork = nrb * npairs;
     const int grid = std::max(1, std::min(device_cus() - reserve, nwork));
     hipLaunchKernelGGL((k_update_q_bounded<B, T>), dim3(grid), dim3(512), UQ_BOUNDED_LDS, s, pairs, Q, ldq, vhat,
