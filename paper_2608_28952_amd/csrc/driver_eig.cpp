@@ -117,6 +117,10 @@ static int default_block(int n) { return n > 512 ? 64 : 32; }
 
 // Sweeps after which the subproblems are solved to convergence (see phase()).
 constexpr int INNER_ESCALATE = 30;
+// Relative off-norm at which the FP64 path refines Q inside the quadratic
+// phase, and the sweeps after it that still count as that phase (run_eig).
+constexpr double EARLY_REFINE = 1e-6;
+constexpr int EARLY_REFINE_SWEEPS = 4;
 
 // V_hat / flag buffers of consecutive rounds (see EigState)
 constexpr int NVBUF = 3;
@@ -671,6 +675,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
         launch_pack_sym(np, np, p.b, T2, np, 'U', st.ablk, s);
         st.norms(off2, dia2);
     };
+    bool early_refined = false;
     if (status != 2) {
         if (p.mixed) {
             // FP32 sweeps (subproblems still solved in FP64) to off <= 1e-5 or stagnation
@@ -686,6 +691,21 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
                 recompute();
                 status = phase(tol, o.max_sweeps + 8);
             }
+        } else if (p.refine) {
+            // The refinement inside the quadratic phase: once Xi(A) <=
+            // EARLY_REFINE ||A||_F, Q is refined and A_1 = Q^T A_0 Q recomputed,
+            // then the sweeps finish.  The recomputed A_1 carries rounding of
+            // about n u ||A||_F (1.8e-13 at n = 4096), above tol, so a
+            // refinement after convergence costs one more full sweep; here
+            // the quadratic tail absorbs it.  If more than EARLY_REFINE_SWEEPS
+            // sweeps follow, the refinement is repeated at the end.
+            status = phase(std::max(tol, EARLY_REFINE), o.max_sweeps);
+            if (status == 0 && fro0 > 0.0 && std::sqrt(off2) > tol * fro0) {
+                const int before = sweeps;
+                recompute();
+                status = phase(tol, o.max_sweeps + 12);
+                early_refined = status == 0 && sweeps - before <= EARLY_REFINE_SWEEPS;
+            }
         } else {
             status = phase(tol, o.max_sweeps);
         }
@@ -693,7 +713,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
         // the size of Q's orthogonality error and mostly skip.  Below order
         // 256 with the automatic setting, Q's orthogonality is measured first
         // (||Q^T Q - I||_F from one GEMM) and refined only above 2e-13.
-        bool refine_now = status == 0 && p.refine;
+        bool refine_now = status == 0 && p.refine && !early_refined;
         if (status == 0 && !p.refine && p.vectors && o.refine < 0 && p.temps) {
             const int np = p.npad;
             gemm_p('T', 'N', np, np, np, 1.0, st.Q, np, st.Q, np, 0.0, T1, np, s);
