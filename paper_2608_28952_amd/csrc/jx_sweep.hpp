@@ -91,11 +91,13 @@ __device__ __forceinline__ double block_sum(double x, double *red) {
 }
 
 // Orders the LDS accesses of one wave (stores of some lanes, loads of others):
-// waits for the wave's outstanding LDS operations, and nothing moves across.
+// nothing moves across.  Wavefront-scope fences: a wave's LDS operations are
+// performed in issue order, so no wait for outstanding operations is needed
+// (the compiler emits none at this scope).
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <bool WAVE>
@@ -293,6 +295,18 @@ __device__ __forceinline__ void lds_wait_geq(int *p, int v, int *fail, int spin)
     }
     lds_store_release(fail, 1);
 }
+// The same wait with the last value read kept in `seen`: no load while that
+// value already satisfies it (the counter only grows, and the acquire that
+// read it orders everything after it).
+__device__ __forceinline__ void lds_wait_geq_seen(int *p, int v, int &seen, int *fail, int spin) {
+    if (seen >= v) return;
+    for (int it = 0; it < spin; ++it) {
+        seen = lds_load_acquire(p);
+        if (seen >= v) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    lds_store_release(fail, 1);
+}
 
 // ---------------------------------------------------------------------------
 // Round-robin scalar Jacobi on an m2 x m2 matrix held in LDS (slot order)
@@ -318,13 +332,14 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
         for (int x = 0; x < P; ++x) V[x] = (r == P * g + x) ? 1.0 : 0.0;
     }
 
+    int vseen = -(1 << 30);  // last follower count read (VOUT)
     // parameters of the first round
     if (tid < H) {
         const int up = slot_p(tid, 0, M2), uq = slot_q(tid, 0, M2);
         rot_params(As[up * (LD + 1)], As[uq * (LD + 1)], As[min(up, uq) * LD + max(up, uq)], prm0, tid, H);
         if constexpr (VOUT) {
             double *rb = vr.ring + (vr.base & (VR_DEPTH - 1)) * 2 * H;
-            lds_wait_geq(vr.vdone, vr.base + 1 - VR_DEPTH, vr.fail, vr.spin);
+            lds_wait_geq_seen(vr.vdone, vr.base + 1 - VR_DEPTH, vseen, vr.fail, vr.spin);
             rb[tid] = prm0[tid];
             rb[H + tid] = prm0[H + tid];
         }
@@ -443,6 +458,12 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                 vc[j] = VOUT ? 0.0 : pc[(P / 2) * g + j];
                 vs[j] = VOUT ? 0.0 : pc[H + (P / 2) * g + j];
             }
+            // rounds <= t are in the ring (the previous round's stores are
+            // complete once this round's loads are: the release waits for
+            // nothing the rotation below would not wait for)
+            if constexpr (VOUT) {
+                if (t > 0) lds_store_release(vr.sdone, vr.base + t + 1);
+            }
 
             // ---- rotate the pair-blocks: left rows p1, q1; right columns p2, q2
             double piv = 0.0;
@@ -489,7 +510,7 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                     if constexpr (VOUT) {  // next round's slot, once the follower is done with it
                         const int nr = vr.base + t + 1;
                         double *const rd = ok ? vr.ring + (nr & (VR_DEPTH - 1)) * 2 * H + kn : As + dum;
-                        lds_wait_geq(vr.vdone, nr + 1 - VR_DEPTH, vr.fail, vr.spin);
+                        lds_wait_geq_seen(vr.vdone, nr + 1 - VR_DEPTH, vseen, vr.fail, vr.spin);
                         rd[0] = cn;
                         rd[ok ? H : 0] = sn;
                     }
@@ -528,9 +549,9 @@ __device__ void scalar_sweeps(double *As, double *prm0, double *red, int tid, in
                 if (g == 0) V[0] = e0;
             }
             group_sync<WAVE>();
-            // rounds <= t + 1 are in the ring; the last round's "next" parameters
-            // are not (the next sweep writes its round 0 itself)
-            if constexpr (VOUT) lds_store_release(vr.sdone, vr.base + min(t + 2, R));
+            // (the next round publishes this round's ring slot; the last
+            // round's "next" parameters are not published: the next sweep
+            // writes its round 0 itself)
         }
         // end of sweep: clear the last round's pivots (the diagonal is current)
         if (tid < H) {

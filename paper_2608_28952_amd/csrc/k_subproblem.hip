@@ -244,14 +244,21 @@ __device__ __forceinline__ int cross_q(int k, int sh) { return 16 + ((k + sh) & 
 __device__ __forceinline__ int cross_at(int a, int b) { return 32 * (a < b ? a : b) + ((a + b) & 31); }
 __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
     constexpr int H = 16, NI = 120;
-    // parameters of round 0: pivots (k, 16 + k)
+    int vseen = -(1 << 30);  // last follower count read
+    // parameters of round 0: pivots (k, 16 + k); the ring gets (c, s) from
+    // registers (a load after the acquiring wait could not be forwarded)
     if (lane < H) {
         const int p = lane, q = cross_q(lane, 0);
-        rot_params(S[cross_at(p, p)], S[cross_at(q, q)], S[cross_at(p, q)], prm, lane, H);
+        const double apq = S[cross_at(p, q)];
+        double c, s, t;
+        rot_cst(S[cross_at(p, p)], S[cross_at(q, q)], apq, c, s, t);
+        prm[lane] = c;
+        prm[H + lane] = s;
+        prm[2 * H + lane] = t * apq;
         double *rb = vr.ring + (vr.base & (VR_DEPTH - 1)) * 2 * H;
-        lds_wait_geq(vr.vdone, vr.base + 1 - VR_DEPTH, vr.fail, vr.spin);
-        rb[lane] = prm[lane];
-        rb[H + lane] = prm[H + lane];
+        lds_wait_geq_seen(vr.vdone, vr.base + 1 - VR_DEPTH, vseen, vr.fail, vr.spin);
+        rb[lane] = c;
+        rb[H + lane] = s;
     }
     wave_lds_sync();
     lds_store_release(vr.sdone, vr.base + 1);
@@ -304,6 +311,9 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
             nv[ii][2] = c2 * r10 - s2 * r11;
             nv[ii][3] = s2 * r10 + c2 * r11;
         }
+        // the previous round's parameters are in the ring (its stores are
+        // complete once this round's loads are)
+        if (sh > 0) lds_store_release(vr.sdone, vr.base + sh + 1);
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
             if (!ok[ii]) continue;
@@ -320,16 +330,20 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
             S[cross_at(lane, cross_q(lane, sh))] = 0.0;  // this round's pivot (no item holds it)
             if (sh + 1 < H) {
                 const double apq = lane < 15 ? nv[0][1] : nv[0][2];
-                rot_params(app, aqq, apq, nxt, lane, H);
+                double c, s, t;
+                rot_cst(app, aqq, apq, c, s, t);
+                nxt[lane] = c;
+                nxt[H + lane] = s;
+                nxt[2 * H + lane] = t * apq;
                 const int n = vr.base + sh + 1;
                 double *rb = vr.ring + (n & (VR_DEPTH - 1)) * 2 * H;
-                lds_wait_geq(vr.vdone, n + 1 - VR_DEPTH, vr.fail, vr.spin);
-                rb[lane] = nxt[lane];
-                rb[H + lane] = nxt[H + lane];
+                lds_wait_geq_seen(vr.vdone, n + 1 - VR_DEPTH, vseen, vr.fail, vr.spin);
+                rb[lane] = c;
+                rb[H + lane] = s;
             }
         }
         wave_lds_sync();
-        if (sh + 1 < H) lds_store_release(vr.sdone, vr.base + sh + 2);
+        // (the next round publishes this round's ring slot)
     }
 }
 
