@@ -117,10 +117,20 @@ static int default_block(int n) { return n > 512 ? 64 : 32; }
 
 // Sweeps after which the subproblems are solved to convergence (see phase()).
 constexpr int INNER_ESCALATE = 30;
-// Relative off-norm at which the FP64 path refines Q inside the quadratic
-// phase, and the sweeps after it that still count as that phase (run_eig).
-constexpr double EARLY_REFINE = 1e-6;
-constexpr int EARLY_REFINE_SWEEPS = 4;
+// Relative off-norm at which the FP64 sweeps refine Q inside the quadratic
+// phase (run_eig): low enough that one sweep usually follows (as after a
+// refinement at convergence, so Q keeps that orthogonality), high enough
+// that this sweep is one the solve needs anyway.  More than
+// EARLY_REFINE_SWEEPS sweeps after it, and the refinement is repeated at
+// the end.
+constexpr double EARLY_REFINE = 1e-8;
+constexpr int EARLY_REFINE_SWEEPS = 2;
+// The refinement is moved into the quadratic phase only when the last sweep
+// cut the off-norm by this factor: under linear convergence (clusters of
+// equal eigenvalues) more sweeps remain, and the refinement waits for the
+// end (an exactly clustered spectrum at n = 256, refined early at 4e-9 in a
+// run of 0.4x decreases, stalled near 7e-11 for 50 sweeps).
+constexpr double EARLY_REFINE_DROP = 1e-2;
 
 // V_hat / flag buffers of consecutive rounds (see EigState)
 constexpr int NVBUF = 3;
@@ -629,8 +639,10 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     const bool verbose = std::getenv("JACOBI_VERBOSE") != nullptr;
     // Sweeps until Xi(A) <= stop * ||A||_F.  Returns 0 (reached), 1 (cap),
     // 2 (non-finite), 4 (FP32 phase slows down: less than 2x decrease per sweep
-    // below 1e-3).
-    auto phase = [&](double stop, int cap) -> int {
+    // below 1e-3), 5 (early > 0: the quadratic phase has reached
+    // Xi(A) <= early ||A||_F, the last sweep having cut the off-norm by at
+    // least EARLY_REFINE_DROP).
+    auto phase = [&](double stop, int cap, double early = 0.0) -> int {
         double prev = -1.0;
         for (;;) {
             if (verbose)
@@ -639,6 +651,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             if (!finite(off2) || !finite(dia2)) return 2;
             const double rel = fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0;
             if (rel <= stop) return 0;
+            if (early > 0.0 && prev > 0.0 && rel <= early && rel <= EARLY_REFINE_DROP * prev) return 5;
             // End of the FP32 phase once a sweep no longer halves the off-norm.
             // Slow convergence here means eigenvalues close together or near
             // FP32 resolution, which the FP64 phase must resolve anyway: on a
@@ -676,6 +689,32 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
         st.norms(off2, dia2);
     };
     bool early_refined = false;
+    // Sweeps to tol with the orthogonality refinement inside the quadratic
+    // phase: once Xi(A) <= EARLY_REFINE ||A||_F after a sweep that cut it by
+    // EARLY_REFINE_DROP, Q is refined and A_1 = Q^T A_0 Q recomputed, then
+    // the sweeps finish.  The recomputed A_1
+    // carries rounding of about n u ||A||_F (1.8e-13 at n = 4096), above tol,
+    // so a refinement after convergence costs one more full sweep; here the
+    // last sweep of the quadratic phase absorbs it.  If more than
+    // EARLY_REFINE_SWEEPS sweeps follow, the refinement is repeated at the
+    // end.  `fresh`: A_1 has just
+    // been recomputed (the precision switch); already in the quadratic phase,
+    // that recomputation is the refinement.
+    auto to_tol = [&](int cap, bool fresh) {
+        const int s0 = sweeps;
+        if (fresh && fro0 > 0.0 && std::sqrt(off2) <= EARLY_REFINE * fro0) {
+            status = phase(tol, cap);
+            early_refined = status == 0 && sweeps - s0 <= EARLY_REFINE_SWEEPS;
+            return;
+        }
+        status = phase(tol, cap, EARLY_REFINE);
+        if (status == 5) {
+            const int before = sweeps;
+            recompute();
+            status = phase(tol, cap + 12);
+            early_refined = status == 0 && sweeps - before <= EARLY_REFINE_SWEEPS;
+        }
+    };
     if (status != 2) {
         if (p.mixed) {
             // FP32 sweeps (subproblems still solved in FP64) to off <= 1e-5 or stagnation
@@ -689,23 +728,10 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             if (status != 2) {
                 launch_cast_to_f64((size_t)p.npad * p.npad, st.Q32, st.Q, s);
                 recompute();
-                status = phase(tol, o.max_sweeps + 8);
+                to_tol(o.max_sweeps + 8, true);
             }
         } else if (p.refine) {
-            // The refinement inside the quadratic phase: once Xi(A) <=
-            // EARLY_REFINE ||A||_F, Q is refined and A_1 = Q^T A_0 Q recomputed,
-            // then the sweeps finish.  The recomputed A_1 carries rounding of
-            // about n u ||A||_F (1.8e-13 at n = 4096), above tol, so a
-            // refinement after convergence costs one more full sweep; here
-            // the quadratic tail absorbs it.  If more than EARLY_REFINE_SWEEPS
-            // sweeps follow, the refinement is repeated at the end.
-            status = phase(std::max(tol, EARLY_REFINE), o.max_sweeps);
-            if (status == 0 && fro0 > 0.0 && std::sqrt(off2) > tol * fro0) {
-                const int before = sweeps;
-                recompute();
-                status = phase(tol, o.max_sweeps + 12);
-                early_refined = status == 0 && sweeps - before <= EARLY_REFINE_SWEEPS;
-            }
+            to_tol(o.max_sweeps, false);
         } else {
             status = phase(tol, o.max_sweeps);
         }
