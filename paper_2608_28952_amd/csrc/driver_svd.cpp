@@ -24,6 +24,11 @@
 
 namespace jx {
 
+// Largest relative cosine at which the SVD sweeps refine V inside the
+// quadratic phase, and the decrease the last sweep must show (run_svd).
+constexpr double EARLY_REFINE_COS = 1e-6;
+constexpr double EARLY_REFINE_DROP = 1e-2;
+
 static int svd_block(int n) { return n > 512 ? 64 : 32; }
 
 SvdPlan plan_svd(int m, int n, const jacobi_opts &o) {
@@ -507,8 +512,10 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
     };
     // Sweeps until a sweep rotates no pair (stop <= 0) or the largest relative
     // cosine drops to stop.  Returns 0, 1 (cap), 2 (non-finite), 4 (the FP32
-    // phase stagnates or has no more to gain).
-    auto phase = [&](double stop, int cap) -> int {
+    // phase stagnates or has no more to gain), 5 (early > 0: a sweep in the
+    // quadratic phase left the largest cosine at or below early, having cut
+    // it by at least EARLY_REFINE_DROP).
+    auto phase = [&](double stop, int cap, double early = 0.0) -> int {
         double prev = -1.0;
         for (;;) {
             if (sweeps >= cap) return 1;
@@ -517,6 +524,7 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
             if (f32) ++sweeps32;
             if (!std::isfinite(last_meas)) return 2;
             if (rot == 0 || (stop > 0.0 && last_meas <= stop)) return 0;
+            if (early > 0.0 && prev > 0.0 && last_meas <= early && last_meas <= EARLY_REFINE_DROP * prev) return 5;
             if (f32 && prev >= 0.0 && last_meas < 1e-3 && last_meas > 0.5 * prev) return 4;
             // V from the FP32 phase is accurate to about u32 = 2^-24, so G0 V
             // gives the columns of the smallest singular values cosines of
@@ -527,16 +535,39 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
             prev = last_meas;
         }
     };
-    // V <- V (3 I - V^T V) / 2, G = G0 V in FP64 from the original
-    auto recompute = [&]() {
+    // V <- V (3 I - V^T V) / 2 (ns times), G = G0 V in FP64 from the original.
+    // After the FP32 phase V is orthogonal to about 1e-6; one step leaves
+    // 1e-12, which G0 V turns into cosines of about cond(G) 1e-12 (1.4e-6 at
+    // cond = 1e6, in the way of the later refinement), so the switch takes two.
+    auto recompute = [&](int ns) {
         const int np = p.npad;
-        launch_gemm_f64('T', 'N', np, np, np, 1.0, V, np, V, np, 0.0, T1, np, s);
-        JX_HIP(hipMemcpyAsync(T2, V, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
-        launch_gemm_f64('N', 'N', np, np, np, -0.5, V, np, T1, np, 1.5, T2, np, s);
-        JX_HIP(hipMemcpyAsync(V, T2, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
+        for (int k = 0; k < ns; ++k) {
+            launch_gemm_f64('T', 'N', np, np, np, 1.0, V, np, V, np, 0.0, T1, np, s);
+            JX_HIP(hipMemcpyAsync(T2, V, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
+            launch_gemm_f64('N', 'N', np, np, np, -0.5, V, np, T1, np, 1.5, T2, np, s);
+            JX_HIP(hipMemcpyAsync(V, T2, sizeof(double) * (size_t)np * np, hipMemcpyDeviceToDevice, s));
+        }
         launch_gemm_f64('N', 'N', p.mpad, np, np, 1.0, G0, p.mpad, V, np, 0.0, G, p.mpad, s);
     };
     const double switch_cos = 1e-5;
+    // Sweeps to convergence with the refinement inside the quadratic phase.
+    // Convergence is a sweep that rotates no pair; refined after it, the
+    // recomputed G = G0 V carries cosines of rounding size above tol, which
+    // take one more rotating sweep and one more check sweep.  Refined once a
+    // sweep has left the largest cosine at or below EARLY_REFINE_COS (and cut
+    // it by 100x: the quadratic phase), the sweep that finishes the
+    // convergence also absorbs that rounding.  If more than two sweeps
+    // follow, the refinement is repeated at the end.
+    bool early_refined = false;
+    auto to_conv = [&](int cap) {
+        status = phase(0.0, cap, p.refine ? EARLY_REFINE_COS : 0.0);
+        if (status == 5) {
+            const int before = sweeps;
+            recompute(1);
+            status = phase(0.0, cap + 12);
+            early_refined = status == 0 && sweeps - before <= 2;
+        }
+    };
     if (p.mixed) {
         launch_cast_to_f32((size_t)p.mpad * p.npad, G, G32, s);
         launch_set_identity32(p.npad, V32, p.npad, s);
@@ -545,14 +576,14 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
         f32 = false;
         if (status != 2) {
             launch_cast_to_f64((size_t)p.npad * p.npad, V32, V, s);
-            recompute();
-            status = phase(0.0, o.max_sweeps + 8);
+            recompute(2);
+            to_conv(o.max_sweeps + 8);
         }
     } else {
-        status = phase(0.0, o.max_sweeps);
+        to_conv(o.max_sweeps);
     }
-    if (status == 0 && p.refine) {
-        recompute();
+    if (status == 0 && p.refine && !early_refined) {
+        recompute(1);
         status = phase(0.0, o.max_sweeps + 12);
     }
     if (status != 2) {
