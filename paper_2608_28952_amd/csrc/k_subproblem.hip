@@ -598,30 +598,44 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
         // Vt rows of block pair k <- W_k^T (those rows), then the tiles follow
         // the block ring: 1 <- 2 <- 4 <- 6 <- 7 <- 5 <- 3 <- 1.  Every W read is
         // one lane base plus a constant (no per-address registers).
+        // nz: bit 2 tt + j is set when tile vt[tt][j] may be nonzero (wave-
+        // uniform).  Vt starts as the identity (tiles (2c, 0) and (2c + 1, 1))
+        // and fills in over the first block rounds: the products with tiles
+        // known to be zero are skipped (a third of the MFMAs of one inner
+        // sweep, all in its first four block rounds).
         const double *Wl = Ap + AP + WOFF + g * 33 + x;
+        const int cu = __builtin_amdgcn_readfirstlane(c);
+        int nz = (1 << (4 * cu)) | (1 << (4 * cu + 3));
         auto apply = [&]() {
+            int nzn = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const double *Wk = Wl + k * SW;
                 d4 n0[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
                 d4 n1[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
+                for (int ti = 0; ti < 2; ++ti) {
+                    const int tb = (nz >> (2 * (2 * k + ti))) & 3;  // column tiles j of vt[2k + ti] in use
+                    if (tb == 0) continue;
 #pragma unroll
                     for (int s4 = 0; s4 < 4; ++s4) {
                         const int rr = 16 * ti + 4 * s4;  // + g (in Wl)
                         const double a0 = Wk[rr * 33], a1 = Wk[rr * 33 + 16];
 #pragma unroll
                         for (int j = 0; j < 2; ++j) {
+                            if (!((tb >> j) & 1)) continue;
                             n0[j] = mfma_f64(a0, vt[2 * k + ti][j][s4], n0[j]);
                             n1[j] = mfma_f64(a1, vt[2 * k + ti][j][s4], n1[j]);
                         }
                     }
+                }
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     vt[2 * k][j] = n0[j];
                     vt[2 * k + 1][j] = n1[j];
                 }
+                const int pb = ((nz >> (4 * k)) | (nz >> (4 * k + 2))) & 3;
+                nzn |= (pb | pb << 2) << (4 * k);
                 // keep the next pair's W loads from being hoisted over this
                 // one (Vt already holds half the register file)
                 __builtin_amdgcn_sched_barrier(0);
@@ -637,6 +651,8 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
                 vt[5][j] = vt[3][j];
                 vt[3][j] = o1;
             }
+            auto tb = [&](int tt) { return (nzn >> (2 * tt)) & 3; };
+            nz = tb(0) | tb(2) << 2 | tb(4) << 4 | tb(1) << 6 | tb(6) << 8 | tb(3) << 10 | tb(7) << 12 | tb(5) << 14;
         };
         // The same barriers and sweep decisions as the solver role; apply()
         // appears once (two inlined copies cost the register allocator its Vt).
