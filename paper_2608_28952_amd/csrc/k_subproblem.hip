@@ -414,19 +414,21 @@ __global__ void __launch_bounds__(512) k_subproblem2(SubArgs a) {
     {
         // the upper triangle of A_hat, column-major positions e = c M2 + r (a
         // wave's 64 positions share a column half: one source block per
-        // wave), eight loads in flight per thread before their LDS stores
+        // wave), all 32 of a thread's loads in flight before their LDS
+        // stores (the three source blocks come from other CUs' writes: 8 at a
+        // time cost about 0.5 % of the n = 4096 solve)
         const HatSource<M2, MODE> load(a, pr);
-#pragma unroll 1
-        for (int e0 = 0; e0 < M2 * M2; e0 += 8 * NT) {
-            double v[8];
+        constexpr int PER = M2 * M2 / NT;
+        {
+            double v[PER];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * NT + tid, r = e % M2, c = e / M2;
+            for (int u = 0; u < PER; ++u) {
+                const int e = u * NT + tid, r = e % M2, c = e / M2;
                 v[u] = r <= c ? load(r, c) : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * NT + tid, r = e % M2, c = e / M2;
+            for (int u = 0; u < PER; ++u) {
+                const int e = u * NT + tid, r = e % M2, c = e / M2;
                 if (r <= c) {
                     Ap[pk(r, c)] = v[u];
                     const double w2 = v[u] * v[u];
