@@ -96,7 +96,13 @@ typedef struct {
                              then a recomputed FP64 A = Q^T A0 Q or G = G0 V and
                              FP64 sweeps to tol); -1 = automatic (default: on
                              for n >= 256 -- eig: with eigenvectors -- and in
-                             mixed precision) */
+                             mixed precision).  Blocked eig and svd refine
+                             inside the quadratic phase (after the first sweep
+                             that leaves off(A) <= 1e-8 ||A||_F, or the largest
+                             cosine <= 1e-6, having cut it by 100x), so that
+                             the sweep that finishes also absorbs the
+                             recomputation's rounding; again at the end if
+                             more than two sweeps follow */
     int sort;             /* 1 = eigenvalues ascending / sigma descending (default) */
     int want_vectors;     /* 0 = eigenvalues (singular values) only; default 1 */
     int threshold;        /* eig with block = 1: 0 = absolute stop test above
