@@ -651,7 +651,6 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             if (!finite(off2) || !finite(dia2)) return 2;
             const double rel = fro0 > 0 ? std::sqrt(off2) / fro0 : 0.0;
             if (rel <= stop) return 0;
-            if (early > 0.0 && prev > 0.0 && rel <= early && rel <= EARLY_REFINE_DROP * prev) return 5;
             // End of the FP32 phase once a sweep no longer halves the off-norm.
             // Slow convergence here means eigenvalues close together or near
             // FP32 resolution, which the FP64 phase must resolve anyway: on a
@@ -660,6 +659,7 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
             // plain FP64 needs 8 from that point: 30 sweeps in all against 27.
             if (st.f32 && prev >= 0.0 && rel < 1e-3 && rel > 0.5 * prev) return 4;
             if (sweeps >= cap) return 1;
+            if (early > 0.0 && prev > 0.0 && rel <= early && rel <= EARLY_REFINE_DROP * prev) return 5;
             prev = rel;
             // Approximate inner solves converge only linearly on (nearly)
             // repeated eigenvalues: an exactly clustered spectrum took 53-56
@@ -691,15 +691,14 @@ int run_eig(int n, const double *dA, int lda, char uplo, double *dW, double *dQ,
     bool early_refined = false;
     // Sweeps to tol with the orthogonality refinement inside the quadratic
     // phase: once Xi(A) <= EARLY_REFINE ||A||_F after a sweep that cut it by
-    // EARLY_REFINE_DROP, Q is refined and A_1 = Q^T A_0 Q recomputed, then
-    // the sweeps finish.  The recomputed A_1
+    // EARLY_REFINE_DROP (and before the sweep cap), Q is refined and A_1 =
+    // Q^T A_0 Q recomputed, then the sweeps finish.  The recomputed A_1
     // carries rounding of about n u ||A||_F (1.8e-13 at n = 4096), above tol,
     // so a refinement after convergence costs one more full sweep; here the
     // last sweep of the quadratic phase absorbs it.  If more than
     // EARLY_REFINE_SWEEPS sweeps follow, the refinement is repeated at the
-    // end.  `fresh`: A_1 has just
-    // been recomputed (the precision switch); already in the quadratic phase,
-    // that recomputation is the refinement.
+    // end.  `fresh`: A_1 has just been recomputed (the precision switch);
+    // already in the quadratic phase, that recomputation is the refinement.
     auto to_tol = [&](int cap, bool fresh) {
         const int s0 = sweeps;
         if (fresh && fro0 > 0.0 && std::sqrt(off2) <= EARLY_REFINE * fro0) {

@@ -524,7 +524,9 @@ int run_svd(int m, int n, const double *dG, int ldg, double *dS, double *dU, int
             if (f32) ++sweeps32;
             if (!std::isfinite(last_meas)) return 2;
             if (rot == 0 || (stop > 0.0 && last_meas <= stop)) return 0;
-            if (early > 0.0 && prev > 0.0 && last_meas <= early && last_meas <= EARLY_REFINE_DROP * prev) return 5;
+            if (early > 0.0 && prev > 0.0 && sweeps < cap && last_meas <= early &&
+                last_meas <= EARLY_REFINE_DROP * prev)
+                return 5;
             if (f32 && prev >= 0.0 && last_meas < 1e-3 && last_meas > 0.5 * prev) return 4;
             // V from the FP32 phase is accurate to about u32 = 2^-24, so G0 V
             // gives the columns of the smallest singular values cosines of

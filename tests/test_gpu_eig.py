@@ -397,6 +397,23 @@ def test_eig_graded_512_relative_accuracy(jx):
     assert res <= 1e-12 and orth <= 1e-12
 
 
+def test_eig_sweep_cap_with_refinement(jx):
+    """opts.max_sweeps bounds the sweeps to convergence also when the
+    orthogonality refinement runs inside the quadratic phase: one sweep
+    short of what the full solve needs, the solve stops at the cap with
+    status 1 (not converged) instead of refining and sweeping on."""
+    n = 1024
+    A, lam = inputs.eig_graded(n, 11)
+    W, _, info = eig_gpu(jx, A, block=64)
+    assert info["status"] == 0, info
+    S = info["sweeps"]
+    print(f"graded n={n} b=64: {S} sweeps", flush=True)
+    assert np.max(np.abs(W - np.sort(lam))) <= 1e-12 * np.max(np.abs(lam))
+    for cap in (S - 1, S - 2):
+        _, _, ic = eig_gpu(jx, A, block=64, max_sweeps=cap, check=False)
+        assert ic["status"] == 1 and ic["sweeps"] == cap, (cap, ic)
+
+
 def test_eig_values_only_and_unsorted(jx):
     A, _ = inputs.eig_uniform(150, 5)
     Wv, Qv, info = eig_gpu(jx, A, want_vectors=0)
