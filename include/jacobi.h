@@ -77,7 +77,9 @@ typedef struct {
                              eig: stop when Xi(A) <= tol * ||A||_F (1e-14);
                              svd: stop when every column pair has
                              |g_i^T g_j| <= tol * |g_i| |g_j| (sqrt(m) * eps) */
-    int max_sweeps;       /* default 60 */
+    int max_sweeps;       /* default 60; caps the sweeps up to the orthogonality
+                             refinement (the sweeps after it may run up to 12
+                             past the cap) */
     int block;            /* b; 0 = default (64 for n > 512, smaller below); eig
                              also 1 = scalar Jacobi (Alg. 1 with b = 1, round-
                              robin rounds of n/2 rotations in one workgroup;

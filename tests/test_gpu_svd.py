@@ -166,6 +166,26 @@ def test_svd_constructed_log_uniform_sigma(jx, m, n):
     assert ou <= 1e-12 / ref[-1]
 
 
+@pytest.mark.parametrize("precondition", [0, -1])
+def test_svd_sweep_cap_with_refinement(jx, precondition):
+    """opts.max_sweeps bounds the sweeps up to the refinement of V, which
+    runs inside the quadratic phase (the sweeps after a refinement may run
+    past the cap, as after a refinement at convergence): with a cap below
+    the sweep that starts it, the solve stops at the cap with status 1.  The
+    full solve refines after its third-last sweep (one rotating and one
+    checking sweep follow)."""
+    G, sigma = inputs.svd_case(2048, 256, 3)
+    S, _, _, info = svd_gpu(jx, G, precondition=precondition)
+    assert info["status"] == 0, info
+    ref = np.sort(sigma)[::-1]
+    assert np.max(np.abs(S - ref)) <= 1e-12 * ref[0]
+    n_sw = info["sweeps"]
+    print(f"svd 2048 x 256 precondition={precondition}: {n_sw} sweeps", flush=True)
+    for cap in (n_sw - 3, n_sw // 2):
+        _, _, _, ic = svd_gpu(jx, G, precondition=precondition, max_sweeps=cap, check=False)
+        assert ic["status"] == 1 and ic["sweeps"] == cap, (cap, ic)
+
+
 def test_svd_edge_cases(jx):
     rng = np.random.default_rng(5)
     # a zero column: sigma = 0 and a zero U column
