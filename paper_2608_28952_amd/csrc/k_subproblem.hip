@@ -283,33 +283,66 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
         k2[ii] = b;
     }
     const bool prod = lane < H;  // item 0 holds the pivot of pair `lane` for the next round
-    const int kn = (lane + 1) & 15;
+    const int kn = (lane + 1) & 15, lp = lane & 15;
+    // LDS addresses: entry (a, b) of each item and the producer's (p, p)
+    // stay; the others move with the round and are computed a round ahead,
+    // while that round's loads are in flight, so that each round's loads
+    // issue at its start
+    int a00[2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii) a00[ii] = cross_at(k1[ii], k2[ii]);
+    const int adp = cross_at(lp, lp);
+    auto round_ad = [&](int sh, int (&ad)[2][3], int &adq, int &adz) {
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+            const int a = k1[ii], b = k2[ii], qa = cross_q(a, sh), qb = cross_q(b, sh);
+            ad[ii][0] = cross_at(a, qb);
+            ad[ii][1] = cross_at(qa, b);
+            ad[ii][2] = cross_at(qa, qb);
+        }
+        const int qk = cross_q(kn, sh);
+        adq = cross_at(qk, qk);                // q of the next pair
+        adz = cross_at(lp, cross_q(lp, sh));   // this round's pivot of pair lp
+    };
+    int ad[2][3], adq, adz;
+    round_ad(0, ad, adq, adz);
     for (int sh = 0; sh < H; ++sh) {
         const double *cur = prm + (sh & 1) * 3 * H;
         double *nxt = prm + ((sh + 1) & 1) * 3 * H;
-        double nv[2][4];
         // producer: the two diagonal entries of pair `lane`'s next pivot
         // (p of this pair, q of the next pair), read before the round's stores
         double dp = 0.0, dq = 0.0, shp = 0.0, shq = 0.0;
         if (prod) {
-            dp = S[cross_at(lane, lane)];
-            dq = S[cross_at(cross_q(kn, sh), cross_q(kn, sh))];
+            dp = S[adp];
+            dq = S[adq];
             shp = cur[2 * H + lane];
             shq = cur[2 * H + kn];
         }
+        double c1[2], s1[2], c2[2], s2[2], b00[2], b01[2], b10[2], b11[2];
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
-            const int a = k1[ii], b = k2[ii], qa = cross_q(a, sh), qb = cross_q(b, sh);
-            const double c1 = cur[a], s1 = cur[H + a], c2 = cur[b], s2 = cur[H + b];
-            const double b00 = S[cross_at(a, b)], b01 = S[cross_at(a, qb)];
-            const double b10 = S[cross_at(qa, b)], b11 = S[cross_at(qa, qb)];
+            const int a = k1[ii], b = k2[ii];
+            c1[ii] = cur[a];
+            s1[ii] = cur[H + a];
+            c2[ii] = cur[b];
+            s2[ii] = cur[H + b];
+            b00[ii] = S[a00[ii]];
+            b01[ii] = S[ad[ii][0]];
+            b10[ii] = S[ad[ii][1]];
+            b11[ii] = S[ad[ii][2]];
+        }
+        int nad[2][3], nadq, nadz;
+        round_ad(sh + 1, nad, nadq, nadz);
+        double nv[2][4];
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
             // rows: J1^T, then columns: J2 (J = [[c, s], [-s, c]] on (p, q))
-            const double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;
-            const double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
-            nv[ii][0] = c2 * r00 - s2 * r01;
-            nv[ii][1] = s2 * r00 + c2 * r01;
-            nv[ii][2] = c2 * r10 - s2 * r11;
-            nv[ii][3] = s2 * r10 + c2 * r11;
+            const double r00 = c1[ii] * b00[ii] - s1[ii] * b10[ii], r01 = c1[ii] * b01[ii] - s1[ii] * b11[ii];
+            const double r10 = s1[ii] * b00[ii] + c1[ii] * b10[ii], r11 = s1[ii] * b01[ii] + c1[ii] * b11[ii];
+            nv[ii][0] = c2[ii] * r00 - s2[ii] * r01;
+            nv[ii][1] = s2[ii] * r00 + c2[ii] * r01;
+            nv[ii][2] = c2[ii] * r10 - s2[ii] * r11;
+            nv[ii][3] = s2[ii] * r10 + c2[ii] * r11;
         }
         // the previous round's parameters are in the ring (its stores are
         // complete once this round's loads are)
@@ -317,17 +350,16 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
             if (!ok[ii]) continue;
-            const int a = k1[ii], b = k2[ii], qa = cross_q(a, sh), qb = cross_q(b, sh);
-            S[cross_at(a, b)] = nv[ii][0];
-            S[cross_at(a, qb)] = nv[ii][1];
-            S[cross_at(qa, b)] = nv[ii][2];
-            S[cross_at(qa, qb)] = nv[ii][3];
+            S[a00[ii]] = nv[ii][0];
+            S[ad[ii][0]] = nv[ii][1];
+            S[ad[ii][1]] = nv[ii][2];
+            S[ad[ii][2]] = nv[ii][3];
         }
         if (prod) {
             const double app = dp - shp, aqq = dq + shq;
-            S[cross_at(lane, lane)] = app;
-            S[cross_at(cross_q(kn, sh), cross_q(kn, sh))] = aqq;
-            S[cross_at(lane, cross_q(lane, sh))] = 0.0;  // this round's pivot (no item holds it)
+            S[adp] = app;
+            S[adq] = aqq;
+            S[adz] = 0.0;  // this round's pivot (no item holds it)
             if (sh + 1 < H) {
                 const double apq = lane < 15 ? nv[0][1] : nv[0][2];
                 double c, s, t;
@@ -344,6 +376,12 @@ __device__ void cross_sweep(double *S, double *prm, int lane, const VRing &vr) {
         }
         wave_lds_sync();
         // (the next round publishes this round's ring slot)
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) ad[ii][m] = nad[ii][m];
+        adq = nadq;
+        adz = nadz;
     }
 }
 
